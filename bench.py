@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Benchmark of LBG codebook design on one MI355X.
+
+One step = one complete LBG run (Algorithm 1: centroid of the training set,
+then split / Lloyd iterations until N codevectors) on the 16-image workload:
+16 synthetic 512 x 512 pictures (seeds 0..15), 4 x 4 blocks -> M = 262,144
+training vectors of dimension L = 16, split from the global mean to N = 256,
+stop when the relative distortion change is <= 1e-3.  The training matrix is
+resident in HBM before the timed region starts.
+
+Prints one JSON line.  ``value`` is vector-codeword distances per second over
+the whole job (sum over every allocation of M * n, divided by the wall time
+of the timed steps).  ``roofline`` reports the allocation kernel (the
+dominant one) against the FP32 matrix-core peak, from its own HIP-event
+durations inside the timed steps; ``cpu_baseline`` times the FP64 CPU oracle
+on a bounded sample of the same workload on this host's cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload():
+    import synth
+    cfg = synth.CONFIG1
+    X = synth.image_training_set(cfg["seeds"], cfg["W"], cfg["H"], cfg["b"])
+    return cfg, X
+
+
+def cpu_baseline(X, N, images):
+    """The FP64 oracle, as it stands, on the first ``images`` pictures' rows
+    with all host cores; distances/s of the full LBG run."""
+    import oracle
+    rows_per_image = X.shape[0] // 16
+    S = X[: images * rows_per_image]
+    cores = len(os.sched_getaffinity(0))
+    oracle.load()
+    t0 = time.perf_counter()
+    r = oracle.train(S, N, nthreads=cores)
+    t = time.perf_counter() - t0
+    dist = int(S.shape[0]) * int(sum(int(n) * (int(i) + 1)
+                                     for n, i in zip(r["level_n"], r["level_iters"])))
+    return dict(value=dist / t, unit="distances/s", cores=cores, kind="oracle",
+                sample=f"full LBG to N={N} on the first {images} of 16 images "
+                       f"(M={S.shape[0]}, L={S.shape[1]}), FP64, {t:.2f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-images", type=int, default=16,
+                    help="images of the workload the CPU oracle baseline runs on")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this benchmark runs on exactly one GPU; --gpus {args.gpus} "
+              "is not supported (the library has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_0910_4711_amd as P
+
+    cfg, X = workload()
+    M, L = X.shape
+    N = cfg["N"]
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    ws = torch.empty(P.load().lbg_workspace_size(P.OP_TRAIN, M, L, N, P.FP32),
+                     dtype=torch.uint8, device=dev)
+    log(f"workload {cfg['name']}: M={M} L={L} N={N}; device {torch.cuda.get_device_name(dev)}")
+
+    for i in range(args.warmup):
+        P.train(Xd, N, workspace=ws, timing=True)
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize(dev)
+    tot = dict(dist=0, ms_assign=0.0, ms_update=0.0, ms_split=0.0, assigns=0, updates=0,
+               fallback=0)
+    last = None
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        C, idx, D, st = P.train(Xd, N, workspace=ws, timing=True)
+        tot["dist"] += st["total_distances"]
+        tot["ms_assign"] += st["ms_assign"]
+        tot["ms_update"] += st["ms_update"]
+        tot["ms_split"] += st["ms_split"]
+        tot["assigns"] += st["total_assigns"]
+        tot["updates"] += st["total_updates"]
+        tot["fallback"] += st["fallback_rows"]
+        last = (D, st)
+    torch.cuda.synchronize(dev)
+    elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {elapsed:.4f} s")
+
+    D, st = last
+    flops = 2.0 * L * tot["dist"]  # 2L flops per vector-codeword distance
+    assign_s = tot["ms_assign"] / 1e3
+    achieved_tf = flops / assign_s / 1e12
+    upd_bytes = tot["updates"] * M * (4 * L + 4)  # X rows + cell index per update
+    upd_gbs = upd_bytes / (tot["ms_update"] / 1e3) / 1e9 if tot["ms_update"] > 0 else None
+
+    out = {
+        "metric": "LBG iteration vector-codeword distances/s",
+        "value": tot["dist"] / elapsed,
+        "unit": "distances/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": cfg["name"],
+            "M": M, "L": L, "N": N, "thr": 1e-3, "eps_split": 0.01,
+            "images": len(cfg["seeds"]), "image_size": [cfg["H"], cfg["W"]], "block": cfg["b"],
+            "precision": "fp32 (exact allocation)",
+        },
+        "roofline": {
+            "bound": "mfma",
+            "achieved": achieved_tf,
+            "peak": PEAK_FP32_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tf / PEAK_FP32_MFMA_TFLOPS,
+            "traffic": None,
+            "kernel": "allocation (assign_fp32_kernel<16,2>)",
+            "launches": tot["assigns"],
+            "avg_launch_us": tot["ms_assign"] / tot["assigns"] * 1e3,
+            "flops_per_launch_avg": flops / tot["assigns"],
+        },
+        "update": {
+            "bound": "hbm",
+            "achieved_gbs": upd_gbs,
+            "peak_gbs": PEAK_HBM_GBS,
+            "frac": (upd_gbs / PEAK_HBM_GBS) if upd_gbs else None,
+            "avg_update_us": tot["ms_update"] / max(1, tot["updates"]) * 1e3,
+        },
+        "per_step": {
+            "assigns": tot["assigns"] // args.steps,
+            "updates": tot["updates"] // args.steps,
+            "ms_assign": tot["ms_assign"] / args.steps,
+            "ms_update": tot["ms_update"] / args.steps,
+            "ms_split": tot["ms_split"] / args.steps,
+            "fallback_rows": tot["fallback"] // args.steps,
+            "level_iters": st["level_iters"],
+            "D": D,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (FP64 oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(X, N, args.cpu_images)
+        log(f"cpu baseline done: {out['cpu_baseline']['sample']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * lbg.h -- C ABI of the MI355X (gfx950) LBG codebook-design library.
+ *
+ * LBG (Linde-Buzo-Gray) vector-quantizer design as parallelised in Annaji &
+ * Rao, "Parallelization of the LBG Vector Quantization Algorithm for Shared
+ * Memory Systems": a training set of M vectors of dimension L (the paper's
+ * "M x k" input, Sec. 3.1 Notations) is turned into a codebook of N
+ * codevectors ("N x k" output, Algorithm 1).  The Lloyd iteration of
+ * Algorithm 1 -- Cell Allocation (nearest codevector for every training
+ * vector), the distortion sum, the termination test and Codebook Updation
+ * (cell centroids) -- runs on the GPU; codebooks grow by Codebook Splitting.
+ *
+ * Conventions for every entry point:
+ *   - Arrays are row-major and contiguous.  Unless a parameter says "host",
+ *     pointers are DEVICE pointers on the current HIP device.  Float arrays
+ *     must be 4-byte aligned; X and C are read with 16-byte vector loads when
+ *     16-byte aligned and L % 4 == 0, and with scalar loads otherwise.
+ *   - The caller owns every buffer.  The library never frees caller memory
+ *     and allocates no caller-visible memory; scratch space is the caller's
+ *     workspace ``ws`` of at least lbg_workspace_size(...) bytes (device,
+ *     256-byte aligned).  ws may be NULL only when that size is 0.
+ *   - ``stream`` is a hipStream_t (NULL = the legacy default stream).  Calls
+ *     enqueue work on it and return without waiting, except lbg_train, which
+ *     waits on its stream to run the level / iteration control.
+ *   - Return codes: LBG_OK, LBG_EINVAL (bad size, NULL required pointer,
+ *     misalignment, N not a power of two in lbg_train, bad parameter),
+ *     LBG_ENOWS (workspace too small), LBG_EHIP (a HIP runtime error; the
+ *     message names it), LBG_WMAXITER (warning from lbg_train: some level hit
+ *     its iteration cap; results are valid).  On failure no kernel has been
+ *     enqueued and lbg_last_error() returns a message (thread-local).
+ *   - Cell indices are int32; codevector index ties go to the lowest index.
+ *   - Results are deterministic: the same inputs give bit-identical outputs
+ *     on every run (no floating-point atomics anywhere).
+ */
+#ifndef LBG_H
+#define LBG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBG_OK 0
+#define LBG_EINVAL (-1)
+#define LBG_ENOWS (-2)
+#define LBG_EHIP (-3)
+#define LBG_WMAXITER 1
+
+/* Distance arithmetic of the allocation. */
+#define LBG_FP32 0         /* FP32 matrix-core distances, exact result (below) */
+#define LBG_BF16_RESCORE 1 /* BF16 matrix-core distances, top-2 rescored */
+
+/* Codebook split forms. */
+#define LBG_SPLIT_MULT 0 /* c(1+eps), c(1-eps) */
+#define LBG_SPLIT_ADD 1  /* c+delta, c-delta (the paper's additive form) */
+
+/* Workspace queries. */
+#define LBG_OP_ASSIGN 1
+#define LBG_OP_UPDATE 2
+#define LBG_OP_DISTORTION 3
+#define LBG_OP_TRAIN 4
+#define LBG_OP_BACKWARD 5
+#define LBG_OP_CENTROID 6
+
+/* Largest supported sizes. */
+#define LBG_MAX_M ((((int64_t)1) << 31) - 1) /* rows: int32 cell table */
+#define LBG_MAX_L 256                   /* vector dimension */
+#define LBG_MAX_N 65536                 /* codevectors */
+
+/*
+ * Codebook Splitting (Algorithm 1, "Codebook Splitting"; Sec. 3.2): every
+ * codevector c_i of C (n x L) yields two children, written to C2 (2n x L):
+ *   C2[2i]   = c_i * (1 + eps)      C2[2i+1] = c_i * (1 - eps)
+ * each product formed in FP64 and rounded once to FP32.  C2 must not
+ * overlap C.  eps in (0, 1).
+ */
+int lbg_split(const float* C, int64_t n, int64_t L, double eps, float* C2,
+              void* stream);
+
+/* Additive form of the split (the paper's [c + delta], [c - delta]):
+ *   C2[2i] = c_i + delta, C2[2i+1] = c_i - delta (FP64, rounded to FP32). */
+int lbg_split_add(const float* C, int64_t n, int64_t L, double delta,
+                  float* C2, void* stream);
+
+/*
+ * Initial codebook (Algorithm 1, Initialization; Table 1): c0 = mean of the M
+ * rows of X, summed in FP64 in a fixed order, rounded to FP32.  c0: 1 x L.
+ */
+int lbg_centroid(const float* X, int64_t M, int64_t L, float* c0, void* ws,
+                 size_t ws_bytes, void* stream);
+
+/*
+ * Cell Allocation (Algorithm 1, "Cell Allocation"; Sec. 3.2): for every row
+ * x_m of X (M x L) the index of the nearest row of C (N x L) under the
+ * squared Euclidean distance, lowest index on ties:
+ *   idx[m] = min { k : d(x_m, c_k) = min_j d(x_m, c_j) }.
+ * mind[m] (nullable) receives d(x_m, c_idx[m]) rounded to FP32.
+ *
+ * precision == LBG_FP32: distances are screened on FP32 matrix cores in the
+ * expanded form |x|^2 - 2 x.c + |c|^2; the best candidate is rescored in
+ * FP64 in the direct form sum_l (x_l - c_l)^2 and accepted only when a
+ * rigorous error bound proves no other codevector can be as close;
+ * otherwise the row is searched again exhaustively in FP64.  The result
+ * equals the FP64 direct-form argmin exactly.
+ * precision == LBG_BF16_RESCORE: the screen runs in BF16 with FP32
+ * accumulation; the two best candidates are rescored in FP64 and the
+ * closer one (lowest index on ties) is taken.  Approximate: a row whose
+ * true nearest codevector is not among the BF16 top two can be misassigned.
+ */
+int lbg_assign(const float* X, int64_t M, int64_t L, const float* C, int64_t N,
+               int32_t* idx, float* mind, int precision, void* ws,
+               size_t ws_bytes, void* stream);
+
+/*
+ * Codebook Updation (Algorithm 1, "Codebook Updation"; Sec. 3.2): every
+ * codevector becomes the centroid of its cell,
+ *   C_new[k] = (1/|S_k|) sum_{m : idx[m] = k} x_m,
+ * summed in FP64 in a fixed order (cell by cell, rows in index order within
+ * fixed-size runs, runs combined in order) and rounded to FP32.  An empty
+ * cell keeps C_old[k].  counts[k] (nullable, int32) receives |S_k|.
+ * C_new may equal C_old (in place); otherwise they must not overlap.
+ * Entries of idx outside [0, N) are ignored (they join no cell).
+ */
+int lbg_update(const float* X, int64_t M, int64_t L, const int32_t* idx,
+               const float* C_old, int64_t N, float* C_new, int32_t* counts,
+               void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Average distortion (LBG restatement, Sec. 2.2; the master's
+ * IntegrateDistortions of Algorithm 1):
+ *   D = (1/M) sum_m d(x_m, c_idx[m])
+ * per-row distances in FP64 direct form, summed in FP64 in a fixed order.
+ * D is a single DEVICE double.  idx entries must lie in [0, N); rows with an
+ * index outside that range contribute 0.
+ */
+int lbg_distortion(const float* X, int64_t M, int64_t L, const float* C,
+                   int64_t N, const int32_t* idx, double* D, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/*
+ * Gradient of D(C, X) = (1/M) sum_m min_k d(x_m, c_k) at the allocation idx,
+ * scaled by g (the upstream gradient of a scalar loss):
+ *   gX[m] = g * 2/M * (x_m - c_idx[m])
+ *   gC[k] = g * 2/M * sum_{m : idx[m] = k} (c_k - x_m)
+ * gC sums the differences in FP64 in the fixed order of lbg_update.  Either
+ * output may be NULL.  At a tie the gradient is the one of the lowest-index
+ * minimiser (the allocation passed in).
+ */
+int lbg_distortion_backward(const float* X, int64_t M, int64_t L,
+                            const float* C, int64_t N, const int32_t* idx,
+                            double g, float* gX, float* gC, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* Parameters of lbg_train.  lbg_params_default() fills the defaults. */
+typedef struct lbg_params {
+  double thr;        /* relative distortion-change threshold (1e-3), >= 0 */
+  double eps_split;  /* multiplicative split factor (0.01), in (0, 1) */
+  double delta;      /* additive split offset (split_mode == LBG_SPLIT_ADD) */
+  int32_t split_mode;  /* LBG_SPLIT_MULT (default) or LBG_SPLIT_ADD */
+  int32_t max_iter;    /* cap on updates per level (1000) */
+  int32_t precision;   /* LBG_FP32 (default) or LBG_BF16_RESCORE */
+  int32_t fixed_iters; /* > 0: exactly this many updates per level */
+  const int32_t* forced_iters; /* HOST, nullable: updates for level i */
+  int32_t n_forced;            /* entries of forced_iters */
+  const float* C_init;         /* DEVICE, nullable: starting codebook */
+  int64_t N_init;              /* rows of C_init (power of two, <= N) */
+  int32_t timing;              /* nonzero: time kernels with HIP events */
+} lbg_params;
+
+void lbg_params_default(lbg_params* p);
+
+/* Statistics of one lbg_train run (HOST struct).  D_trace (HOST, nullable)
+ * receives the distortion of every allocation, up to D_cap entries. */
+typedef struct lbg_stats {
+  int32_t n_levels;
+  int32_t level_n[32];      /* codebook size of each level */
+  int32_t level_iters[32];  /* updates performed at each level */
+  int32_t total_updates;
+  int32_t total_assigns;
+  int64_t total_distances;  /* sum of M * n over all allocations */
+  int64_t fallback_rows;    /* rows searched again exhaustively (FP32 mode) */
+  double* D_trace;
+  int32_t D_cap;
+  int32_t n_D;
+  /* With p->timing set: summed durations (milliseconds, HIP events on the
+   * call's stream) of the allocation kernels, of the update kernels and of
+   * the split kernels; zero otherwise. */
+  double ms_assign;
+  double ms_update;
+  double ms_split;
+} lbg_stats;
+
+/*
+ * LBG with splitting (Algorithm 1): start from the centroid of X (or from
+ * C_init), then alternately split and iterate Cell Allocation / Updation at
+ * each level until the relative distortion change (D_prev - D) <= thr *
+ * D_prev, where D_prev is the distortion of the previous allocation at the
+ * same level (the first allocation after a split never stops), until the
+ * codebook has N codevectors (N a power of two, Terms of Sec. 2.2).
+ * On return C_out (DEVICE, N x L) holds the codebook that produced the last
+ * allocation, idx_out (DEVICE, M) that allocation and *D_out (HOST) its
+ * distortion.  st (HOST, nullable) receives statistics.  Synchronises
+ * ``stream``.
+ */
+int lbg_train(const float* X, int64_t M, int64_t L, int64_t N,
+              const lbg_params* p, float* C_out, int32_t* idx_out,
+              double* D_out, lbg_stats* st, void* ws, size_t ws_bytes,
+              void* stream);
+
+/* Bytes of workspace the operation ``op`` (LBG_OP_*) needs. */
+size_t lbg_workspace_size(int op, int64_t M, int64_t L, int64_t N,
+                          int precision);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* lbg_last_error(void);
+
+/* Library version string. */
+const char* lbg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBG_H */

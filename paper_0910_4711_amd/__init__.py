@@ -1,0 +1,334 @@
+"""MI355X (gfx950) LBG codebook design -- thin Python binding of liblbg.so.
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current stream.  The
+library must have been built (``python -m paper_0910_4711_amd.build``); there
+is no fallback of any kind.
+
+Functions follow Algorithm 1 of Annaji & Rao, "Parallelization of the LBG
+Vector Quantization Algorithm for Shared Memory Systems":
+``centroid`` (Initialization), ``split`` (Codebook Splitting), ``assign``
+(Cell Allocation), ``distortion`` (IntegrateDistortions), ``update``
+(Codebook Updation), ``train`` (the whole algorithm), plus the distortion's
+gradient and ``Distortion`` (a torch.autograd.Function).
+"""
+
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import threading
+
+import torch
+
+__all__ = [
+    "FP32", "BF16_RESCORE", "SPLIT_MULT", "SPLIT_ADD", "LBGError",
+    "library_path", "load", "centroid", "split", "assign", "update",
+    "distortion", "distortion_backward", "train", "Distortion",
+]
+
+FP32 = 0
+BF16_RESCORE = 1
+SPLIT_MULT = 0
+SPLIT_ADD = 1
+OK, EINVAL, ENOWS, EHIP, WMAXITER = 0, -1, -2, -3, 1
+OP_ASSIGN, OP_UPDATE, OP_DISTORTION, OP_TRAIN, OP_BACKWARD, OP_CENTROID = 1, 2, 3, 4, 5, 6
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liblbg.so")
+_lock = threading.Lock()
+_lib = None
+
+
+class LBGError(RuntimeError):
+    """A library call returned an error code."""
+
+
+class Params(ct.Structure):
+    _fields_ = [
+        ("thr", ct.c_double),
+        ("eps_split", ct.c_double),
+        ("delta", ct.c_double),
+        ("split_mode", ct.c_int32),
+        ("max_iter", ct.c_int32),
+        ("precision", ct.c_int32),
+        ("fixed_iters", ct.c_int32),
+        ("forced_iters", ct.POINTER(ct.c_int32)),
+        ("n_forced", ct.c_int32),
+        ("C_init", ct.c_void_p),
+        ("N_init", ct.c_int64),
+        ("timing", ct.c_int32),
+    ]
+
+
+class Stats(ct.Structure):
+    _fields_ = [
+        ("n_levels", ct.c_int32),
+        ("level_n", ct.c_int32 * 32),
+        ("level_iters", ct.c_int32 * 32),
+        ("total_updates", ct.c_int32),
+        ("total_assigns", ct.c_int32),
+        ("total_distances", ct.c_int64),
+        ("fallback_rows", ct.c_int64),
+        ("D_trace", ct.POINTER(ct.c_double)),
+        ("D_cap", ct.c_int32),
+        ("n_D", ct.c_int32),
+        ("ms_assign", ct.c_double),
+        ("ms_update", ct.c_double),
+        ("ms_split", ct.c_double),
+    ]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load liblbg.so; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH):
+            raise LBGError(f"{_LIB_PATH} is missing: build it with "
+                           "`python -m paper_0910_4711_amd.build`")
+        lib = ct.CDLL(_LIB_PATH)
+        i64, i32, vp, dbl, sz = ct.c_int64, ct.c_int, ct.c_void_p, ct.c_double, ct.c_size_t
+        sig = {
+            "lbg_split": [vp, i64, i64, dbl, vp, vp],
+            "lbg_split_add": [vp, i64, i64, dbl, vp, vp],
+            "lbg_centroid": [vp, i64, i64, vp, vp, sz, vp],
+            "lbg_assign": [vp, i64, i64, vp, i64, vp, vp, i32, vp, sz, vp],
+            "lbg_update": [vp, i64, i64, vp, vp, i64, vp, vp, vp, sz, vp],
+            "lbg_distortion": [vp, i64, i64, vp, i64, vp, vp, vp, sz, vp],
+            "lbg_distortion_backward": [vp, i64, i64, vp, i64, vp, dbl, vp, vp, vp, sz, vp],
+            "lbg_train": [vp, i64, i64, i64, ct.POINTER(Params), vp, vp,
+                          ct.POINTER(ct.c_double), ct.POINTER(Stats), vp, sz, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ct.c_int
+        lib.lbg_workspace_size.argtypes = [ct.c_int, i64, i64, i64, ct.c_int]
+        lib.lbg_workspace_size.restype = ct.c_size_t
+        lib.lbg_last_error.argtypes = []
+        lib.lbg_last_error.restype = ct.c_char_p
+        lib.lbg_version.argtypes = []
+        lib.lbg_version.restype = ct.c_char_p
+        lib.lbg_params_default.argtypes = [ct.POINTER(Params)]
+        lib.lbg_params_default.restype = None
+        _lib = lib
+        return lib
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        msg = load().lbg_last_error().decode(errors="replace")
+        raise LBGError(f"{what} failed ({rc}): {msg}")
+    return rc
+
+
+def _ptr(t):
+    return ct.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device):
+    return ct.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _f32_2d(name, t):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.dim() != 2:
+        raise TypeError(f"{name} must be a 2-D float32 tensor")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be on a GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _i32_1d(name, t, n):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or t.dim() != 1 or t.numel() != n:
+        raise TypeError(f"{name} must be a 1-D int32 tensor of {n} entries")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous GPU tensor")
+    return t
+
+
+def _ws(op, M, L, N, precision, device):
+    nb = load().lbg_workspace_size(op, M, L, N, precision)
+    if nb == 0:
+        return None, 0
+    return torch.empty(nb, dtype=torch.uint8, device=device), nb
+
+
+def _prec(p):
+    if p in (FP32, "fp32", "f32"):
+        return FP32
+    if p in (BF16_RESCORE, "bf16", "bf16_rescore"):
+        return BF16_RESCORE
+    raise ValueError(f"unknown precision {p!r}")
+
+
+def centroid(X):
+    """Initial codebook: mean of the rows of X (1 x L, FP32)."""
+    X = _f32_2d("X", X)
+    M, L = X.shape
+    c0 = torch.empty((1, L), dtype=torch.float32, device=X.device)
+    ws, nb = _ws(OP_CENTROID, M, L, 1, FP32, X.device)
+    _check(load().lbg_centroid(_ptr(X), M, L, _ptr(c0), _ptr(ws), nb, _stream(X.device)),
+           "lbg_centroid")
+    return c0
+
+
+def split(C, eps=0.01, mode=SPLIT_MULT, delta=0.0):
+    """Codebook Splitting: (2n x L) children, row 2i = '+', 2i+1 = '-'."""
+    C = _f32_2d("C", C)
+    n, L = C.shape
+    C2 = torch.empty((2 * n, L), dtype=torch.float32, device=C.device)
+    lib = load()
+    if mode == SPLIT_ADD:
+        rc = lib.lbg_split_add(_ptr(C), n, L, float(delta), _ptr(C2), _stream(C.device))
+    else:
+        rc = lib.lbg_split(_ptr(C), n, L, float(eps), _ptr(C2), _stream(C.device))
+    _check(rc, "lbg_split")
+    return C2
+
+
+def assign(X, C, precision=FP32, with_mind=True):
+    """Cell Allocation: (idx int32 [M], mind float32 [M] or None)."""
+    X, C = _f32_2d("X", X), _f32_2d("C", C)
+    M, L = X.shape
+    N = C.shape[0]
+    if C.shape[1] != L:
+        raise ValueError("X and C differ in dimension")
+    if C.device != X.device:
+        raise ValueError("X and C are on different devices")
+    idx = torch.empty(M, dtype=torch.int32, device=X.device)
+    mind = torch.empty(M, dtype=torch.float32, device=X.device) if with_mind else None
+    ws, nb = _ws(OP_ASSIGN, M, L, N, _prec(precision), X.device)
+    _check(load().lbg_assign(_ptr(X), M, L, _ptr(C), N, _ptr(idx), _ptr(mind),
+                             _prec(precision), _ptr(ws), nb, _stream(X.device)),
+           "lbg_assign")
+    return idx, mind
+
+
+def update(X, idx, C_old, out=None):
+    """Codebook Updation: (C_new [N x L] float32, counts [N] int32)."""
+    X, C_old = _f32_2d("X", X), _f32_2d("C_old", C_old)
+    M, L = X.shape
+    N = C_old.shape[0]
+    if C_old.shape[1] != L:
+        raise ValueError("X and C differ in dimension")
+    idx = _i32_1d("idx", idx, M)
+    C_new = out if out is not None else torch.empty_like(C_old)
+    _f32_2d("out", C_new)
+    counts = torch.empty(N, dtype=torch.int32, device=X.device)
+    ws, nb = _ws(OP_UPDATE, M, L, N, FP32, X.device)
+    _check(load().lbg_update(_ptr(X), M, L, _ptr(idx), _ptr(C_old), N, _ptr(C_new),
+                             _ptr(counts), _ptr(ws), nb, _stream(X.device)), "lbg_update")
+    return C_new, counts
+
+
+def distortion(X, C, idx):
+    """Average distortion of allocation idx: 0-d float64 GPU tensor."""
+    X, C = _f32_2d("X", X), _f32_2d("C", C)
+    M, L = X.shape
+    N = C.shape[0]
+    idx = _i32_1d("idx", idx, M)
+    D = torch.empty((), dtype=torch.float64, device=X.device)
+    ws, nb = _ws(OP_DISTORTION, M, L, N, FP32, X.device)
+    _check(load().lbg_distortion(_ptr(X), M, L, _ptr(C), N, _ptr(idx), _ptr(D), _ptr(ws),
+                                 nb, _stream(X.device)), "lbg_distortion")
+    return D
+
+
+def distortion_backward(X, C, idx, g=1.0, need_x=True, need_c=True):
+    """Gradient of D at allocation idx scaled by g: (gX or None, gC or None)."""
+    X, C = _f32_2d("X", X), _f32_2d("C", C)
+    M, L = X.shape
+    N = C.shape[0]
+    idx = _i32_1d("idx", idx, M)
+    gX = torch.empty_like(X) if need_x else None
+    gC = torch.empty_like(C) if need_c else None
+    ws, nb = _ws(OP_BACKWARD, M, L, N, FP32, X.device)
+    _check(load().lbg_distortion_backward(_ptr(X), M, L, _ptr(C), N, _ptr(idx), float(g),
+                                          _ptr(gX), _ptr(gC), _ptr(ws), nb,
+                                          _stream(X.device)), "lbg_distortion_backward")
+    return gX, gC
+
+
+def train(X, N, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta=0.0,
+          max_iter=1000, precision=FP32, fixed_iters=0, forced_iters=None,
+          C_init=None, D_cap=4096, workspace=None, timing=False):
+    """LBG with splitting (Algorithm 1).  Returns (C, idx, D, stats) with C
+    [N x L] float32, idx [M] int32, D a Python float and stats a dict."""
+    X = _f32_2d("X", X)
+    M, L = X.shape
+    lib = load()
+    p = Params()
+    lib.lbg_params_default(ct.byref(p))
+    p.thr, p.eps_split, p.delta = float(thr), float(eps_split), float(delta)
+    p.split_mode, p.max_iter = int(split_mode), int(max_iter)
+    p.precision, p.fixed_iters = _prec(precision), int(fixed_iters)
+    p.timing = 1 if timing else 0
+    keep = []
+    if forced_iters is not None:
+        f = (ct.c_int32 * len(forced_iters))(*[int(v) for v in forced_iters])
+        keep.append(f)
+        p.forced_iters = ct.cast(f, ct.POINTER(ct.c_int32))
+        p.n_forced = len(forced_iters)
+    if C_init is not None:
+        C_init = _f32_2d("C_init", C_init)
+        if C_init.shape[1] != L:
+            raise ValueError("C_init has the wrong dimension")
+        p.C_init, p.N_init = C_init.data_ptr(), C_init.shape[0]
+    C = torch.empty((N, L), dtype=torch.float32, device=X.device)
+    idx = torch.empty(M, dtype=torch.int32, device=X.device)
+    Dbuf = (ct.c_double * max(1, D_cap))()
+    st = Stats()
+    st.D_trace = ct.cast(Dbuf, ct.POINTER(ct.c_double))
+    st.D_cap = D_cap
+    nb = lib.lbg_workspace_size(OP_TRAIN, M, L, N, p.precision)
+    ws = workspace
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=X.device)
+    D = ct.c_double(0.0)
+    rc = lib.lbg_train(_ptr(X), M, L, int(N), ct.byref(p), _ptr(C), _ptr(idx), ct.byref(D),
+                       ct.byref(st), _ptr(ws), nb, _stream(X.device))
+    _check(rc, "lbg_train")
+    nl = st.n_levels
+    stats = dict(
+        status=rc,
+        level_n=list(st.level_n[:nl]),
+        level_iters=list(st.level_iters[:nl]),
+        total_updates=st.total_updates,
+        total_assigns=st.total_assigns,
+        total_distances=st.total_distances,
+        fallback_rows=st.fallback_rows,
+        D_trace=[Dbuf[i] for i in range(min(st.n_D, D_cap))],
+        ms_assign=st.ms_assign,
+        ms_update=st.ms_update,
+        ms_split=st.ms_split,
+    )
+    return C, idx, D.value, stats
+
+
+class Distortion(torch.autograd.Function):
+    """D(X, C) = mean_m min_k ||x_m - c_k||^2 with the library's forward
+    (exact FP32-mode allocation + FP64 distortion) and hand-written backward
+    kernels (dD/dX, dD/dC)."""
+
+    @staticmethod
+    def forward(ctx, X, C):
+        idx, _ = assign(X, C, FP32, with_mind=False)
+        D = distortion(X, C, idx)
+        ctx.save_for_backward(X, C, idx)
+        return D
+
+    @staticmethod
+    def backward(ctx, g):
+        X, C, idx = ctx.saved_tensors
+        gv = float(g.item())
+        gX, gC = distortion_backward(X, C, idx, gv, need_x=ctx.needs_input_grad[0],
+                                     need_c=ctx.needs_input_grad[1])
+        return gX, gC

@@ -1,0 +1,121 @@
+// Cell Allocation (Algorithm 1, "Cell Allocation"): the nearest codevector of
+// every training vector under the squared Euclidean distance, lowest index
+// on ties, plus per-row-tile FP64 sums of the winning distances (the
+// per-processor distortion that the master integrates).  This file holds the
+// FP32 screen (exact result), the dispatch, and an exhaustive FP64 kernel for
+// dimensions above the matrix-core kernels' limit.
+#include "assign_common.h"
+
+namespace lbg {
+namespace {
+
+using namespace assign_detail;
+
+// Exhaustive FP64 search, one thread per row.
+__global__ __launch_bounds__(256) void assign_exact_kernel(
+    const float* __restrict__ X, int64_t M, int L, const float* __restrict__ C,
+    int n, int32_t* __restrict__ idx, float* __restrict__ mind,
+    double* __restrict__ dpart) {
+  __shared__ double sD[256];
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double best = 0.0;
+  if (m < M) {
+    const float* x = X + m * (int64_t)L;
+    int bi = 0;
+    best = d64(x, C, L);
+    for (int k = 1; k < n; ++k) {
+      const double d = d64(x, C + (int64_t)k * L, L);
+      if (d < best) {
+        best = d;
+        bi = k;
+      }
+    }
+    idx[m] = bi;
+    if (mind) mind[m] = (float)best;
+  }
+  sD[threadIdx.x] = best;
+  __syncthreads();
+  tile_partial<256>(sD, dpart, blockIdx.x);
+}
+
+template <int LP>
+size_t prep_size(int64_t N, int precision) {
+  const int64_t n_pad = (N + 31) & ~(int64_t)31;
+  if (precision == LBG_BF16_RESCORE) {
+    constexpr int LB = LP < 16 ? 16 : LP;
+    return (size_t)n_pad * Bf16Screen<LB>::S * 2;
+  }
+  return (size_t)n_pad * Fp32Screen<LP>::S * 4;
+}
+
+}  // namespace
+
+int padded_dim(int64_t L) {
+  if (L <= 8) return 8;
+  if (L <= 16) return 16;
+  if (L <= 32) return 32;
+  if (L <= 64) return 64;
+  if (L <= 128) return 128;
+  return 0;  // exhaustive kernel
+}
+
+int tile_bits_for(int64_t n) {
+  const int tiles = (int)((n + 31) / 32);
+  int b = 0;
+  while ((1 << b) < tiles) ++b;
+  return b;
+}
+
+size_t prep_bytes(int64_t L, int64_t N, int precision) {
+  switch (padded_dim(L)) {
+    case 8: return prep_size<8>(N, precision);
+    case 16: return prep_size<16>(N, precision);
+    case 32: return prep_size<32>(N, precision);
+    case 64: return prep_size<64>(N, precision);
+    case 128: return prep_size<128>(N, precision);
+    default: return 0;
+  }
+}
+
+int assign_rows_per_wg(int64_t L, int precision) {
+  (void)precision;
+  const int LP = padded_dim(L);
+  if (LP == 0) return 256;
+  return LP == 128 ? 128 : 256;
+}
+
+int64_t assign_num_parts(int64_t M, int64_t L, int precision) {
+  const int r = assign_rows_per_wg(L, precision);
+  return (M + r - 1) / r;
+}
+
+void plan_assign(Carver& c, int64_t M, int64_t L, int64_t N, int precision, AssignWs* ws) {
+  ws->dpart = c.take<double>((size_t)assign_num_parts(M, L, precision));
+  ws->nfb = c.take<unsigned long long>(1);
+  ws->prep = c.take<unsigned char>(prep_bytes(L, N, precision));
+}
+
+int launch_assign(const float* X, int64_t M, int64_t L, const float* C, int64_t N,
+                  int32_t* idx, float* mind, int precision, double* dpart,
+                  unsigned long long* nfb, void* prep, hipStream_t s) {
+  const int LP = padded_dim(L);
+  const int Li = (int)L, n = (int)N;
+  if (LP == 0) {
+    const int64_t grid = (M + 255) / 256;
+    hipLaunchKernelGGL(assign_exact_kernel, dim3((unsigned)grid), dim3(256), 0, s, X, M, Li, C,
+                       n, idx, mind, dpart);
+    LBG_TRY_HIP(hipGetLastError());
+    return LBG_OK;
+  }
+  if (precision == LBG_BF16_RESCORE)
+    return launch_assign_bf16(X, M, Li, C, n, idx, mind, dpart, LP, prep, s);
+  switch (LP) {
+    case 8: return launch_screen<Fp32Screen<8>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s);
+    case 16: return launch_screen<Fp32Screen<16>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s);
+    case 32: return launch_screen<Fp32Screen<32>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s);
+    case 64: return launch_screen<Fp32Screen<64>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s);
+    default: return launch_screen<Fp32Screen<128>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s);
+  }
+}
+
+}  // namespace lbg

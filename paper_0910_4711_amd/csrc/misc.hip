@@ -1,0 +1,200 @@
+// Small kernels around the Lloyd iteration: Codebook Splitting, the initial
+// centroid, the distortion of a given allocation, the fixed-order reduction
+// of per-workgroup partial sums and the gradient with respect to X.
+#include <algorithm>
+
+#include "lbg_internal.h"
+
+namespace lbg {
+namespace {
+
+constexpr int kThreads = 256;
+
+// Codebook Splitting: child 2i = "+" and child 2i+1 = "-" of codevector i,
+// formed in FP64 and rounded once to FP32.
+__global__ __launch_bounds__(kThreads) void split_kernel(const float* __restrict__ C,
+                                                         int64_t n, int L, int mode,
+                                                         double eps, double delta,
+                                                         float* __restrict__ C2) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= n * L) return;
+  const int64_t i = e / L;
+  const int d = (int)(e % L);
+  const double c = (double)C[e];
+  double up, dn;
+  if (mode == LBG_SPLIT_ADD) {
+    up = c + delta;
+    dn = c - delta;
+  } else {
+    up = c * (1.0 + eps);
+    dn = c * (1.0 - eps);
+  }
+  C2[(2 * i) * L + d] = (float)up;
+  C2[(2 * i + 1) * L + d] = (float)dn;
+}
+
+// Per-block column sums of a row range, FP64, fixed order: thread (q, d)
+// adds rows q, q + R, q + 2R, ... of the block's range (R = 256 / L rows in
+// flight, L <= 256), then the R partial sums of each column are added in q
+// order.
+__global__ __launch_bounds__(kThreads) void colsum_kernel(const float* __restrict__ X,
+                                                          int64_t M, int L,
+                                                          int64_t rows_per_block,
+                                                          double* __restrict__ part) {
+  __shared__ double s[kThreads];
+  const int R = kThreads / L;
+  const int t = threadIdx.x;
+  const int q = t / L, d = t % L;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = min(M, r0 + rows_per_block);
+  double acc = 0.0;
+  if (q < R)
+    for (int64_t r = r0 + q; r < r1; r += R) acc += (double)X[r * L + d];
+  s[t] = acc;
+  __syncthreads();
+  if (t < L) {
+    double v = 0.0;
+    for (int qi = 0; qi < R; ++qi) v += s[qi * L + t];
+    part[(int64_t)blockIdx.x * L + t] = v;
+  }
+}
+
+// One block per column: thread t adds the block partials t, t+256, ... in
+// order, then a fixed tree adds the 256 thread sums.
+__global__ __launch_bounds__(kThreads) void colsum_final_kernel(
+    const double* __restrict__ part, int64_t nparts, int L, int64_t M,
+    float* __restrict__ c0) {
+  __shared__ double s[kThreads];
+  const int d = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t p = threadIdx.x; p < nparts; p += kThreads) acc += part[p * L + d];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) c0[d] = (float)(s[0] / (double)M);
+}
+
+// Fixed-order sum of FP64 partials: thread t adds parts t, t+256, ...; the
+// 256 results are added by a fixed tree.
+__global__ __launch_bounds__(kThreads) void reduce_parts_kernel(
+    const double* __restrict__ parts, int64_t nparts, double denom,
+    double* __restrict__ out) {
+  __shared__ double s[kThreads];
+  double acc = 0.0;
+  for (int64_t p = threadIdx.x; p < nparts; p += kThreads) acc += parts[p];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0] / denom;
+}
+
+// Distance of every row to its allocated codevector (FP64 direct form, in
+// dimension order), block partial sums in a fixed tree.
+__global__ __launch_bounds__(kThreads) void rowdist_kernel(
+    const float* __restrict__ X, int64_t M, int L, const float* __restrict__ C,
+    int n, const int32_t* __restrict__ idx, double* __restrict__ part) {
+  __shared__ double s[kThreads];
+  const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double d = 0.0;
+  if (m < M) {
+    const int k = idx[m];
+    if ((unsigned)k < (unsigned)n) {
+      const float* x = X + m * L;
+      const float* c = C + (int64_t)k * L;
+      for (int l = 0; l < L; ++l) {
+        const double t = (double)x[l] - (double)c[l];
+        d = d + t * t;
+      }
+    }
+  }
+  s[threadIdx.x] = d;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(kThreads) void grad_x_kernel(
+    const float* __restrict__ X, int64_t M, int L, const float* __restrict__ C,
+    int n, const int32_t* __restrict__ idx, double g2, float* __restrict__ gX) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= M * L) return;
+  const int64_t m = e / L;
+  const int d = (int)(e % L);
+  const int k = idx[m];
+  if ((unsigned)k >= (unsigned)n) {
+    gX[e] = 0.0f;
+    return;
+  }
+  gX[e] = (float)(g2 * ((double)X[e] - (double)C[(int64_t)k * L + d]));
+}
+
+}  // namespace
+
+int launch_split(const float* C, int64_t n, int64_t L, int mode, double eps,
+                 double delta, float* C2, hipStream_t s) {
+  const int64_t grid = (n * L + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(split_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, C, n,
+                     (int)L, mode, eps, delta, C2);
+  LBG_TRY_HIP(hipGetLastError());
+  return LBG_OK;
+}
+
+void plan_centroid(Carver& c, int64_t M, int64_t L, CentroidWs* ws) {
+  ws->nwg = std::min<int64_t>(1024, std::max<int64_t>(1, (M + 255) / 256));
+  ws->part = c.take<double>((size_t)(ws->nwg * L));
+}
+
+int launch_centroid(const float* X, int64_t M, int64_t L, float* c0,
+                    const CentroidWs& ws, hipStream_t s) {
+  const int64_t rpb = (M + ws.nwg - 1) / ws.nwg;
+  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)ws.nwg), dim3(kThreads), 0, s, X, M,
+                     (int)L, rpb, ws.part);
+  LBG_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((unsigned)L), dim3(kThreads), 0, s, ws.part,
+                     ws.nwg, (int)L, M, c0);
+  LBG_TRY_HIP(hipGetLastError());
+  return LBG_OK;
+}
+
+int launch_reduce_parts(const double* parts, int64_t nparts, double denom,
+                        double* out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(kThreads), 0, s, parts, nparts,
+                     denom, out);
+  LBG_TRY_HIP(hipGetLastError());
+  return LBG_OK;
+}
+
+void plan_distortion(Carver& c, int64_t M, DistWs* ws) {
+  ws->nparts = std::max<int64_t>(1, (M + kThreads - 1) / kThreads);
+  ws->part = c.take<double>((size_t)ws->nparts);
+}
+
+int launch_distortion(const float* X, int64_t M, int64_t L, const float* C,
+                      int64_t N, const int32_t* idx, double* D,
+                      const DistWs& ws, hipStream_t s) {
+  hipLaunchKernelGGL(rowdist_kernel, dim3((unsigned)ws.nparts), dim3(kThreads), 0, s, X,
+                     M, (int)L, C, (int)N, idx, ws.part);
+  LBG_TRY_HIP(hipGetLastError());
+  return launch_reduce_parts(ws.part, ws.nparts, (double)M, D, s);
+}
+
+int launch_grad_x(const float* X, int64_t M, int64_t L, const float* C,
+                  int64_t N, const int32_t* idx, double g2, float* gX,
+                  hipStream_t s) {
+  const int64_t grid = (M * L + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(grad_x_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, X, M,
+                     (int)L, C, (int)N, idx, g2, gX);
+  LBG_TRY_HIP(hipGetLastError());
+  return LBG_OK;
+}
+
+}  // namespace lbg

@@ -1,0 +1,286 @@
+"""GPU library vs the FP64 CPU oracle, element by element, on seeded inputs.
+
+Bars (from the arithmetic of each step):
+  * allocation (FP32 mode): identical indices -- the library proves its
+    screen or searches again in FP64, so it returns the FP64 direct-form
+    argmin; the winning distance equals the oracle's FP64 distance rounded
+    to FP32;
+  * split: identical to the oracle's split with FP32 storage (both form the
+    product in FP64 and round once);
+  * centroid / update: identical for integer-valued data (FP64 sums of
+    integers are exact in any order); otherwise within 1 FP32 ulp of the
+    oracle's FP64 mean rounded to FP32;
+  * distortion: relative 1e-12 (same per-row FP64 values, different order of
+    the final sum);
+  * whole LBG on integer-valued images: identical codebooks, allocations and
+    per-level iteration counts as the oracle with FP32 codebook storage;
+    against the FP64-storage oracle: codebooks within relative 1e-5 per
+    codevector and final distortion within relative 1e-6.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_0910_4711_amd as P
+    P.load()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return P
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _gmm(seed, M, L, K, scale=1.0):
+    return (synth.gmm(seed, M, L, K) * scale).astype(np.float32)
+
+
+def _img_rows(M, L=16, seed=0):
+    b = int(round(L ** 0.5))
+    X = synth.image_training_set((seed,), 512, 512, b)
+    return np.ascontiguousarray(X[:M])
+
+
+ASSIGN_CASES = [
+    # (M, L, n, kind)
+    (1, 16, 1, "img"),
+    (37, 16, 5, "img"),
+    (1000, 16, 64, "img"),
+    (4097, 16, 256, "img"),
+    (3000, 16, 257, "img"),
+    (2000, 64, 100, "img"),
+    (2500, 1, 7, "gmm"),
+    (1500, 3, 33, "gmm"),
+    (1300, 8, 128, "gmm"),
+    (999, 17, 40, "gmm"),
+    (777, 32, 300, "gmm"),
+    (800, 100, 20, "gmm"),
+    (600, 128, 129, "gmm"),
+    (300, 200, 9, "gmm"),
+]
+
+
+def _case(M, L, n, kind, seed):
+    if kind == "img":
+        X = _img_rows(M, L, seed)
+    else:
+        X = _gmm(seed, M, L, max(2, n // 2))
+    rng = np.random.default_rng(seed + 100)
+    C = X[rng.integers(0, M, size=n)].astype(np.float64)
+    C = (C + rng.normal(0, 3.0, size=C.shape)).astype(np.float32)
+    return X, C
+
+
+@pytest.mark.parametrize("M,L,n,kind", ASSIGN_CASES)
+def test_assign_fp32_exact(P, M, L, n, kind):
+    X, C = _case(M, L, n, kind, seed=M + L + n)
+    idx_o, d1, _ = oracle.assign(X, C.astype(np.float64))
+    idx, mind = P.assign(dev(X), dev(C), P.FP32)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(idx), idx_o)
+    np.testing.assert_array_equal(host(mind), d1.astype(np.float32))
+
+
+def test_assign_ties_lowest_index(P):
+    # duplicated codevectors and vectors exactly midway between two of them
+    rng = np.random.default_rng(5)
+    C = rng.integers(-20, 20, size=(40, 16)).astype(np.float32) * 2
+    C[7] = C[3]
+    C[30] = C[3]
+    C[12] = C[29]
+    X = np.concatenate([
+        C[[3, 7, 30, 12, 29]],
+        ((C[5] + C[6]) / 2)[None],
+        ((C[1] + C[9]) / 2)[None],
+        rng.integers(-40, 40, size=(500, 16)).astype(np.float32),
+    ]).astype(np.float32)
+    idx_o, _, _ = oracle.assign(X, C.astype(np.float64))
+    idx, _ = P.assign(dev(X), dev(C), P.FP32)
+    np.testing.assert_array_equal(host(idx), idx_o)
+    assert host(idx)[0] == 3 and host(idx)[1] == 3 and host(idx)[3] == 12
+
+
+def test_assign_all_equal_and_zero(P):
+    X = np.full((513, 16), 255.0, np.float32)
+    X[100:200] = 0.0
+    C = np.stack([np.full(16, 255.0), np.zeros(16), np.full(16, 255.0), np.zeros(16)]).astype(np.float32)
+    idx, mind = P.assign(dev(X), dev(C), P.FP32)
+    h = host(idx)
+    assert np.all(h[:100] == 0) and np.all(h[100:200] == 1) and np.all(h[200:] == 0)
+    assert np.all(host(mind) == 0)
+
+
+def test_split_matches_oracle(P):
+    rng = np.random.default_rng(3)
+    C = (rng.normal(size=(33, 17)) * 50).astype(np.float32)
+    C[4] = 0.0
+    for eps in (0.01, 0.25):
+        got = host(P.split(dev(C), eps=eps))
+        want = oracle.split(C.astype(np.float64), eps=eps, store_fp32=True)
+        np.testing.assert_array_equal(got, want.astype(np.float32))
+    got = host(P.split(dev(C), mode=P.SPLIT_ADD, delta=0.37))
+    want = oracle.split(C.astype(np.float64), mode=oracle.SPLIT_ADD, delta=0.37, store_fp32=True)
+    np.testing.assert_array_equal(got, want.astype(np.float32))
+
+
+@pytest.mark.parametrize("M,L", [(1, 1), (255, 16), (4096, 16), (10007, 64), (3000, 200)])
+def test_centroid(P, M, L):
+    Xi = _gmm(M, M, L, 3)
+    Xint = np.rint(Xi)
+    for X, exact in ((Xint, True), (Xi, False)):
+        got = host(P.centroid(dev(X)))[0]
+        want = oracle.centroid(X)[0]
+        if exact:
+            np.testing.assert_array_equal(got, want.astype(np.float32))
+        else:
+            np.testing.assert_allclose(got, want, rtol=2 ** -23, atol=1e-30)
+
+
+UPDATE_CASES = [(1, 1, 1), (100, 16, 7), (4096, 16, 64), (20000, 16, 256), (9000, 64, 1024),
+                (5000, 3, 9), (3000, 100, 50), (1000, 200, 5), (70000, 8, 4096)]
+
+
+@pytest.mark.parametrize("M,L,n", UPDATE_CASES)
+def test_update(P, M, L, n):
+    rng = np.random.default_rng(M + L + n)
+    Xf = _gmm(n, M, L, 4)
+    Xint = np.rint(Xf).astype(np.float32)
+    C_old = rng.normal(size=(n, L)).astype(np.float32)
+    # skewed cell sizes with some empty cells and one very large cell
+    idx = rng.integers(0, max(1, n - 2), size=M).astype(np.int32)
+    idx[: M // 3] = 0
+    for X, exact in ((Xint, True), (Xf, False)):
+        C_new, counts = P.update(dev(X), dev(idx), dev(C_old))
+        want, cnt = oracle.update(X, idx, C_old.astype(np.float64), store_fp32=True)
+        np.testing.assert_array_equal(host(counts), cnt)
+        got = host(C_new)
+        if exact:
+            np.testing.assert_array_equal(got, want.astype(np.float32))
+        else:
+            np.testing.assert_allclose(got, want, rtol=2 ** -23, atol=0)
+        empty = cnt == 0
+        np.testing.assert_array_equal(got[empty], C_old[empty])
+
+
+def test_update_in_place_and_invalid_indices(P):
+    rng = np.random.default_rng(11)
+    M, L, n = 5000, 16, 32
+    X = np.rint(_gmm(1, M, L, 4))
+    idx = rng.integers(0, n, size=M).astype(np.int32)
+    idx[::7] = -1
+    idx[::11] = n + 3
+    C = rng.normal(size=(n, L)).astype(np.float32)
+    Cd = dev(C)
+    _, counts = P.update(dev(X), dev(idx), Cd, out=Cd)
+    keep = (idx >= 0) & (idx < n)
+    want, cnt = oracle.update(X[keep], idx[keep], C.astype(np.float64), store_fp32=True)
+    np.testing.assert_array_equal(host(counts), cnt)
+    np.testing.assert_array_equal(host(Cd), want.astype(np.float32))
+
+
+@pytest.mark.parametrize("M,L,n", [(1, 4, 1), (1000, 16, 64), (33333, 64, 256), (500, 200, 7)])
+def test_distortion(P, M, L, n):
+    X = _gmm(M, M, L, 5)
+    rng = np.random.default_rng(2)
+    C = rng.normal(size=(n, L)).astype(np.float32) * 10
+    idx = rng.integers(0, n, size=M).astype(np.int32)
+    got = float(P.distortion(dev(X), dev(C), dev(idx)))
+    want = oracle.distortion(X, C.astype(np.float64), idx)
+    assert abs(got - want) <= 1e-12 * abs(want)
+
+
+def _config0():
+    return synth.image_training_set((0,), 256, 256, 4)
+
+
+def test_train_config0_matches_oracle(P):
+    X = _config0()
+    C, idx, D, st = P.train(dev(X), 64)
+    ref = oracle.train(X, 64, store_fp32=True)
+    np.testing.assert_array_equal(st["level_iters"], ref["level_iters"])
+    np.testing.assert_array_equal(host(idx), ref["idx"])
+    np.testing.assert_array_equal(host(C), ref["C"].astype(np.float32))
+    assert abs(D - ref["D"]) <= 1e-12 * ref["D"]
+    np.testing.assert_allclose(st["D_trace"], ref["D_trace"], rtol=1e-12)
+    # the FP64-storage oracle (spec tolerances)
+    r64 = oracle.train(X, 64, store_fp32=False)
+    Cg = host(C).astype(np.float64)
+    num = np.linalg.norm(Cg - r64["C"], axis=1)
+    den = np.linalg.norm(r64["C"], axis=1)
+    assert np.all(np.where(den > 0, num / np.maximum(den, 1e-300), num) <= 1e-5)
+    assert abs(D - r64["D"]) <= 1e-6 * r64["D"]
+
+
+def test_train_small_cases(P):
+    # N = 1, C_init, fixed iterations, additive split, point masses (D = 0)
+    X = _img_rows(2000, 16, 3)
+    C, idx, D, st = P.train(dev(X), 1)
+    ref = oracle.train(X, 1, store_fp32=True)
+    np.testing.assert_array_equal(host(C), ref["C"].astype(np.float32))
+    assert abs(D - ref["D"]) <= 1e-12 * ref["D"]
+
+    rng = np.random.default_rng(4)
+    C0 = X[rng.permutation(2000)[:16]]
+    C, idx, D, st = P.train(dev(X), 16, C_init=dev(C0), fixed_iters=5)
+    ref = oracle.train(X, 16, C_init=C0.astype(np.float64), fixed_iters=5, store_fp32=True)
+    np.testing.assert_array_equal(host(C), ref["C"].astype(np.float32))
+    np.testing.assert_array_equal(host(idx), ref["idx"])
+    assert st["level_iters"] == [5]
+
+    C, idx, D, st = P.train(dev(X), 8, split_mode=P.SPLIT_ADD, delta=0.5)
+    ref = oracle.train(X, 8, split_mode=oracle.SPLIT_ADD, delta=0.5, store_fp32=True)
+    np.testing.assert_array_equal(host(C), ref["C"].astype(np.float32))
+
+    Xp = np.array([[1.0]] * 5 + [[3.0]] * 3, np.float32)
+    C, idx, D, st = P.train(dev(Xp), 2, max_iter=50)
+    assert st["status"] == P.OK and D == 0.0 and list(host(C)[:, 0]) == [3.0, 1.0]
+
+
+def test_train_deterministic(P):
+    X = _img_rows(30000, 16, 1)
+    a = P.train(dev(X), 32)
+    b = P.train(dev(X), 32)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_bf16_rescore_close_to_oracle(P):
+    X = synth.image_training_set((0, 1), 256, 256, 8)  # M = 2048, L = 64
+    rng = np.random.default_rng(1000)
+    C = X[synth.distinct_rows(X, 128, 1000)]
+    idx, mind = P.assign(dev(X), dev(C), P.BF16_RESCORE)
+    idx_o, d1, d2 = oracle.assign(X, C.astype(np.float64))
+    h = host(idx)
+    miss = h != idx_o
+    # a miss is allowed only where the BF16 screen could not separate the
+    # two best codevectors: the true gap is below the BF16 rounding scale
+    gap = (d2 - d1)[miss]
+    assert miss.mean() < 0.01
+    xx = (X.astype(np.float64) ** 2).sum(1)[miss]
+    assert np.all(gap <= 2 ** -6 * (xx + d1[miss] + 1))
+    # the rescored distance is exact for the chosen codevector
+    Xd = X.astype(np.float64)
+    dd = ((Xd - C.astype(np.float64)[h]) ** 2).sum(1)
+    np.testing.assert_array_equal(host(mind), dd.astype(np.float32))
+
+
+def test_backward_matches_oracle(P):
+    X = _gmm(7, 6000, 16, 20)
+    rng = np.random.default_rng(7)
+    C = X[rng.permutation(6000)[:50]] + 0.5
+    idx_o, _, _ = oracle.assign(X, C.astype(np.float64))
+    gX, gC = P.distortion_backward(dev(X), dev(C), dev(idx_o.astype(np.int32)), g=1.5)
+    rX, rC = oracle.grad(X, C.astype(np.float64), idx_o, g=1.5)
+    np.testing.assert_allclose(host(gX), rX, rtol=2 ** -22, atol=1e-30)
+    np.testing.assert_allclose(host(gC), rC, rtol=2 ** -22, atol=1e-12)
