@@ -167,6 +167,9 @@ typedef struct lbg_params {
   const float* C_init;         /* DEVICE, nullable: starting codebook */
   int64_t N_init;              /* rows of C_init (power of two, <= N) */
   int32_t timing;              /* nonzero: time kernels with HIP events */
+  int32_t graph;               /* nonzero: replay batches of iterations as
+                                  hipGraphs (non-NULL streams only); the
+                                  default launches kernels directly */
 } lbg_params;
 
 void lbg_params_default(lbg_params* p);
@@ -185,8 +188,8 @@ typedef struct lbg_stats {
   int32_t D_cap;
   int32_t n_D;
   /* With p->timing set: summed durations (milliseconds, HIP events on the
-   * call's stream) of the allocation kernels, of the update kernels and of
-   * the split kernels; zero otherwise. */
+   * call's stream) of the allocation kernels and of the update kernels;
+   * ms_split is not measured (zero). */
   double ms_assign;
   double ms_update;
   double ms_split;

@@ -58,6 +58,7 @@ class Params(ct.Structure):
         ("C_init", ct.c_void_p),
         ("N_init", ct.c_int64),
         ("timing", ct.c_int32),
+        ("graph", ct.c_int32),
     ]
 
 
@@ -259,7 +260,7 @@ def distortion_backward(X, C, idx, g=1.0, need_x=True, need_c=True):
 
 def train(X, N, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta=0.0,
           max_iter=1000, precision=FP32, fixed_iters=0, forced_iters=None,
-          C_init=None, D_cap=4096, workspace=None, timing=False):
+          C_init=None, D_cap=4096, workspace=None, timing=False, graph=False):
     """LBG with splitting (Algorithm 1).  Returns (C, idx, D, stats) with C
     [N x L] float32, idx [M] int32, D a Python float and stats a dict."""
     X = _f32_2d("X", X)
@@ -271,6 +272,7 @@ def train(X, N, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta=0.0,
     p.split_mode, p.max_iter = int(split_mode), int(max_iter)
     p.precision, p.fixed_iters = _prec(precision), int(fixed_iters)
     p.timing = 1 if timing else 0
+    p.graph = 1 if graph else 0
     keep = []
     if forced_iters is not None:
         f = (ct.c_int32 * len(forced_iters))(*[int(v) for v in forced_iters])

@@ -84,23 +84,22 @@ int check_precision(int precision) {
   return LBG_OK;
 }
 
-struct TrainWs {
-  float* Cb[2];
-  double* D;
-  AssignWs as;
-  UpdateWs up;
-  CentroidWs ce;
-};
+}  // namespace
 
-void plan_train(Carver& c, int64_t M, int64_t L, int64_t N, int precision,
-                TrainWs* w) {
+void plan_train(Carver& c, int64_t M, int64_t L, int64_t N, int precision, TrainWs* w) {
   w->Cb[0] = c.take<float>((size_t)(N * L));
   w->Cb[1] = c.take<float>((size_t)(N * L));
   w->D = c.take<double>(1);
   plan_assign(c, M, L, N, precision, &w->as);
   plan_update(c, M, L, N, &w->up);
   plan_centroid(c, M, L, &w->ce);
+  w->st = c.take<DevState>(1);
+  w->pend = c.take<DevState>(1);
+  w->Dtrace = c.take<double>((size_t)kTraceCap);
+  w->Atrace = c.take<int32_t>((size_t)kTraceCap);
 }
+
+namespace {
 
 double* pinned_scalar() {
   static thread_local double* p = nullptr;
@@ -208,6 +207,7 @@ void lbg_params_default(lbg_params* p) {
   p->C_init = nullptr;
   p->N_init = 0;
   p->timing = 0;
+  p->graph = 0;
 }
 
 size_t lbg_workspace_size(int op, int64_t M, int64_t L, int64_t N, int precision) {
@@ -467,6 +467,8 @@ int lbg_train(const float* X, int64_t M, int64_t L, int64_t N, const lbg_params*
     st->D_trace = keep;
     st->D_cap = cap;
   }
+  if (train_device_ok(L, w))
+    return train_device(X, M, L, N, p, C_out, idx_out, D_out, st, w, s);
   LBG_TRY_HIP(hipMemsetAsync(w.as.nfb, 0, sizeof(unsigned long long), s));
 
   // Optional kernel timing: an event pair around every allocation, update

@@ -59,12 +59,7 @@ int padded_dim(int64_t L) {
   return 0;  // exhaustive kernel
 }
 
-int tile_bits_for(int64_t n) {
-  const int tiles = (int)((n + 31) / 32);
-  int b = 0;
-  while ((1 << b) < tiles) ++b;
-  return b;
-}
+int tile_bits_for(int64_t n) { return tile_bits_of(n); }
 
 size_t prep_bytes(int64_t L, int64_t N, int precision) {
   switch (padded_dim(L)) {
@@ -84,9 +79,13 @@ int assign_rows_per_wg(int64_t L, int precision) {
   return LP == 128 ? 128 : 256;
 }
 
+// Matrix-core kernels: one partial per wave of every block of the
+// persistent grid (kPersistBlocks at most); exhaustive kernel: one per block
+// of 256 rows.
 int64_t assign_num_parts(int64_t M, int64_t L, int precision) {
   const int r = assign_rows_per_wg(L, precision);
-  return (M + r - 1) / r;
+  const int64_t tiles = (M + r - 1) / r;
+  return padded_dim(L) == 0 ? tiles : 4 * std::min<int64_t>(tiles, kPersistBlocks);
 }
 
 void plan_assign(Carver& c, int64_t M, int64_t L, int64_t N, int precision, AssignWs* ws) {
@@ -97,10 +96,14 @@ void plan_assign(Carver& c, int64_t M, int64_t L, int64_t N, int precision, Assi
 
 int launch_assign(const float* X, int64_t M, int64_t L, const float* C, int64_t N,
                   int32_t* idx, float* mind, int precision, double* dpart,
-                  unsigned long long* nfb, void* prep, hipStream_t s) {
+                  unsigned long long* nfb, void* prep, hipStream_t s, Ctl ctl, CbPair cbp) {
   const int LP = padded_dim(L);
   const int Li = (int)L, n = (int)N;
   if (LP == 0) {
+    if (ctl.st) {
+      set_error("internal: device-side control needs L <= 128");
+      return LBG_EINVAL;
+    }
     const int64_t grid = (M + 255) / 256;
     hipLaunchKernelGGL(assign_exact_kernel, dim3((unsigned)grid), dim3(256), 0, s, X, M, Li, C,
                        n, idx, mind, dpart);
@@ -108,13 +111,13 @@ int launch_assign(const float* X, int64_t M, int64_t L, const float* C, int64_t 
     return LBG_OK;
   }
   if (precision == LBG_BF16_RESCORE)
-    return launch_assign_bf16(X, M, Li, C, n, idx, mind, dpart, LP, prep, s);
+    return launch_assign_bf16(X, M, Li, C, n, idx, mind, dpart, LP, prep, s, ctl, cbp);
   switch (LP) {
-    case 8: return launch_screen<Fp32Screen<8>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s);
-    case 16: return launch_screen<Fp32Screen<16>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s);
-    case 32: return launch_screen<Fp32Screen<32>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s);
-    case 64: return launch_screen<Fp32Screen<64>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s);
-    default: return launch_screen<Fp32Screen<128>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s);
+    case 8: return launch_screen<Fp32Screen<8>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s, ctl, cbp);
+    case 16: return launch_screen<Fp32Screen<16>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s, ctl, cbp);
+    case 32: return launch_screen<Fp32Screen<32>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s, ctl, cbp);
+    case 64: return launch_screen<Fp32Screen<64>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s, ctl, cbp);
+    default: return launch_screen<Fp32Screen<128>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s, ctl, cbp);
   }
 }
 

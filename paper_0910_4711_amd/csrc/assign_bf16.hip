@@ -15,13 +15,14 @@ namespace lbg {
 using namespace assign_detail;
 
 int launch_assign_bf16(const float* X, int64_t M, int L, const float* C, int n, int32_t* idx,
-                       float* mind, double* dpart, int LP, void* prep, hipStream_t s) {
+                       float* mind, double* dpart, int LP, void* prep, hipStream_t s,
+                       Ctl ctl, CbPair cbp) {
   switch (LP) {
     case 8:
-    case 16: return launch_screen<Bf16Screen<16>>(X, M, L, C, n, idx, mind, dpart, nullptr, prep, s);
-    case 32: return launch_screen<Bf16Screen<32>>(X, M, L, C, n, idx, mind, dpart, nullptr, prep, s);
-    case 64: return launch_screen<Bf16Screen<64>>(X, M, L, C, n, idx, mind, dpart, nullptr, prep, s);
-    default: return launch_screen<Bf16Screen<128>>(X, M, L, C, n, idx, mind, dpart, nullptr, prep, s);
+    case 16: return launch_screen<Bf16Screen<16>>(X, M, L, C, n, idx, mind, dpart, nullptr, prep, s, ctl, cbp);
+    case 32: return launch_screen<Bf16Screen<32>>(X, M, L, C, n, idx, mind, dpart, nullptr, prep, s, ctl, cbp);
+    case 64: return launch_screen<Bf16Screen<64>>(X, M, L, C, n, idx, mind, dpart, nullptr, prep, s, ctl, cbp);
+    default: return launch_screen<Bf16Screen<128>>(X, M, L, C, n, idx, mind, dpart, nullptr, prep, s, ctl, cbp);
   }
 }
 

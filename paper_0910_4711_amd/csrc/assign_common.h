@@ -43,6 +43,7 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr float kBig = 3.0e38f;    // squared norm of padding codevectors
+constexpr int kPersistBlocks = 512;  // grid of the allocation kernel (2 per CU)
 constexpr int kLdsBudget = 61440;  // bytes of LDS for the staged codebook
 
 // Row of the 32 x 32 matrix-core result held in accumulator register r of
@@ -96,9 +97,16 @@ __device__ __forceinline__ void split3(float v, __bf16& hi, __bf16& mid, __bf16&
 // Codebook in the screen's row layout; one block per row.
 template <class SC>
 __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ C, int n,
-                                                   int L, typename SC::elem* __restrict__ Cp) {
+                                                   int L, typename SC::elem* __restrict__ Cp,
+                                                   const DevState* __restrict__ st, CbPair cbp) {
   const int row = blockIdx.x;
   const int t = threadIdx.x;
+  if (st) {
+    if (st->done) return;
+    n = st->n;
+    C = cbp.c[st->cb];
+    if (row >= ((n + 31) & ~31)) return;
+  }
   typedef typename SC::elem E;
   __shared__ double part[256];
   double q = 0.0;
@@ -272,21 +280,96 @@ __device__ __forceinline__ double d64(const float* x, const float* c, int L) {
 //   searched exhaustively in FP64 by the whole wave (lowest index on ties).
 //   Otherwise (BF16 screen): both candidates are rescored in FP64 and the
 //   closer one is taken, the lower index on equal distances.
+// Exhaustive FP64 search of one row by the whole wave (FP32 screen only):
+// lane l scores codevectors l, l+64, ... in increasing order (strict <), then
+// the wave takes the smallest distance, lowest index on equal distances.
+// Codevectors come from the LDS-resident screen copy (-2c, exact) when the
+// whole codebook is staged, otherwise from C with vector loads.
 template <class SC, bool VEC>
-__device__ __forceinline__ void finish_rows(const Slots<SC::XT>& sl,
-                                            const float* __restrict__ X, int64_t M, int L,
-                                            const float* __restrict__ C, int n,
-                                            int32_t* __restrict__ idx,
-                                            float* __restrict__ mind, double* sD,
-                                            int64_t row0, int tile_bits,
-                                            unsigned long long* nfb) {
+__device__ __forceinline__ void search_row(const float* __restrict__ xrow, int L,
+                                           const float* __restrict__ C, int n,
+                                           const float* resident, int lane, double* best_d,
+                                           int* best_i) {
+  constexpr int LP = SC::LP;
+  float xr[LP];
+  load_row<LP, VEC>(xrow, L, xr);
+  double best = INFINITY;
+  int bi = 0x7fffffff;
+  if (resident) {
+    for (int k = lane; k < n; k += 64) {
+      const float* r = resident + (int64_t)k * SC::S;
+      float cr[LP];
+#pragma unroll
+      for (int s4 = 0; s4 < LP; s4 += 4) {
+        const float4 q = *reinterpret_cast<const float4*>(r + s4);
+        cr[s4] = -0.5f * q.x;
+        cr[s4 + 1] = -0.5f * q.y;
+        cr[s4 + 2] = -0.5f * q.z;
+        cr[s4 + 3] = -0.5f * q.w;
+      }
+      const double dk = d64_regs<LP>(xr, cr, L);
+      if (dk < best) {
+        best = dk;
+        bi = k;
+      }
+    }
+  } else {
+    int k = lane;
+    for (; k + 64 < n; k += 128) {
+      float c0[LP], c1[LP];
+      load_row<LP, VEC>(C + (int64_t)k * L, L, c0);
+      load_row<LP, VEC>(C + (int64_t)(k + 64) * L, L, c1);
+      const double d0 = d64_regs<LP>(xr, c0, L);
+      const double d1 = d64_regs<LP>(xr, c1, L);
+      if (d0 < best) {
+        best = d0;
+        bi = k;
+      }
+      if (d1 < best) {
+        best = d1;
+        bi = k + 64;
+      }
+    }
+    if (k < n) {
+      float c0[LP];
+      load_row<LP, VEC>(C + (int64_t)k * L, L, c0);
+      const double d0 = d64_regs<LP>(xr, c0, L);
+      if (d0 < best) {
+        best = d0;
+        bi = k;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ob = __shfl_xor(best, off);
+    const int oi = __shfl_xor(bi, off);
+    if (ob < best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  *best_d = best;
+  *best_i = bi;
+}
+
+// Returns the sum of the winning distances of the rows this lane handled.
+template <class SC, bool VEC, class BF>
+__device__ __forceinline__ double finish_rows(const Slots<SC::XT>& sl,
+                                              const float* __restrict__ X, int64_t M, int L,
+                                              const float* __restrict__ C, int n,
+                                              int32_t* __restrict__ idx,
+                                              float* __restrict__ mind, int64_t row0,
+                                              int tile_bits, unsigned long long* nfb,
+                                              const typename SC::elem* resident,
+                                              const BF (&xf)[SC::XT][SC::NS]) {
   constexpr int XT = SC::XT;
   constexpr int LP = SC::LP;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
   const int h = lane >> 5;
   const int j = lane & 31;
   const uint32_t lowmask = (1u << tile_bits) - 1u;
+  double dsum = 0.0;
 
   Top2 tp[XT];
 #pragma unroll
@@ -309,13 +392,48 @@ __device__ __forceinline__ void finish_rows(const Slots<SC::XT>& sl,
     bool flag = false;
     double d = 0.0;
     int win = 0;
+    float xr[LP];
+    if constexpr (SC::EXACT) {
+      // the row from the two half-waves' fragments: this lane's half, and the
+      // other half from lane (j, 1-h), which sends its half of the row this
+      // lane handles (xt = 2p + h)
+      const int sx = 2 * p + (1 - h);
+#pragma unroll
+      for (int s2 = 0; s2 < LP / 2; ++s2) {
+        float own = 0.0f, send = 0.0f;
+#pragma unroll
+        for (int q = 0; q < XT; ++q) {
+          if (q == xt) own = xf[q][s2];
+          if (q == sx) send = xf[q][s2];
+        }
+        const float recv = __shfl_xor(send, 32);
+        xr[s2] = h ? recv : own;
+        xr[LP / 2 + s2] = h ? own : recv;
+      }
+    }
     if (live) {
       win = t.i1;
       const bool bad = (unsigned)win >= (unsigned)n;  // non-finite input
       if (bad) win = 0;
-      float xr[LP], cr[LP];
-      load_row<LP, VEC>(X + m * (int64_t)L, L, xr);
-      load_row<LP, VEC>(C + (int64_t)win * L, L, cr);
+      float cr[LP];
+      if constexpr (SC::EXACT) {
+        if (resident) {
+          const float* r = reinterpret_cast<const float*>(resident) + (int64_t)win * SC::S;
+#pragma unroll
+          for (int s4 = 0; s4 < LP; s4 += 4) {
+            const float4 q4 = *reinterpret_cast<const float4*>(r + s4);
+            cr[s4] = -0.5f * q4.x;
+            cr[s4 + 1] = -0.5f * q4.y;
+            cr[s4 + 2] = -0.5f * q4.z;
+            cr[s4 + 3] = -0.5f * q4.w;
+          }
+        } else {
+          load_row<LP, VEC>(C + (int64_t)win * L, L, cr);
+        }
+      } else {
+        load_row<LP, VEC>(X + m * (int64_t)L, L, xr);
+        load_row<LP, VEC>(C + (int64_t)win * L, L, cr);
+      }
       d = d64_regs<LP>(xr, cr, L);
       if constexpr (SC::EXACT) {
         double xx = 0.0;
@@ -344,25 +462,9 @@ __device__ __forceinline__ void finish_rows(const Slots<SC::XT>& sl,
         const int src = __ffsll((long long)fl) - 1;
         fl &= fl - 1;
         const int64_t mf = __shfl(m, src);
-        const float* x = X + mf * (int64_t)L;
-        double best = INFINITY;
-        int bi = 0x7fffffff;
-        for (int k = lane; k < n; k += 64) {
-          const double dk = d64(x, C + (int64_t)k * L, L);
-          if (dk < best) {
-            best = dk;
-            bi = k;
-          }
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-          const double ob = __shfl_xor(best, off);
-          const int oi = __shfl_xor(bi, off);
-          if (ob < best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
-          }
-        }
+        double best;
+        int bi;
+        search_row<SC, VEC>(X + mf * (int64_t)L, L, C, n, resident, lane, &best, &bi);
         if (lane == src) {
           d = best;
           win = bi;
@@ -373,8 +475,9 @@ __device__ __forceinline__ void finish_rows(const Slots<SC::XT>& sl,
       idx[m] = win;
       if (mind) mind[m] = (float)d;
     }
-    if (have) sD[wave * 32 * XT + xt * 32 + j] = live ? d : 0.0;
+    if (live) dsum += d;
   }
+  return dsum;
 }
 
 // Fixed-order sum of the tile's ROWS distances into dpart[tile].
@@ -412,13 +515,94 @@ __device__ __forceinline__ void stage(const void* __restrict__ src, void* dst, i
   }
 }
 
+// Resident codebook staged straight from C: -2c (exact) zero-padded to LP
+// dimensions and n_pad rows, then each row's squared norm (FP64, rounded to
+// FP32) in its padding, as prep_kernel writes it.  Loads are issued four at a
+// time per thread before their stores.
+template <class SC, bool VEC>
+__device__ __forceinline__ void stage_from_C(const float* __restrict__ C, int n, int L,
+                                             int n_pad, typename SC::elem* sA) {
+  constexpr int LP = SC::LP;
+  constexpr int S = SC::S;
+  typedef typename SC::elem E;
+  if (VEC) {
+    constexpr int Q = LP / 4;
+    const int nv = n_pad * Q;
+    for (int base = 0; base < nv; base += 4 * kAssignThreads) {
+      float4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = base + u * kAssignThreads + threadIdx.x;
+        const int r = e / Q;
+        v[u] = (e < nv && r < n) ? *reinterpret_cast<const float4*>(C + (int64_t)e * 4)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = base + u * kAssignThreads + threadIdx.x;
+        if (e < nv) {
+          E* dst = sA + (e / Q) * S + (e % Q) * 4;
+          dst[0] = (E)(-2.0f * v[u].x);
+          dst[1] = (E)(-2.0f * v[u].y);
+          dst[2] = (E)(-2.0f * v[u].z);
+          dst[3] = (E)(-2.0f * v[u].w);
+        }
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < n_pad * LP; e += kAssignThreads) {
+      const int r = e / LP, d = e % LP;
+      const float v = (r < n && d < L) ? C[(int64_t)r * L + d] : 0.0f;
+      sA[r * S + d] = (E)(-2.0f * v);
+    }
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < n_pad; r += kAssignThreads) {
+    double q = 0.0;
+#pragma unroll 8
+    for (int d = 0; d < LP; ++d) {
+      const double v = (double)(float)sA[r * S + d];
+      q += v * v;
+    }
+    const float nrm = (r < n) ? (float)(0.25 * q) : kBig;
+    E* pad = sA + r * S + LP;
+    if constexpr (SC::EXACT) {
+      pad[0] = nrm;
+      pad[1] = 1.0f;
+      pad[2] = 0.0f;
+      pad[3] = 0.0f;
+    } else {
+      __bf16 hi, mid, lo;
+      split3(nrm, hi, mid, lo);
+      const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
+      pad[0] = hi;
+      pad[1] = mid;
+      pad[2] = lo;
+      pad[3] = one;
+      pad[4] = one;
+      pad[5] = one;
+      pad[6] = zero;
+      pad[7] = zero;
+    }
+  }
+  __syncthreads();
+}
+
 // -------------------------------------------------------------- kernel --
 template <class SC, bool VEC>
 __global__ __launch_bounds__(kAssignThreads, 2) void assign_kernel(
     const float* __restrict__ X, int64_t M, int L, const float* __restrict__ C, int n,
     const typename SC::elem* __restrict__ Cp, int n_pad, int CR, int32_t* __restrict__ idx,
     float* __restrict__ mind, double* __restrict__ dpart, unsigned long long* __restrict__ nfb,
-    int tile_bits) {
+    int tile_bits, Ctl ctl, CbPair cbp) {
+  const DevState* st = ctl.st;
+  if (st) {
+    if (st->done) return;
+    n = st->n;
+    C = cbp.c[st->cb];
+    n_pad = (n + 31) & ~31;
+    tile_bits = tile_bits_of(n);
+  }
   constexpr int XT = SC::XT;
   constexpr int LP = SC::LP;
   constexpr int S = SC::S;
@@ -427,7 +611,6 @@ __global__ __launch_bounds__(kAssignThreads, 2) void assign_kernel(
   typedef typename SC::elem E;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   E* sA = reinterpret_cast<E*>(smem);
-  __shared__ double sD[ROWS];
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -440,11 +623,9 @@ __global__ __launch_bounds__(kAssignThreads, 2) void assign_kernel(
   asm volatile("v_mov_b32 %0, %1" : "=v"(vmask) : "v"(vmask));
   const float ninf = -INFINITY;
 
-  if (resident) {
-    stage(Cp, sA, n_pad * S * SC::ESZ);
-    __syncthreads();
-  }
+  if (resident) stage_from_C<SC, VEC>(C, n, L, n_pad, sA);
 
+  double wsum = 0.0;
   for (int64_t rt = blockIdx.x; rt < ntiles_rows; rt += gridDim.x) {
     const int64_t row0 = rt * ROWS + (int64_t)wave * 32 * XT;
 
@@ -556,40 +737,52 @@ __global__ __launch_bounds__(kAssignThreads, 2) void assign_kernel(
       }
     }
 
-    finish_rows<SC, VEC>(sl, X, M, L, C, n, idx, mind, sD, row0, tile_bits, nfb);
-    __syncthreads();
-    tile_partial<ROWS>(sD, dpart, rt);
-    __syncthreads();
+    wsum += finish_rows<SC, VEC, BF>(sl, X, M, L, C, n, idx, mind, row0, tile_bits, nfb,
+                                     resident ? sA : nullptr, xf);
   }
+  // per-wave partial of the distortion over the block's row tiles (in order),
+  // lanes added by a fixed butterfly
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) wsum += __shfl_xor(wsum, off);
+  if (dpart && lane == 0) dpart[blockIdx.x * 4 + wave] = wsum;
 }
 
 // Host side: prepare the codebook and launch.
+// With a device state, n is the largest codebook size (LDS and grids are
+// sized for it); the kernels take the current size from the state.
 template <class SC>
 int launch_screen(const float* X, int64_t M, int L, const float* C, int n, int32_t* idx,
                   float* mind, double* dpart, unsigned long long* nfb, void* prep,
-                  hipStream_t s) {
+                  hipStream_t s, Ctl ctl, CbPair cbp) {
+  const DevState* st = ctl.st;
   typedef typename SC::elem E;
   const int n_pad = (n + 31) & ~31;
   E* Cp = reinterpret_cast<E*>(prep);
-  hipLaunchKernelGGL((prep_kernel<SC>), dim3((unsigned)n_pad), dim3(256), 0, s, C, n, L, Cp);
-  LBG_TRY_HIP(hipGetLastError());
   const int CR = chunk_rows<SC>(n_pad);
+  if (CR < n_pad) {  // chunked: stage from the prepared copy
+    hipLaunchKernelGGL((prep_kernel<SC>), dim3((unsigned)n_pad), dim3(256), 0, s, C, n, L, Cp,
+                       st, cbp);
+    LBG_TRY_HIP(hipGetLastError());
+  }
   constexpr int ROWS = rows_per_tile<SC>();
   const int64_t tiles = (M + ROWS - 1) / ROWS;
-  // A resident codebook is staged once per workgroup: persistent grid of
-  // two workgroups per CU.  A chunked one is staged per row tile anyway.
-  int64_t grid = tiles;
-  if (CR >= n_pad) grid = std::min<int64_t>(tiles, 2 * 256);
+  // Persistent grid of two workgroups per CU: a resident codebook is staged
+  // once per workgroup, a chunked one per row tile.
+  const int64_t grid = std::min<int64_t>(tiles, kPersistBlocks);
   const size_t lds = (size_t)CR * SC::S * SC::ESZ;
   const int tb = tile_bits_for(n);
-  const bool vec = (L == SC::LP) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
-                   ((reinterpret_cast<uintptr_t>(C) & 15) == 0);
+  bool vec = (L == SC::LP) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  if (st)
+    vec = vec && ((reinterpret_cast<uintptr_t>(cbp.c[0]) & 15) == 0) &&
+          ((reinterpret_cast<uintptr_t>(cbp.c[1]) & 15) == 0);
+  else
+    vec = vec && ((reinterpret_cast<uintptr_t>(C) & 15) == 0);
   if (vec)
     hipLaunchKernelGGL((assign_kernel<SC, true>), dim3((unsigned)grid), dim3(kAssignThreads), lds,
-                       s, X, M, L, C, n, Cp, n_pad, CR, idx, mind, dpart, nfb, tb);
+                       s, X, M, L, C, n, Cp, n_pad, CR, idx, mind, dpart, nfb, tb, ctl, cbp);
   else
     hipLaunchKernelGGL((assign_kernel<SC, false>), dim3((unsigned)grid), dim3(kAssignThreads),
-                       lds, s, X, M, L, C, n, Cp, n_pad, CR, idx, mind, dpart, nfb, tb);
+                       lds, s, X, M, L, C, n, Cp, n_pad, CR, idx, mind, dpart, nfb, tb, ctl, cbp);
   LBG_TRY_HIP(hipGetLastError());
   return LBG_OK;
 }
@@ -599,6 +792,7 @@ int launch_screen(const float* X, int64_t M, int L, const float* C, int n, int32
 // Workspace bytes for the prepared codebook of either screen.
 size_t prep_bytes(int64_t L, int64_t N, int precision);
 int launch_assign_bf16(const float* X, int64_t M, int L, const float* C, int n, int32_t* idx,
-                       float* mind, double* dpart, int LP, void* prep, hipStream_t s);
+                       float* mind, double* dpart, int LP, void* prep, hipStream_t s,
+                       Ctl ctl, CbPair cbp);
 
 }  // namespace lbg

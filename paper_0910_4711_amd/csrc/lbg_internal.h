@@ -27,6 +27,50 @@ int hip_fail(hipError_t e, const char* what);
     if (r__ < 0) return r__;   \
   } while (0)
 
+// ---------------------------------------------------- device-side control --
+// State of a training run kept in device memory, so that the iteration and
+// level control of Algorithm 1 runs on the GPU without host round trips.
+// The "decide" kernel (one block, after each allocation) applies the stop
+// test and sets the action of the iteration; the update and split kernels
+// read it and do nothing unless it names them; every kernel of an iteration
+// does nothing once the run is done.
+enum { kActNone = 0, kActUpdate = 1, kActSplit = 2 };
+struct DevState {
+  int32_t n, cb;                     // codebook of the next allocation
+  int32_t src, dst, n_src, action;   // this iteration's update / split
+  int32_t done, status;              // status: LBG_OK or LBG_WMAXITER
+  int32_t level, it, first;
+  int32_t n_assign, n_update;
+  int32_t N, max_iter, fixed_iters, n_forced, split_mode, D_cap;
+  int32_t forced[32];
+  int32_t level_n[32], level_iters[32];
+  int64_t M, distances;
+  double D, D_prev, thr, eps, delta;
+};
+struct CbPair {
+  float* c[2];  // the two codebook buffers the state's indices refer to
+};
+// Launch-time bundle for kernels under device-side control (null st: not).
+// The update's accumulation kernel derives the decision of the iteration
+// from the allocation's per-wave partials (every block the same way) and its
+// block 0 writes the next state into ``pend``; the update's last kernel
+// acts on ``pend`` and its block 0 commits it to ``st``.
+struct Ctl {
+  DevState* st;
+  DevState* pend;
+  const double* dpart;
+  int64_t nparts;
+  double* Dtrace;   // distortion of every allocation
+  int32_t* Atrace;  // action decided after every allocation
+};
+
+__host__ __device__ inline int tile_bits_of(int64_t n) {
+  const int tiles = (int)((n + 31) / 32);
+  int b = 0;
+  while ((1 << b) < tiles) ++b;
+  return b;
+}
+
 // ------------------------------------------------------------- workspace --
 // Carves a caller workspace into 256-byte aligned pieces.  With base ==
 // nullptr it only counts, so the same plan yields the size query and the
@@ -51,7 +95,7 @@ constexpr int kAssignThreads = 256;
 int assign_rows_per_wg(int64_t L, int precision);
 
 struct AssignWs {
-  double* dpart;           // per-row-tile distortion partial sums
+  double* dpart;           // per-wave distortion partial sums
   unsigned long long* nfb; // rows that fell back to the exhaustive search
   unsigned char* prep;     // codebook in the screen's LDS row layout
 };
@@ -60,9 +104,14 @@ void plan_assign(Carver& c, int64_t M, int64_t L, int64_t N, int precision,
 
 // Enqueue the allocation.  dpart (nullable) receives per-workgroup FP64
 // partial sums of the winning distances; nfb (nullable) counts fallback rows.
+// With ``st`` set, the codebook and its size come from the device state
+// (buffer cbp.c[st->cb], st->n rows, N the largest size) and the launch does
+// nothing once the run is done.
 int launch_assign(const float* X, int64_t M, int64_t L, const float* C,
                   int64_t N, int32_t* idx, float* mind, int precision,
-                  double* dpart, unsigned long long* nfb, void* prep, hipStream_t s);
+                  double* dpart, unsigned long long* nfb, void* prep, hipStream_t s,
+                  Ctl ctl = Ctl{nullptr, nullptr, nullptr, 0, nullptr, nullptr},
+                  CbPair cbp = CbPair{{nullptr, nullptr}});
 int64_t assign_num_parts(int64_t M, int64_t L, int precision);
 
 // Sum ``nparts`` FP64 partials in a fixed order and divide by ``denom``.
@@ -84,7 +133,8 @@ void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w);
 int launch_afp_shift(const float* X, int64_t M, int64_t L, const AfpWs& w, hipStream_t s);
 int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const float* C_old,
                int64_t N, float* C_out, int32_t* counts, int mode, double g2, const AfpWs& w,
-               hipStream_t s);
+               hipStream_t s, Ctl ctl = Ctl{nullptr, nullptr, nullptr, 0, nullptr, nullptr},
+               CbPair cbp = CbPair{{nullptr, nullptr}});
 
 // Sort-based fixed-order segmented sums (codebooks too large for the above).
 struct UpdateWs {
@@ -116,7 +166,11 @@ int launch_centroid(const float* X, int64_t M, int64_t L, float* c0,
                     const CentroidWs& ws, hipStream_t s);
 
 int launch_split(const float* C, int64_t n, int64_t L, int mode, double eps,
-                 double delta, float* C2, hipStream_t s);
+                 double delta, float* C2, hipStream_t s, const DevState* st = nullptr,
+                 CbPair cbp = CbPair{{nullptr, nullptr}});
+// One block: D = sum(dpart) / M (fixed order), trace, stop test, action.
+int launch_decide(const double* dpart, int64_t nparts, DevState* st, double* Dtrace,
+                  int32_t* Atrace, hipStream_t s);
 
 struct DistWs {
   double* part;
@@ -130,5 +184,29 @@ int launch_distortion(const float* X, int64_t M, int64_t L, const float* C,
 int launch_grad_x(const float* X, int64_t M, int64_t L, const float* C,
                   int64_t N, const int32_t* idx, double g2, float* gX,
                   hipStream_t s);
+
+// ------------------------------------------------------------- training --
+constexpr int kTraceCap = 32768;  // allocations recorded on the device
+
+struct TrainWs {
+  float* Cb[2];
+  double* D;
+  AssignWs as;
+  UpdateWs up;
+  CentroidWs ce;
+  DevState* st;
+  DevState* pend;
+  double* Dtrace;
+  int32_t* Atrace;
+};
+void plan_train(Carver& c, int64_t M, int64_t L, int64_t N, int precision, TrainWs* w);
+
+// Whether the device-controlled loop can run this problem.
+bool train_device_ok(int64_t L, const TrainWs& w);
+// LBG with splitting, controlled on the device (see DevState).  Returns
+// LBG_OK / LBG_WMAXITER or an error.
+int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_params* p,
+                 float* C_out, int32_t* idx_out, double* D_out, lbg_stats* st,
+                 const TrainWs& w, hipStream_t s);
 
 }  // namespace lbg

@@ -3,6 +3,7 @@
 // of per-workgroup partial sums and the gradient with respect to X.
 #include <algorithm>
 
+#include "control.h"
 #include "lbg_internal.h"
 
 namespace lbg {
@@ -15,7 +16,15 @@ constexpr int kThreads = 256;
 __global__ __launch_bounds__(kThreads) void split_kernel(const float* __restrict__ C,
                                                          int64_t n, int L, int mode,
                                                          double eps, double delta,
-                                                         float* __restrict__ C2) {
+                                                         float* __restrict__ C2,
+                                                         const DevState* __restrict__ st,
+                                                         CbPair cbp) {
+  if (st) {
+    if (st->done || st->action != kActSplit) return;
+    n = st->n_src;
+    C = cbp.c[st->src];
+    C2 = cbp.c[st->dst];
+  }
   const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (e >= n * L) return;
   const int64_t i = e / L;
@@ -140,10 +149,27 @@ __global__ __launch_bounds__(kThreads) void grad_x_kernel(
 }  // namespace
 
 int launch_split(const float* C, int64_t n, int64_t L, int mode, double eps,
-                 double delta, float* C2, hipStream_t s) {
+                 double delta, float* C2, hipStream_t s, const DevState* st, CbPair cbp) {
   const int64_t grid = (n * L + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(split_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, C, n,
-                     (int)L, mode, eps, delta, C2);
+                     (int)L, mode, eps, delta, C2, st, cbp);
+  LBG_TRY_HIP(hipGetLastError());
+  return LBG_OK;
+}
+
+__global__ __launch_bounds__(kThreads) void decide_kernel(const double* __restrict__ parts,
+                                                          int64_t nparts, DevState* st,
+                                                          double* __restrict__ Dtrace,
+                                                          int32_t* __restrict__ Atrace) {
+  __shared__ double red[kThreads];
+  if (st->done) return;
+  decide_block(parts, nparts, st, Dtrace, Atrace, red);
+}
+
+int launch_decide(const double* dpart, int64_t nparts, DevState* st, double* Dtrace,
+                  int32_t* Atrace, hipStream_t s) {
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kThreads), 0, s, dpart, nparts, st, Dtrace,
+                     Atrace);
   LBG_TRY_HIP(hipGetLastError());
   return LBG_OK;
 }

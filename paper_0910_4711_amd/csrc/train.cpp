@@ -1,0 +1,360 @@
+// LBG with splitting (Algorithm 1) with the iteration / level control on the
+// device.  The host enqueues batches of kBatchIters iterations -- allocation,
+// decide, update, split -- and reads the device state after each batch; the
+// decide kernel makes every later kernel of a finished run a no-op.  On a
+// non-default stream a batch is a hipGraph, captured once per set of
+// buffers and sizes and kept in a small cache.
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "lbg_internal.h"
+
+namespace lbg {
+namespace {
+
+constexpr int kBatchIters = 8;
+// Timing events only order the stream on the device: no system-scope fence.
+constexpr unsigned kEventFlags = hipEventDisableSystemFence;
+
+struct GraphKey {
+  const void* X;
+  const void* ws;
+  const void* idx;
+  int64_t M, L, N;
+  int precision, split_mode, timed;
+  double eps, delta;
+  hipStream_t stream;
+  bool operator==(const GraphKey& o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
+};
+
+struct GraphEntry {
+  bool used = false;
+  GraphKey key;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  bool timed = false;
+  hipEvent_t ev[kBatchIters][3][2];
+  uint64_t stamp = 0;
+};
+
+constexpr int kCacheSize = 8;
+std::mutex g_cache_mu;
+GraphEntry g_cache[kCacheSize];
+uint64_t g_stamp = 0;
+
+void release(GraphEntry& e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.graph) (void)hipGraphDestroy(e.graph);
+  if (e.timed)
+    for (int i = 0; i < kBatchIters; ++i)
+      for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 2; ++j) (void)hipEventDestroy(e.ev[i][k][j]);
+  e = GraphEntry();
+}
+
+struct Batch {
+  const float* X;
+  int64_t M, L, N;
+  int precision, split_mode;
+  double eps, delta;
+  int32_t* idx;
+  const TrainWs* w;
+  int64_t nparts;
+};
+
+// One iteration is two pieces: the allocation, then the update, whose
+// accumulation kernel also takes the decision of the iteration and whose
+// last kernel performs a split instead when that is the decision.
+constexpr int kPieces = 2;
+
+int enqueue_piece(const Batch& b, int piece, hipStream_t s) {
+  const TrainWs& w = *b.w;
+  CbPair cbp{{w.Cb[0], w.Cb[1]}};
+  const Ctl ctl{w.st, w.pend, w.as.dpart, b.nparts, w.Dtrace, w.Atrace};
+  if (piece == 0)
+    return launch_assign(b.X, b.M, b.L, nullptr, b.N, b.idx, nullptr, b.precision, w.as.dpart,
+                         w.as.nfb, w.as.prep, s, ctl, cbp);
+  return launch_afp(b.X, b.M, b.L, b.idx, nullptr, b.N, nullptr, nullptr, 0, 0.0, w.up.afp, s,
+                    ctl, cbp);
+}
+
+// kBatchIters iterations launched directly; ev (nullable) brackets the
+// allocation and the update of every iteration.
+int enqueue_batch(const Batch& b, hipStream_t s, hipEvent_t (*ev)[3][2]) {
+  for (int i = 0; i < kBatchIters; ++i)
+    for (int piece = 0; piece < kPieces; ++piece) {
+      if (ev) LBG_TRY_HIP(hipEventRecord(ev[i][piece][0], s));
+      LBG_TRY(enqueue_piece(b, piece, s));
+      if (ev) LBG_TRY_HIP(hipEventRecord(ev[i][piece][1], s));
+    }
+  return LBG_OK;
+}
+
+// The same iterations as one graph (opt-in: on gfx950 with ROCm 7.2 direct
+// launches measured faster): each piece is captured once into a child graph;
+// the batch chains kBatchIters copies of the four children, with
+// event-record nodes around the timed pieces (events recorded by graph nodes
+// added this way can be timed; events recorded during a capture cannot).
+int build_batch_graph(const Batch& b, hipStream_t s, hipEvent_t (*ev)[3][2], hipGraph_t* out) {
+  hipGraph_t child[kPieces] = {nullptr, nullptr};
+  hipGraph_t g = nullptr;
+  int rc = LBG_OK;
+  auto cleanup = [&]() {
+    for (auto& c : child)
+      if (c) (void)hipGraphDestroy(c);
+  };
+  for (int piece = 0; piece < kPieces && rc == LBG_OK; ++piece) {
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "hipStreamBeginCapture");
+      break;
+    }
+    rc = enqueue_piece(b, piece, s);
+    e = hipStreamEndCapture(s, &child[piece]);
+    if (rc == LBG_OK && e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
+  }
+  if (rc == LBG_OK) {
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) rc = hip_fail(e, "hipGraphCreate");
+  }
+  hipGraphNode_t prev = nullptr;
+  for (int i = 0; i < kBatchIters && rc == LBG_OK; ++i)
+    for (int piece = 0; piece < kPieces && rc == LBG_OK; ++piece) {
+      hipGraphNode_t node;
+      hipError_t e;
+      if (ev) {
+        e = hipGraphAddEventRecordNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0,
+                                       ev[i][piece][0]);
+        if (e != hipSuccess) { rc = hip_fail(e, "hipGraphAddEventRecordNode"); break; }
+        prev = node;
+      }
+      e = hipGraphAddChildGraphNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, child[piece]);
+      if (e != hipSuccess) { rc = hip_fail(e, "hipGraphAddChildGraphNode"); break; }
+      prev = node;
+      if (ev) {
+        e = hipGraphAddEventRecordNode(&node, g, &prev, 1, ev[i][piece][1]);
+        if (e != hipSuccess) { rc = hip_fail(e, "hipGraphAddEventRecordNode"); break; }
+        prev = node;
+      }
+    }
+  cleanup();
+  if (rc != LBG_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  *out = g;
+  return LBG_OK;
+}
+
+double* pinned_block(size_t bytes) {
+  static thread_local double* p = nullptr;
+  static thread_local size_t have = 0;
+  if (have < bytes) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    have = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&p), bytes, hipHostMallocDefault) != hipSuccess)
+      return nullptr;
+    have = bytes;
+  }
+  return p;
+}
+
+}  // namespace
+
+bool train_device_ok(int64_t L, const TrainWs& w) { return w.up.use_afp && L <= 128; }
+
+int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_params* p,
+                 float* C_out, int32_t* idx_out, double* D_out, lbg_stats* st,
+                 const TrainWs& w, hipStream_t s) {
+  DevState hs;
+  memset(&hs, 0, sizeof(hs));
+  hs.N = (int32_t)N;
+  hs.M = M;
+  hs.max_iter = p->max_iter;
+  hs.fixed_iters = p->fixed_iters;
+  hs.split_mode = p->split_mode;
+  hs.thr = p->thr;
+  hs.eps = p->eps_split;
+  hs.delta = p->delta;
+  hs.D_cap = kTraceCap;
+  hs.first = 1;
+  hs.D_prev = INFINITY;
+  hs.status = LBG_OK;
+  hs.n_forced = std::min(p->n_forced, 32);
+  for (int i = 0; i < hs.n_forced; ++i) hs.forced[i] = p->forced_iters[i];
+
+  CbPair cbp{{w.Cb[0], w.Cb[1]}};
+  if (p->C_init) {
+    LBG_TRY_HIP(hipMemcpyAsync(w.Cb[0], p->C_init, (size_t)(p->N_init * L) * sizeof(float),
+                               hipMemcpyDeviceToDevice, s));
+    hs.cb = 0;
+    hs.n = (int32_t)p->N_init;
+  } else {
+    LBG_TRY(launch_centroid(X, M, L, w.Cb[0], w.ce, s));
+    if (N == 1) {
+      // the centroid is the one-level codebook: one allocation, no update
+      hs.cb = 0;
+      hs.n = 1;
+      hs.n_forced = 1;
+      hs.forced[0] = 0;
+    } else {
+      LBG_TRY(launch_split(w.Cb[0], 1, L, p->split_mode, p->eps_split, p->delta, w.Cb[1], s));
+      hs.cb = 1;
+      hs.n = 2;
+    }
+  }
+  // pinned host block: action trace, then the state
+  int32_t* acts = reinterpret_cast<int32_t*>(pinned_block(sizeof(DevState) + kTraceCap * 4));
+  if (!acts) {
+    set_error("could not allocate pinned host memory");
+    return LBG_EHIP;
+  }
+  DevState* pin = reinterpret_cast<DevState*>(acts + kTraceCap);
+  memcpy(pin, &hs, sizeof(hs));
+  LBG_TRY_HIP(hipMemcpyAsync(w.st, pin, sizeof(DevState), hipMemcpyHostToDevice, s));
+  LBG_TRY_HIP(hipMemsetAsync(w.as.nfb, 0, sizeof(unsigned long long), s));
+  LBG_TRY(launch_afp_shift(X, M, L, w.up.afp, s));
+
+  const bool timed = p->timing != 0 && st != nullptr;
+  Batch b{X, M, L, N, p->precision, p->split_mode, p->eps_split, p->delta, idx_out, &w,
+          assign_num_parts(M, L, p->precision)};
+  const bool use_graph = s != nullptr && p->graph != 0;
+
+  GraphEntry* ge = nullptr;
+  std::unique_lock<std::mutex> lk(g_cache_mu, std::defer_lock);
+  hipEvent_t local_ev[kBatchIters][3][2];
+  int local_ev_n = 0;
+  auto destroy_local = [&]() {
+    hipEvent_t* flat = &local_ev[0][0][0];
+    for (int i = 0; i < local_ev_n; ++i) (void)hipEventDestroy(flat[i]);
+    local_ev_n = 0;
+  };
+  if (use_graph) {
+    lk.lock();
+    GraphKey key;
+    memset(&key, 0, sizeof(key));
+    key.X = X;
+    key.ws = w.Cb[0];
+    key.idx = idx_out;
+    key.M = M;
+    key.L = L;
+    key.N = N;
+    key.precision = p->precision;
+    key.split_mode = p->split_mode;
+    key.timed = timed;
+    key.eps = p->eps_split;
+    key.delta = p->delta;
+    key.stream = s;
+    for (auto& e : g_cache)
+      if (e.used && e.key == key) ge = &e;
+    if (!ge) {
+      GraphEntry* slot = &g_cache[0];
+      for (auto& e : g_cache) {
+        if (!e.used) {
+          slot = &e;
+          break;
+        }
+        if (e.stamp < slot->stamp) slot = &e;
+      }
+      release(*slot);
+      slot->key = key;
+      slot->timed = timed;
+      if (timed)
+        for (int i = 0; i < kBatchIters; ++i)
+          for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 2; ++j)
+              LBG_TRY_HIP(hipEventCreateWithFlags(&slot->ev[i][k][j], kEventFlags));
+      hipGraph_t g = nullptr;
+      const int rc = build_batch_graph(b, s, timed ? slot->ev : nullptr, &g);
+      if (rc < 0) {
+        release(*slot);
+        return rc;
+      }
+      slot->graph = g;
+      LBG_TRY_HIP(hipGraphInstantiate(&slot->exec, g, nullptr, nullptr, 0));
+      slot->used = true;
+      ge = slot;
+    }
+    ge->stamp = ++g_stamp;
+  } else if (timed) {
+    for (int i = 0; i < kBatchIters; ++i)
+      for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 2; ++j) {
+          LBG_TRY_HIP(hipEventCreateWithFlags(&local_ev[i][k][j], kEventFlags));
+          ++local_ev_n;
+        }
+  }
+
+  double ms[3] = {0.0, 0.0, 0.0};
+  int32_t prev_assign = 0;
+  int rc = LBG_OK;
+  for (;;) {
+    if (ge) {
+      const hipError_t e = hipGraphLaunch(ge->exec, s);
+      if (e != hipSuccess) {
+        rc = hip_fail(e, "hipGraphLaunch");
+        break;
+      }
+    } else {
+      rc = enqueue_batch(b, s, timed ? local_ev : nullptr);
+      if (rc < 0) break;
+    }
+    if (hipMemcpyAsync(pin, w.st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(acts, w.Atrace, kTraceCap * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = hip_fail(hipGetLastError(), "state readback");
+      break;
+    }
+    if (timed) {
+      hipEvent_t(*ev)[3][2] = ge ? ge->ev : local_ev;
+      for (int i = 0; i < kBatchIters; ++i) {
+        const int a = prev_assign + i;
+        if (a >= pin->n_assign) break;
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, ev[i][0][0], ev[i][0][1]) == hipSuccess) ms[0] += t;
+        const int act = a < kTraceCap ? acts[a] : kActNone;
+        if (act == kActUpdate && hipEventElapsedTime(&t, ev[i][1][0], ev[i][1][1]) == hipSuccess)
+          ms[1] += t;
+      }
+    }
+    prev_assign = pin->n_assign;
+    if (pin->done) break;
+  }
+  if (lk.owns_lock()) lk.unlock();
+  destroy_local();
+  if (rc < 0) return rc;
+
+  LBG_TRY_HIP(hipMemcpyAsync(C_out, w.Cb[pin->cb], (size_t)(N * L) * sizeof(float),
+                             hipMemcpyDeviceToDevice, s));
+  if (st) {
+    unsigned long long nf = 0;
+    LBG_TRY_HIP(hipMemcpyAsync(&nf, w.as.nfb, sizeof(nf), hipMemcpyDeviceToHost, s));
+    const int nD = std::min(pin->n_assign, std::min(st->D_cap, kTraceCap));
+    if (st->D_trace && nD > 0)
+      LBG_TRY_HIP(hipMemcpyAsync(st->D_trace, w.Dtrace, (size_t)nD * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+    LBG_TRY_HIP(hipStreamSynchronize(s));
+    st->fallback_rows = (int64_t)nf;
+    st->n_D = pin->n_assign;
+    st->total_assigns = pin->n_assign;
+    st->total_updates = pin->n_update;
+    st->total_distances = pin->distances;
+    st->n_levels = pin->level;
+    for (int i = 0; i < std::min(pin->level, 32); ++i) {
+      st->level_n[i] = pin->level_n[i];
+      st->level_iters[i] = pin->level_iters[i];
+    }
+    st->ms_assign = ms[0];
+    st->ms_update = ms[1];
+    st->ms_split = ms[2];
+  } else {
+    LBG_TRY_HIP(hipStreamSynchronize(s));
+  }
+  *D_out = pin->D;
+  return pin->status;
+}
+
+}  // namespace lbg

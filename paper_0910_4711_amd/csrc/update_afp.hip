@@ -23,6 +23,7 @@
 //             is formed in integers before the single rounding.
 #include <algorithm>
 
+#include "control.h"
 #include "lbg_internal.h"
 
 namespace lbg {
@@ -134,10 +135,30 @@ template <int G, int VW, int DPL>
 __global__ __launch_bounds__(kT) void acc_kernel(
     const float* __restrict__ X, int64_t M, int L, const int32_t* __restrict__ idx, int N,
     int cps, int nslices, int64_t rows_per_chunk, const int* __restrict__ shift_p,
-    unsigned long long* __restrict__ part, int32_t* __restrict__ pcnt) {
+    unsigned long long* __restrict__ part, int32_t* __restrict__ pcnt, Ctl ctl) {
   extern __shared__ unsigned long long sacc[];
   __shared__ int32_t slist[kBatch];
   __shared__ int32_t snsel;
+  if (ctl.st) {
+    // Decision of this iteration from the allocation's partials, the same in
+    // every block; block 0 records the next state in ctl.pend.
+    __shared__ double red[kT];
+    __shared__ int s_act;
+    const DevState* st = ctl.st;
+    if (st->done) return;
+    const double D = block_distortion(ctl.dpart, ctl.nparts, st->M, red);
+    if (threadIdx.x == 0) {
+      const Step r = step_of(st, D);
+      s_act = r.action;
+      if (blockIdx.x == 0) {
+        *ctl.pend = *st;
+        apply_step(st, ctl.pend, D, r, ctl.Dtrace, ctl.Atrace);
+      }
+    }
+    __syncthreads();
+    if (s_act != kActUpdate) return;
+    N = st->n;
+  }
   const int chunk = blockIdx.x / nslices, slice = blockIdx.x % nslices;
   const int k0 = slice * cps, k1 = min(N, k0 + cps), nk = max(0, k1 - k0);
   int32_t* scnt = reinterpret_cast<int32_t*>(sacc + (size_t)cps * L);
@@ -215,10 +236,42 @@ template <int MODE>
 __global__ __launch_bounds__(kT) void fin_kernel(
     const unsigned long long* __restrict__ part, const int32_t* __restrict__ pcnt, int nchunks,
     int N, int L, const int* __restrict__ shift_p, const float* __restrict__ C_old,
-    float* __restrict__ out, int32_t* __restrict__ counts, double g2) {
+    float* __restrict__ out, int32_t* __restrict__ counts, double g2, Ctl ctl, CbPair cbp) {
   __shared__ unsigned long long red[kT];
   __shared__ long long scount;
   const int k = blockIdx.x;
+  if (ctl.st) {
+    // act on the pending state; block 0 commits it for the next allocation
+    if (ctl.st->done) return;
+    const DevState* st = ctl.pend;
+    if (k == 0 && threadIdx.x == 0) *ctl.st = *st;
+    if (st->action == kActSplit) {
+      // Codebook Splitting of codevector k (the split kernel's arithmetic):
+      // children 2k ("+") and 2k+1 ("-"), formed in FP64, rounded once.
+      if (k >= st->n_src) return;
+      const float* Cs = cbp.c[st->src];
+      float* Cd = cbp.c[st->dst];
+      for (int d = threadIdx.x; d < L; d += kT) {
+        const double c = (double)Cs[(int64_t)k * L + d];
+        double up, dn;
+        if (st->split_mode == LBG_SPLIT_ADD) {
+          up = c + st->delta;
+          dn = c - st->delta;
+        } else {
+          up = c * (1.0 + st->eps);
+          dn = c * (1.0 - st->eps);
+        }
+        Cd[(int64_t)(2 * k) * L + d] = (float)up;
+        Cd[(int64_t)(2 * k + 1) * L + d] = (float)dn;
+      }
+      return;
+    }
+    if (st->action != kActUpdate) return;
+    N = st->n_src;
+    C_old = cbp.c[st->src];
+    out = cbp.c[st->dst];
+    if (k >= N) return;
+  }
   const int t = threadIdx.x;
   if (t < 64) {
     long long c = 0;
@@ -275,9 +328,9 @@ __global__ __launch_bounds__(kT) void fin_kernel(
 template <int G, int VW, int DPL>
 void launch_acc(dim3 grid, size_t lds, hipStream_t st, const float* X, int64_t M, int L,
                 const int32_t* idx, int N, int cps, int nslices, int64_t rpc, const int* sp,
-                unsigned long long* part, int32_t* pcnt) {
+                unsigned long long* part, int32_t* pcnt, Ctl ctl) {
   hipLaunchKernelGGL((acc_kernel<G, VW, DPL>), grid, dim3(kT), lds, st, X, M, L, idx, N, cps,
-                     nslices, rpc, sp, part, pcnt);
+                     nslices, rpc, sp, part, pcnt, ctl);
 }
 
 }  // namespace
@@ -315,7 +368,7 @@ int launch_afp_shift(const float* X, int64_t M, int64_t L, const AfpWs& w, hipSt
 
 int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const float* C_old,
                int64_t N, float* C_out, int32_t* counts, int mode, double g2, const AfpWs& w,
-               hipStream_t s) {
+               hipStream_t s, Ctl ctl, CbPair cbp) {
   const bool vec = (L % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
   const int VW = vec ? 4 : 1;
   const int lanes = (int)((L + VW - 1) / VW);
@@ -328,7 +381,7 @@ int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const f
 #define LBG_ACC(GG, VV, DD)                                                                     \
   if (G == GG && VW == VV && DPL == DD) {                                                       \
     launch_acc<GG, VV, DD>(grid, lds, s, X, M, Li, idx, n, w.cps, w.nslices, w.rows_per_chunk, \
-                           w.shift, w.part, w.pcnt);                                            \
+                           w.shift, w.part, w.pcnt, ctl);                                       \
   } else
   LBG_ACC(1, 4, 1) LBG_ACC(2, 4, 1) LBG_ACC(4, 4, 1) LBG_ACC(8, 4, 1) LBG_ACC(16, 4, 1)
   LBG_ACC(32, 4, 1) LBG_ACC(64, 4, 1)
@@ -341,10 +394,10 @@ int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const f
   LBG_TRY_HIP(hipGetLastError());
   if (mode == 0)
     hipLaunchKernelGGL(fin_kernel<0>, dim3((unsigned)N), dim3(kT), 0, s, w.part, w.pcnt,
-                       w.nchunks, n, Li, w.shift, C_old, C_out, counts, g2);
+                       w.nchunks, n, Li, w.shift, C_old, C_out, counts, g2, ctl, cbp);
   else
     hipLaunchKernelGGL(fin_kernel<1>, dim3((unsigned)N), dim3(kT), 0, s, w.part, w.pcnt,
-                       w.nchunks, n, Li, w.shift, C_old, C_out, counts, g2);
+                       w.nchunks, n, Li, w.shift, C_old, C_out, counts, g2, ctl, cbp);
   LBG_TRY_HIP(hipGetLastError());
   return LBG_OK;
 }

@@ -284,3 +284,32 @@ def test_backward_matches_oracle(P):
     rX, rC = oracle.grad(X, C.astype(np.float64), idx_o, g=1.5)
     np.testing.assert_allclose(host(gX), rX, rtol=2 ** -22, atol=1e-30)
     np.testing.assert_allclose(host(gC), rC, rtol=2 ** -22, atol=1e-12)
+
+
+def test_train_graph_replays_match_eager(P):
+    # On a non-default stream the iterations run as a captured hipGraph,
+    # replayed many times per run and reused across runs; every run must
+    # equal the eager (graph-free) run and the oracle, with other GPU work
+    # and synchronisations between the runs.
+    X = synth.image_training_set((2,), 256, 256, 4)
+    Xd = dev(X)
+    ref = oracle.train(X, 32, store_fp32=True)
+    eager = P.train(Xd, 32)
+    np.testing.assert_array_equal(host(eager[0]), ref["C"].astype(np.float32))
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        with torch.cuda.stream(side):
+            C, idx, D, st = P.train(Xd, 32, graph=True)
+        side.synchronize()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(C), host(eager[0]))
+        np.testing.assert_array_equal(host(idx), host(eager[1]))
+        assert D == eager[2]
+        assert st["level_iters"] == eager[3]["level_iters"]
+        _ = (Xd * 2).sum().item()  # unrelated eager work between runs
+    # timing through graph-captured events
+    with torch.cuda.stream(side):
+        C, idx, D, st = P.train(Xd, 32, timing=True, graph=True)
+    side.synchronize()
+    np.testing.assert_array_equal(host(C), host(eager[0]))
+    assert st["ms_assign"] > 0 and st["ms_update"] > 0
