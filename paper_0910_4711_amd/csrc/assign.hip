@@ -74,18 +74,40 @@ size_t prep_bytes(int64_t L, int64_t N, int precision) {
 
 int assign_rows_per_wg(int64_t L, int precision) {
   (void)precision;
-  const int LP = padded_dim(L);
-  if (LP == 0) return 256;
-  return LP == 128 ? 128 : 256;
+  return padded_dim(L) == 0 ? 256 : kRowsPerTile;
 }
 
+namespace {
+template <class SC>
+int64_t grid_of(int64_t M) {
+  return std::min<int64_t>((M + kRowsPerTile - 1) / kRowsPerTile, persist_blocks<SC>());
+}
+}  // namespace
+
 // Matrix-core kernels: one partial per wave of every block of the
-// persistent grid (kPersistBlocks at most); exhaustive kernel: one per block
-// of 256 rows.
+// persistent grid; exhaustive kernel: one per block of 256 rows.
 int64_t assign_num_parts(int64_t M, int64_t L, int precision) {
-  const int r = assign_rows_per_wg(L, precision);
-  const int64_t tiles = (M + r - 1) / r;
-  return padded_dim(L) == 0 ? tiles : 4 * std::min<int64_t>(tiles, kPersistBlocks);
+  const int LP = padded_dim(L);
+  if (LP == 0) return (M + 255) / 256;
+  int64_t g;
+  if (precision == LBG_BF16_RESCORE) {
+    switch (LP) {
+      case 8:
+      case 16: g = grid_of<Bf16Screen<16>>(M); break;
+      case 32: g = grid_of<Bf16Screen<32>>(M); break;
+      case 64: g = grid_of<Bf16Screen<64>>(M); break;
+      default: g = grid_of<Bf16Screen<128>>(M); break;
+    }
+  } else {
+    switch (LP) {
+      case 8: g = grid_of<Fp32Screen<8>>(M); break;
+      case 16: g = grid_of<Fp32Screen<16>>(M); break;
+      case 32: g = grid_of<Fp32Screen<32>>(M); break;
+      case 64: g = grid_of<Fp32Screen<64>>(M); break;
+      default: g = grid_of<Fp32Screen<128>>(M); break;
+    }
+  }
+  return 4 * g;
 }
 
 void plan_assign(Carver& c, int64_t M, int64_t L, int64_t N, int precision, AssignWs* ws) {

@@ -1,26 +1,32 @@
 // Cell Allocation on gfx950 matrix cores: the kernel shared by the FP32
 // screen (exact result) and the BF16 screen (precision form).
 //
-//   * prep: the codebook is written once per call in the LDS row layout of
-//     the screen: -2c (exact scaling), zero-padded to LP dimensions, with the
-//     squared norm stored in the row's padding; rows are padded to a multiple
-//     of 32 with a huge norm so that padding never wins.
-//   * One workgroup = 4 waves; a wave owns XT tiles of 32 training vectors,
-//     a workgroup a "row tile" of 128*XT vectors.  Workgroups loop over row
-//     tiles.  The codebook is staged into LDS with 16-byte copies: once per
-//     workgroup when it fits (resident), otherwise chunk by chunk per row tile.
+//   * The codebook is staged into LDS in the screen's row layout: -2c (exact
+//     scaling), zero-padded to LP dimensions, with the squared norm in the
+//     row's padding; rows are padded to a multiple of 32 with a huge norm so
+//     that padding never wins.  A codebook that fits is staged once per
+//     workgroup (resident); otherwise a prepared copy is staged chunk by chunk
+//     for every row tile.
+//   * One workgroup = 4 waves; a wave owns a tile of 32 training vectors, a
+//     workgroup a row tile of 128.  Workgroups loop over row tiles; the grid
+//     is sized so that 2 to 4 waves share each SIMD (by register use), which
+//     lets one wave's candidate work overlap another's matrix-core work.
 //   * Screen: v_mfma_f32_32x32x2_f32 (FP32) or v_mfma_f32_32x32x16_bf16 (BF16)
 //     computes |c|^2 + |x|^2 - 2 x.c for a 32 (codevectors) x 32 (vectors)
 //     tile; a first K-step with A = [|c|^2, 1], B = [1, |x|^2] adds both norms,
 //     so the accumulator starts at zero.  Codevectors are the A operand, so
-//     each lane holds 16 distances of ONE vector.
+//     each lane holds 16 distances of ONE vector; the two lanes (j, 0) and
+//     (j, 1) hold the 32 codevectors of a tile for vector j between them.
 //   * Each lane keeps the two smallest keys of every accumulator slot; a key
 //     is the screened distance with its low mantissa bits replaced by the tile
-//     number (3 VALU ops per distance: and-or, med3 as min, med3).
+//     number (3 VALU ops per distance: and-or, med3 as min, med3).  The tile
+//     loop is software-pipelined: the products of tile t+1 are issued before
+//     the key updates of tile t.
 //   * FP32: the best candidate is rescored in FP64, direct form, dimension
-//     order; a rigorous bound on the screen's rounding decides whether it is
-//     provably the unique nearest codevector, otherwise the wave searches the
-//     row again exhaustively in FP64.  BF16: the two best candidates are
+//     order (lane (j, 0) sums the first half of the dimensions, lane (j, 1)
+//     continues); a rigorous bound on the screen's rounding decides whether it
+//     is provably the unique nearest codevector, otherwise the wave searches
+//     the row again exhaustively in FP64.  BF16: the two best candidates are
 //     rescored in FP64 and the closer taken (lowest index on ties).
 #pragma once
 
@@ -43,8 +49,7 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr float kBig = 3.0e38f;    // squared norm of padding codevectors
-constexpr int kPersistBlocks = 512;  // grid of the allocation kernel (2 per CU)
-constexpr int kLdsBudget = 61440;  // bytes of LDS for the staged codebook
+constexpr int kRowsPerTile = 128;  // training vectors per workgroup row tile
 
 // Row of the 32 x 32 matrix-core result held in accumulator register r of
 // ``lane``: four groups of four rows, the two half-waves interleaved by four.
@@ -53,13 +58,16 @@ __device__ __forceinline__ int out_row(int lane, int r) {
 }
 
 // ---------------------------------------------------------------- policy --
+// OCC: waves per SIMD the kernel is built for (2 .. 4, by register use); the
+// persistent grid holds 256 * OCC workgroups and each may stage up to
+// LDS bytes of codebook.
 template <int LP_>
 struct Fp32Screen {
   static constexpr int LP = LP_;
   static constexpr int S = LP + 4;   // row stride, elements
   static constexpr int ESZ = 4;      // bytes per element
-  static constexpr int NS = LP / 2;  // K-steps of the data
-  static constexpr int XT = (LP >= 128) ? 1 : 2;
+  static constexpr int NS = LP / 2;  // data K-steps per tile (half per lane half)
+  static constexpr int OCC = LP <= 16 ? 3 : 2;
   static constexpr bool EXACT = true;
   typedef float elem;
 };
@@ -70,20 +78,23 @@ struct Bf16Screen {
   static constexpr int S = LP + 8;
   static constexpr int ESZ = 2;
   static constexpr int NS = LP / 16;
-  static constexpr int XT = (LP >= 128) ? 1 : 2;
+  static constexpr int OCC = LP <= 16 ? 4 : (LP <= 32 ? 3 : 2);
   static constexpr bool EXACT = false;
   typedef __bf16 elem;
 };
 
 template <class SC>
-constexpr int rows_per_tile() { return 4 * 32 * SC::XT; }
+constexpr int persist_blocks() { return 256 * SC::OCC; }
+
+template <class SC>
+constexpr int lds_budget() { return SC::OCC >= 4 ? 40960 : (SC::OCC == 3 ? 53248 : 61440); }
 
 // Rows of codevectors staged per chunk (multiple of 32) for a codebook of
 // n_pad rows: all of it when it fits the LDS budget.
 template <class SC>
 inline int chunk_rows(int n_pad) {
   const int row_bytes = SC::S * SC::ESZ;
-  const int cap = (kLdsBudget / row_bytes) & ~31;
+  const int cap = (lds_budget<SC>() / row_bytes) & ~31;
   return n_pad <= cap ? n_pad : cap;
 }
 
@@ -148,80 +159,154 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ C, 
 }
 
 // ----------------------------------------------------------- candidates --
-template <int XT>
 struct Slots {
-  float mn[XT][16];
-  float mn2[XT][16];
+  float mn[16];
+  float mn2[16];
   __device__ __forceinline__ void init() {
 #pragma unroll
-    for (int xt = 0; xt < XT; ++xt)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        mn[xt][r] = FLT_MAX;
-        mn2[xt][r] = FLT_MAX;
-      }
+    for (int r = 0; r < 16; ++r) {
+      mn[r] = FLT_MAX;
+      mn2[r] = FLT_MAX;
+    }
   }
   // key = distance with its low mantissa bits replaced by the tile number;
-  // min as med3(a, b, -inf) (no NaN canonicalisation), second via med3.
-  __device__ __forceinline__ void push(int xt, const f16v& acc, uint32_t vmask,
-                                       uint32_t tb, float ninf) {
+  // min as med3(a, b, -inf) (ninf must be opaque to the compiler, or the
+  // med3 becomes a canonicalising min), second via med3.
+  __device__ __forceinline__ void push(const f16v& acc, uint32_t vmask, uint32_t tb,
+                                       float ninf) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const float k = __uint_as_float((__float_as_uint(acc[r]) & vmask) | tb);
-      const float a = mn[xt][r];
-      mn2[xt][r] = __builtin_amdgcn_fmed3f(a, mn2[xt][r], k);
-      mn[xt][r] = __builtin_amdgcn_fmed3f(a, k, ninf);
+      const float a = mn[r];
+      mn2[r] = __builtin_amdgcn_fmed3f(a, mn2[r], k);
+      mn[r] = __builtin_amdgcn_fmed3f(a, k, ninf);
     }
   }
 };
 
-struct Top2 {
-  float k1, k2;
-  int i1, i2;
-  __device__ __forceinline__ void insert(float v, int id) {
-    if (v < k1) {
-      k2 = k1;
-      i2 = i1;
-      k1 = v;
-      i1 = id;
-    } else if (v < k2) {
-      k2 = v;
-      i2 = id;
-    }
-  }
-};
-
-__device__ __forceinline__ bool before(float a, int ia, float b, int ib) {
-  return a < b || (a == b && ia < ib);
+// Every lane receives the value of lane (j, 0) in lo and of lane (j, 1) in
+// hi (one v_permlane32_swap of v with itself).
+__device__ __forceinline__ void pair_values(float v, float& lo, float& hi) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v),
+                                                  false, false);
+  lo = __uint_as_float(r[0]);
+  hi = __uint_as_float(r[1]);
 }
 
-// Two smallest keys of one training vector over all slots of both half-
-// waves; both lanes of the pair obtain the same result.
-template <int XT>
-__device__ __forceinline__ Top2 top2_of(const Slots<XT>& sl, int xt, int lane,
-                                        uint32_t lowmask) {
-  Top2 t{INFINITY, INFINITY, -1, -1};
+__device__ __forceinline__ void pair_values(int v, int& lo, int& hi) {
+  float a, b;
+  pair_values(__int_as_float(v), a, b);
+  lo = __float_as_int(a);
+  hi = __float_as_int(b);
+}
+
+// Value held by lane l ^ OFF (OFF a power of two below 64), without a
+// lane-address register: ds_swizzle (xor mode within 32 lanes) or, across
+// the two halves, v_permlane32_swap.
+template <int OFF>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+  if constexpr (OFF == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (threadIdx.x & 32) ? r[0] : r[1];
+  } else {
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (OFF << 10) | 0x1f);
+  }
+}
+
+template <int OFF>
+__device__ __forceinline__ double xor_lane(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint64_t lo = xor_lane<OFF>((uint32_t)b), hi = xor_lane<OFF>((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
+template <int OFF>
+__device__ __forceinline__ int xor_lane(int v) {
+  return (int)xor_lane<OFF>((uint32_t)v);
+}
+
+// Smallest distance over the wave, lowest index on equal distances.
+template <int OFF>
+__device__ __forceinline__ void argmin_step(double& best, int& bi) {
+  const double ob = xor_lane<OFF>(best);
+  const int oi = xor_lane<OFF>(bi);
+  if (ob < best || (ob == best && oi < bi)) {
+    best = ob;
+    bi = oi;
+  }
+}
+
+// Sum over the wave by a fixed butterfly (the same result in every lane).
+__device__ __forceinline__ double wave_sum(double v) {
+  v += xor_lane<32>(v);
+  v += xor_lane<16>(v);
+  v += xor_lane<8>(v);
+  v += xor_lane<4>(v);
+  v += xor_lane<2>(v);
+  v += xor_lane<1>(v);
+  return v;
+}
+
+// Smallest key k1 of the vector (codevector i1, lowest index among equal
+// keys), the smallest key k2 of all other codevectors, and for the BF16
+// screen a codevector i2 with key k2.  Keys of one tile differ in their rows
+// only; equal keys of two tiles cannot occur (the tile number is part of the
+// key).  Each lane reduces its 16 slots (slot r holds row 8 (r >> 2) + 4 h +
+// (r & 3) of every tile), then the pair (j, 0), (j, 1) merges; both lanes of
+// the pair obtain the same result.
+struct Cand {
+  float k1, k2;
+  int i1, i2;
+};
+
+template <bool SECOND>
+__device__ __forceinline__ Cand best_of(const Slots& sl, uint32_t lowmask, float ninf, int h) {
+  float m1 = INFINITY, m2 = INFINITY;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int rr = out_row(lane, r);
-    const float a = sl.mn[xt][r], b = sl.mn2[xt][r];
-    t.insert(a, (int)((__float_as_uint(a) & lowmask) << 5) + rr);
-    t.insert(b, (int)((__float_as_uint(b) & lowmask) << 5) + rr);
+    m2 = __builtin_amdgcn_fmed3f(m1, m2, sl.mn[r]);
+    m1 = __builtin_amdgcn_fmed3f(m1, sl.mn[r], ninf);
   }
-  const float b1 = __shfl_xor(t.k1, 32), b2 = __shfl_xor(t.k2, 32);
-  const int bi1 = __shfl_xor(t.i1, 32), bi2 = __shfl_xor(t.i2, 32);
-  const bool aFirst = before(t.k1, t.i1, b1, bi1);
-  Top2 o;
-  o.k1 = aFirst ? t.k1 : b1;
-  o.i1 = aFirst ? t.i1 : bi1;
-  const float c1 = aFirst ? b1 : t.k1;
-  const int ci1 = aFirst ? bi1 : t.i1;
-  const float c2 = aFirst ? t.k2 : b2;
-  const int ci2 = aFirst ? t.i2 : bi2;
-  const bool cFirst = before(c1, ci1, c2, ci2);
-  o.k2 = cFirst ? c1 : c2;
-  o.i2 = cFirst ? ci1 : ci2;
-  return o;
+  float s2 = INFINITY;
+  int r1 = 0;
+#pragma unroll
+  for (int r = 15; r >= 0; --r) {
+    const bool e = sl.mn[r] == m1;
+    s2 = e ? sl.mn2[r] : s2;
+    r1 = e ? r : r1;
+  }
+  const int row1 = 8 * (r1 >> 2) + 4 * h + (r1 & 3);
+  const float k2l = __builtin_amdgcn_fmed3f(m2, s2, ninf);
+  const int i1l = (int)((__float_as_uint(m1) & lowmask) << 5) + row1;
+  int i2l = -1;
+  if constexpr (SECOND) {
+    int r2 = 0;
+#pragma unroll
+    for (int r = 15; r >= 0; --r) {
+      const bool e = sl.mn[r] == m2 && r != r1;
+      r2 = e ? r : r2;
+    }
+    const int row2 = 8 * (r2 >> 2) + 4 * h + (r2 & 3);
+    i2l = s2 <= m2 ? (int)((__float_as_uint(s2) & lowmask) << 5) + row1
+                   : (int)((__float_as_uint(m2) & lowmask) << 5) + row2;
+  }
+  float a1, b1, a2, b2;
+  int ai, bi;
+  pair_values(m1, a1, b1);
+  pair_values(k2l, a2, b2);
+  pair_values(i1l, ai, bi);
+  const bool aw = a1 < b1 || (a1 == b1 && ai < bi);
+  Cand c;
+  c.k1 = aw ? a1 : b1;
+  c.i1 = aw ? ai : bi;
+  c.k2 = aw ? __builtin_amdgcn_fmed3f(a2, b1, ninf) : __builtin_amdgcn_fmed3f(b2, a1, ninf);
+  c.i2 = -1;
+  if constexpr (SECOND) {
+    int ai2, bi2;
+    pair_values(i2l, ai2, bi2);
+    c.i2 = aw ? (a2 < b1 ? ai2 : bi) : (b2 < a1 ? bi2 : ai);
+  }
+  return c;
 }
 
 // Row of L floats into registers (LP slots, zero beyond L), loads issued
@@ -267,8 +352,56 @@ __device__ __forceinline__ double d64(const float* x, const float* c, int L) {
   return s;
 }
 
-// Rescore, decide, fall back and store for the vectors of this wave.  Lane
-// (j, h) handles vector j of tile xt = 2p + h.
+// Dimensions [l0, l0 + W) of the same sum, continuing from s; the rows are
+// read W elements at a time (zero beyond L).
+template <int W, bool VEC>
+__device__ __forceinline__ double d64_part(const float* __restrict__ x,
+                                           const float* __restrict__ c, int l0, int L,
+                                           double s) {
+  float xa[W], ca[W];
+  if (VEC) {
+#pragma unroll
+    for (int q = 0; q < W; q += 4) {
+      const float4 a = *reinterpret_cast<const float4*>(x + l0 + q);
+      const float4 b = *reinterpret_cast<const float4*>(c + l0 + q);
+      xa[q] = a.x; xa[q + 1] = a.y; xa[q + 2] = a.z; xa[q + 3] = a.w;
+      ca[q] = b.x; ca[q + 1] = b.y; ca[q + 2] = b.z; ca[q + 3] = b.w;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      xa[q] = (l0 + q < L) ? x[l0 + q] : 0.0f;
+      ca[q] = (l0 + q < L) ? c[l0 + q] : 0.0f;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < W; ++q) {
+    if (l0 + q < L) {
+      const double t = (double)xa[q] - (double)ca[q];
+      s = s + t * t;
+    }
+  }
+  return s;
+}
+
+// Squared distance of two rows in memory, streamed 16 dimensions at a time
+// (rows of exactly LP floats) or one at a time.
+template <int LP, bool VEC>
+__device__ __forceinline__ double d64_mem(const float* __restrict__ x,
+                                          const float* __restrict__ c, int L) {
+  if constexpr (!VEC) {
+    return d64(x, c, L);
+  } else {
+    constexpr int W = LP < 16 ? LP : 16;
+    double s = 0.0;
+#pragma unroll
+    for (int l0 = 0; l0 < LP; l0 += W) s = d64_part<W, true>(x, c, l0, L, s);
+    return s;
+  }
+}
+
+// Rescore, decide, fall back and store for the vectors of this wave; lane
+// (j, 1) finishes vector j.
 //   EXACT (FP32 screen): accept the best candidate w only if
 //     d(w) * (1 + 4 (L+2) 2^-53) < K2 / (1 + 2^(tile_bits-23)) - E,
 //     E = 2 * gamma_{L+4} * (1 + 2^-24) * (2 |x| + sqrt(d(w)))^2 + 1e-30,
@@ -276,8 +409,11 @@ __device__ __forceinline__ double d64(const float* x, const float* c, int L) {
 //   rounding error for every codevector c with d(c) <= d(w) (such a c has
 //   |c| <= |x| + sqrt(d(w))); the division undoes the key's replaced mantissa
 //   bits; K2 is the second-smallest key.  So every other codevector is
-//   strictly farther, in exact arithmetic and in FP64.  Rows that fail are
-//   searched exhaustively in FP64 by the whole wave (lowest index on ties).
+//   strictly farther, in exact arithmetic and in FP64.  E is evaluated in
+//   FP32 with its factor raised by 2^-12, which covers the rounding of that
+//   evaluation; the right-hand side is lowered by 2^-48 of itself for the
+//   FP64 rounding of K2 / (1 + ...) - E.  Rows that fail are searched
+//   exhaustively in FP64 by the whole wave (lowest index on ties).
 //   Otherwise (BF16 screen): both candidates are rescored in FP64 and the
 //   closer one is taken, the lower index on equal distances.
 // Exhaustive FP64 search of one row by the whole wave (FP32 screen only):
@@ -291,193 +427,230 @@ __device__ __forceinline__ void search_row(const float* __restrict__ xrow, int L
                                            const float* resident, int lane, double* best_d,
                                            int* best_i) {
   constexpr int LP = SC::LP;
-  float xr[LP];
-  load_row<LP, VEC>(xrow, L, xr);
+  constexpr int W = LP < 16 ? LP : 16;
+  constexpr bool XREG = LP <= 32;  // the row in registers; else streamed with c
+  float xr[XREG ? LP : 1];
+  if constexpr (XREG) load_row<LP, VEC>(xrow, L, xr);
   double best = INFINITY;
   int bi = 0x7fffffff;
-  if (resident) {
-    for (int k = lane; k < n; k += 64) {
-      const float* r = resident + (int64_t)k * SC::S;
-      float cr[LP];
+  for (int k = lane; k < n; k += 64) {
+    double dk = 0.0;
 #pragma unroll
-      for (int s4 = 0; s4 < LP; s4 += 4) {
-        const float4 q = *reinterpret_cast<const float4*>(r + s4);
-        cr[s4] = -0.5f * q.x;
-        cr[s4 + 1] = -0.5f * q.y;
-        cr[s4 + 2] = -0.5f * q.z;
-        cr[s4 + 3] = -0.5f * q.w;
+    for (int l0 = 0; l0 < LP; l0 += W) {
+      float cr[W], xc[W];
+      if (resident) {
+        const float* r = resident + (int64_t)k * SC::S + l0;
+#pragma unroll
+        for (int q = 0; q < W; q += 4) {
+          const float4 v = *reinterpret_cast<const float4*>(r + q);
+          cr[q] = -0.5f * v.x;
+          cr[q + 1] = -0.5f * v.y;
+          cr[q + 2] = -0.5f * v.z;
+          cr[q + 3] = -0.5f * v.w;
+        }
+      } else {
+        const float* r = C + (int64_t)k * L;
+        if (VEC) {
+#pragma unroll
+          for (int q = 0; q < W; q += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(r + l0 + q);
+            cr[q] = v.x;
+            cr[q + 1] = v.y;
+            cr[q + 2] = v.z;
+            cr[q + 3] = v.w;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < W; ++q) cr[q] = (l0 + q < L) ? r[l0 + q] : 0.0f;
+        }
       }
-      const double dk = d64_regs<LP>(xr, cr, L);
-      if (dk < best) {
-        best = dk;
-        bi = k;
+      if constexpr (XREG) {
+#pragma unroll
+        for (int q = 0; q < W; ++q) xc[q] = xr[l0 + q];
+      } else if (VEC) {
+#pragma unroll
+        for (int q = 0; q < W; q += 4) {
+          const float4 v = *reinterpret_cast<const float4*>(xrow + l0 + q);
+          xc[q] = v.x;
+          xc[q + 1] = v.y;
+          xc[q + 2] = v.z;
+          xc[q + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < W; ++q) xc[q] = (l0 + q < L) ? xrow[l0 + q] : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        if (l0 + q < L) {
+          const double t = (double)xc[q] - (double)cr[q];
+          dk = dk + t * t;
+        }
       }
     }
-  } else {
-    int k = lane;
-    for (; k + 64 < n; k += 128) {
-      float c0[LP], c1[LP];
-      load_row<LP, VEC>(C + (int64_t)k * L, L, c0);
-      load_row<LP, VEC>(C + (int64_t)(k + 64) * L, L, c1);
-      const double d0 = d64_regs<LP>(xr, c0, L);
-      const double d1 = d64_regs<LP>(xr, c1, L);
-      if (d0 < best) {
-        best = d0;
-        bi = k;
-      }
-      if (d1 < best) {
-        best = d1;
-        bi = k + 64;
-      }
-    }
-    if (k < n) {
-      float c0[LP];
-      load_row<LP, VEC>(C + (int64_t)k * L, L, c0);
-      const double d0 = d64_regs<LP>(xr, c0, L);
-      if (d0 < best) {
-        best = d0;
-        bi = k;
-      }
+    if (dk < best) {
+      best = dk;
+      bi = k;
     }
   }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const double ob = __shfl_xor(best, off);
-    const int oi = __shfl_xor(bi, off);
-    if (ob < best || (ob == best && oi < bi)) {
-      best = ob;
-      bi = oi;
-    }
-  }
+  argmin_step<32>(best, bi);
+  argmin_step<16>(best, bi);
+  argmin_step<8>(best, bi);
+  argmin_step<4>(best, bi);
+  argmin_step<2>(best, bi);
+  argmin_step<1>(best, bi);
   *best_d = best;
   *best_i = bi;
 }
 
-// Returns the sum of the winning distances of the rows this lane handled.
-template <class SC, bool VEC, class BF>
-__device__ __forceinline__ double finish_rows(const Slots<SC::XT>& sl,
-                                              const float* __restrict__ X, int64_t M, int L,
-                                              const float* __restrict__ C, int n,
-                                              int32_t* __restrict__ idx,
+// Constants of the acceptance test of the FP32 screen.
+struct Bound {
+  float cE;      // 2 gamma_{L+4} (1 + 2^-24) (1 + 2^-12)
+  double invks;  // (1 - 2^-48) / (1 + 2^(tile_bits - 23))
+  double dslack; // 1 + 4 (L + 2) 2^-53
+};
+
+__device__ __forceinline__ Bound bound_of(int L, int tile_bits) {
+  Bound b;
+  const double k = (double)(L + 4) * 0x1p-24;
+  b.cE = (float)(2.0 * (k / (1.0 - k)) * (1.0 + 0x1p-24) * (1.0 + 0x1p-12));
+  b.invks = (1.0 - 0x1p-48) / (1.0 + ldexp(1.0, tile_bits - 23));
+  b.dslack = 1.0 + 4.0 * (double)(L + 2) * 0x1p-53;
+  return b;
+}
+
+// Half of the codevector row that lane half h scores in the chained FP64
+// distance: dimensions [h LP/2, (h+1) LP/2), from the resident screen copy
+// (-2c, exact: times -1/2) or from C.
+template <class SC, bool VEC>
+__device__ __forceinline__ void c_half(const float* __restrict__ C, int L,
+                                       const float* resident, int w, int h,
+                                       float (&cr)[SC::LP / 2]) {
+  constexpr int H = SC::LP / 2;
+  if (resident) {
+    const float* r = resident + (int64_t)w * SC::S + h * H;
+#pragma unroll
+    for (int q = 0; q < H; q += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(r + q);
+      cr[q] = -0.5f * v.x;
+      cr[q + 1] = -0.5f * v.y;
+      cr[q + 2] = -0.5f * v.z;
+      cr[q + 3] = -0.5f * v.w;
+    }
+  } else {
+    const float* r = C + (int64_t)w * L + h * H;
+    if (VEC) {
+#pragma unroll
+      for (int q = 0; q < H; q += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(r + q);
+        cr[q] = v.x;
+        cr[q + 1] = v.y;
+        cr[q + 2] = v.z;
+        cr[q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < H; ++q) cr[q] = (h * H + q < L) ? r[q] : 0.0f;
+    }
+  }
+}
+
+// Returns the winning distance of the vector this lane finished (0 for the
+// other lanes).  xv: lane (j, h) holds dimensions [h LP/2, (h+1) LP/2) of
+// vector j (FP32); xsq: the vector's squared norm (FP32).  Lane (j, 0) sums
+// the FP64 distance over the first half of the dimensions, lane (j, 1)
+// continues it over the second half and finishes the vector.
+template <class SC, bool VEC>
+__device__ __forceinline__ double finish_rows(const Slots& sl, const float* __restrict__ X,
+                                              int64_t M, int L, const float* __restrict__ C,
+                                              int n, int32_t* __restrict__ idx,
                                               float* __restrict__ mind, int64_t row0,
                                               int tile_bits, unsigned long long* nfb,
                                               const typename SC::elem* resident,
-                                              const BF (&xf)[SC::XT][SC::NS]) {
-  constexpr int XT = SC::XT;
+                                              const float (&xv)[SC::LP / 2], float xsq,
+                                              const Bound& bd, float ninf) {
   constexpr int LP = SC::LP;
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int j = lane & 31;
   const uint32_t lowmask = (1u << tile_bits) - 1u;
-  double dsum = 0.0;
 
-  Top2 tp[XT];
+  const Cand t = best_of<!SC::EXACT>(sl, lowmask, ninf, h);
+  const int64_t m = row0 + j;
+  const bool live = h == 1 && m < M;
+  bool flag = false;
+  double d = 0.0;
+  int win = t.i1;
+  const bool bad = (unsigned)win >= (unsigned)n;  // non-finite input
+  if (bad) win = 0;
+  if constexpr (SC::EXACT) {
+    float cr[LP / 2];
+    c_half<SC, VEC>(C, L, reinterpret_cast<const float*>(resident), win, h, cr);
+    double s0 = 0.0;
 #pragma unroll
-  for (int xt = 0; xt < XT; ++xt) tp[xt] = top2_of<XT>(sl, xt, lane, lowmask);
-
-  const double gam = (double)(L + 4) * 0x1p-24 / (1.0 - (double)(L + 4) * 0x1p-24);
-  const double keyslack = 1.0 + ldexp(1.0, tile_bits - 23);
-  const double dslack = 1.0 + 4.0 * (double)(L + 2) * 0x1p-53;
-
-#pragma unroll
-  for (int p = 0; p < (XT + 1) / 2; ++p) {
-    const int xt = 2 * p + h;
-    const bool have = xt < XT;
-    Top2 t = tp[0];
-#pragma unroll
-    for (int q = 1; q < XT; ++q)
-      if (xt == q) t = tp[q];
-    const int64_t m = row0 + xt * 32 + j;
-    const bool live = have && m < M;
-    bool flag = false;
-    double d = 0.0;
-    int win = 0;
-    float xr[LP];
-    if constexpr (SC::EXACT) {
-      // the row from the two half-waves' fragments: this lane's half, and the
-      // other half from lane (j, 1-h), which sends its half of the row this
-      // lane handles (xt = 2p + h)
-      const int sx = 2 * p + (1 - h);
-#pragma unroll
-      for (int s2 = 0; s2 < LP / 2; ++s2) {
-        float own = 0.0f, send = 0.0f;
-#pragma unroll
-        for (int q = 0; q < XT; ++q) {
-          if (q == xt) own = xf[q][s2];
-          if (q == sx) send = xf[q][s2];
-        }
-        const float recv = __shfl_xor(send, 32);
-        xr[s2] = h ? recv : own;
-        xr[LP / 2 + s2] = h ? own : recv;
+    for (int q = 0; q < LP / 2; ++q) {
+      if (q < L) {
+        const double u = (double)xv[q] - (double)cr[q];
+        s0 = s0 + u * u;
       }
     }
+    // lane (j, 1) continues from lane (j, 0)'s partial sum
+    const uint64_t b0 = (uint64_t)__double_as_longlong(s0);
+    float lo_a, hi_a, lo_b, hi_b;
+    pair_values(__uint_as_float((uint32_t)b0), lo_a, hi_a);
+    pair_values(__uint_as_float((uint32_t)(b0 >> 32)), lo_b, hi_b);
+    double s1 = __longlong_as_double(
+        (long long)(((uint64_t)__float_as_uint(lo_b) << 32) | __float_as_uint(lo_a)));
+#pragma unroll
+    for (int q = 0; q < LP / 2; ++q) {
+      if (LP / 2 + q < L) {
+        const double u = (double)xv[q] - (double)cr[q];
+        s1 = s1 + u * u;
+      }
+    }
+    d = s1;
     if (live) {
-      win = t.i1;
-      const bool bad = (unsigned)win >= (unsigned)n;  // non-finite input
-      if (bad) win = 0;
-      float cr[LP];
-      if constexpr (SC::EXACT) {
-        if (resident) {
-          const float* r = reinterpret_cast<const float*>(resident) + (int64_t)win * SC::S;
-#pragma unroll
-          for (int s4 = 0; s4 < LP; s4 += 4) {
-            const float4 q4 = *reinterpret_cast<const float4*>(r + s4);
-            cr[s4] = -0.5f * q4.x;
-            cr[s4 + 1] = -0.5f * q4.y;
-            cr[s4 + 2] = -0.5f * q4.z;
-            cr[s4 + 3] = -0.5f * q4.w;
-          }
-        } else {
-          load_row<LP, VEC>(C + (int64_t)win * L, L, cr);
-        }
-      } else {
-        load_row<LP, VEC>(X + m * (int64_t)L, L, xr);
-        load_row<LP, VEC>(C + (int64_t)win * L, L, cr);
-      }
-      d = d64_regs<LP>(xr, cr, L);
-      if constexpr (SC::EXACT) {
-        double xx = 0.0;
-#pragma unroll
-        for (int l = 0; l < LP; ++l) xx += (double)xr[l] * (double)xr[l];
-        const double r = 2.0 * sqrt(xx) + sqrt(d * dslack);
-        const double E = 2.0 * gam * (1.0 + 0x1p-24) * r * r + 1e-30;
-        const double lim = (double)t.k2 / keyslack - E;
-        flag = bad || !(d * dslack < lim);
-      } else {
-        const int i2 = t.i2;
-        if (i2 >= 0 && i2 < n && i2 != win) {
-          load_row<LP, VEC>(C + (int64_t)i2 * L, L, cr);
-          const double d2 = d64_regs<LP>(xr, cr, L);
-          if (d2 < d || (d2 == d && i2 < win)) {
-            d = d2;
-            win = i2;
-          }
-        }
-      }
+      const float rf = 2.0f * __builtin_sqrtf(xsq) + __builtin_sqrtf((float)d);
+      const double E = (double)(bd.cE * rf * rf) + 1e-30;
+      const double lim = (double)t.k2 * bd.invks - E;
+      flag = bad || !(d * bd.dslack < lim);
     }
-    if constexpr (SC::EXACT) {
-      unsigned long long fl = __ballot(flag);
-      if (nfb && lane == 0 && fl) atomicAdd(nfb, (unsigned long long)__popcll(fl));
-      while (fl) {
-        const int src = __ffsll((long long)fl) - 1;
-        fl &= fl - 1;
-        const int64_t mf = __shfl(m, src);
-        double best;
-        int bi;
-        search_row<SC, VEC>(X + mf * (int64_t)L, L, C, n, resident, lane, &best, &bi);
-        if (lane == src) {
-          d = best;
-          win = bi;
-        }
-      }
-    }
+  } else {
     if (live) {
-      idx[m] = win;
-      if (mind) mind[m] = (float)d;
+      const float* xrow = X + m * (int64_t)L;
+      d = d64_mem<LP, VEC>(xrow, C + (int64_t)win * L, L);
+      const int i2 = t.i2;
+      if (i2 >= 0 && i2 < n && i2 != win) {
+        const double d2 = d64_mem<LP, VEC>(xrow, C + (int64_t)i2 * L, L);
+        if (d2 < d || (d2 == d && i2 < win)) {
+          d = d2;
+          win = i2;
+        }
+      }
     }
-    if (live) dsum += d;
   }
-  return dsum;
+  if constexpr (SC::EXACT) {
+    unsigned long long fl = __ballot(flag);
+    if (nfb && lane == 0 && fl) atomicAdd(nfb, (unsigned long long)__popcll(fl));
+    while (fl) {
+      const int src = __ffsll((long long)fl) - 1;
+      fl &= fl - 1;
+      const int64_t mf = row0 + (src & 31);
+      double best;
+      int bi;
+      search_row<SC, VEC>(X + mf * (int64_t)L, L, C, n,
+                          reinterpret_cast<const float*>(resident), lane, &best, &bi);
+      if (lane == src) {
+        d = best;
+        win = bi;
+      }
+    }
+  }
+  if (live) {
+    idx[m] = win;
+    if (mind) mind[m] = (float)d;
+  }
+  return live ? d : 0.0;
 }
 
 // Fixed-order sum of the tile's ROWS distances into dpart[tile].
@@ -505,7 +678,7 @@ __device__ __forceinline__ void stage(const void* __restrict__ src, void* dst, i
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = base + u * kAssignThreads + threadIdx.x;
-      if (e < nv) v[u] = s[e];
+      v[u] = e < nv ? s[e] : make_uint4(0u, 0u, 0u, 0u);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -589,8 +762,137 @@ __device__ __forceinline__ void stage_from_C(const float* __restrict__ C, int n,
 }
 
 // -------------------------------------------------------------- kernel --
+// A-operand fragments of one tile of 32 codevectors for lane (j, h): the
+// K-step of the norms and the data K-steps.
+template <class SC>
+struct Frag;
+
+template <int LP>
+struct Frag<Fp32Screen<LP>> {
+  float an;
+  float a[LP / 2];
+  // row layout [-2c (LP), |c|^2, 1, 0, 0]: half h supplies K index h of the
+  // norm step ([|c|^2, 1] against [1, |x|^2]) and dimensions [h LP/2, ...)
+  __device__ __forceinline__ void load(const float* ar, int h) {
+    an = ar[LP + h];
+    const float* p = ar + h * (LP / 2);
+#pragma unroll
+    for (int s = 0; s < LP / 2; s += 4) {
+      const float4 q = *reinterpret_cast<const float4*>(p + s);
+      a[s] = q.x;
+      a[s + 1] = q.y;
+      a[s + 2] = q.z;
+      a[s + 3] = q.w;
+    }
+  }
+  __device__ __forceinline__ void mma(const float (&xf)[LP / 2], float xn, f16v& acc) const {
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(an, xn, f16v{}, 0, 0, 0);
+#pragma unroll
+    for (int s = 0; s < LP / 2; ++s)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], xf[s], acc, 0, 0, 0);
+  }
+};
+
+template <int LP>
+struct Frag<Bf16Screen<LP>> {
+  static constexpr int NS = LP / 16;
+  bf16x8 an;
+  bf16x8 a[NS];
+  // row layout [bf16(-2c) (LP), hi, mid, lo, 1, 1, 1, 0, 0]: half 0 supplies
+  // the norm step, half 1 zeros; dimensions [h LP/2, ...) in steps of 8
+  __device__ __forceinline__ void load(const __bf16* ar, int h) {
+    const bf16x8 pad = *reinterpret_cast<const bf16x8*>(ar + LP);
+    const __bf16 zero = (__bf16)0.0f;
+    const bf16x8 zv = {zero, zero, zero, zero, zero, zero, zero, zero};
+    an = h ? zv : pad;
+    const __bf16* p = ar + h * (LP / 2);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) a[s] = *reinterpret_cast<const bf16x8*>(p + 8 * s);
+  }
+  __device__ __forceinline__ void mma(const bf16x8 (&xf)[NS], const bf16x8& xn,
+                                      f16v& acc) const {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an, xn, f16v{}, 0, 0, 0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], xf[s], acc, 0, 0, 0);
+  }
+};
+
+// Screens nt tiles of 32 codevectors (row j of tile 0 at ar) against the
+// wave's vectors.  Software-pipelined: the matrix-core products of tile t+1
+// are issued before the key updates of tile t, so that the two overlap;
+// with small dimensions the A fragments are also loaded one tile ahead.
+template <class SC, class XF, class XN>
+__device__ __forceinline__ void screen_tiles(const typename SC::elem* ar, int nt, uint32_t tb0,
+                                             int h, const XF& xf, const XN& xn, Slots& sl,
+                                             uint32_t vmask, float ninf) {
+  constexpr int TS = 32 * SC::S;  // elements per tile
+  constexpr bool DB = SC::LP <= 32;
+  if constexpr (SC::LP >= 128) {  // long K: the products dominate, no pipelining
+    for (int t = 0; t < nt; ++t) {
+      Frag<SC> f;
+      f.load(ar + t * TS, h);
+      f16v c;
+      f.mma(xf, xn, c);
+      sl.push(c, vmask, tb0 + t, ninf);
+    }
+    return;
+  }
+  Frag<SC> fa, fb;
+  f16v ca, cb;
+  fa.load(ar, h);
+  fa.mma(xf, xn, ca);
+  if (DB && nt > 1) fb.load(ar + TS, h);
+  int t = 0;
+  for (; t + 2 < nt; t += 2) {
+    // ca: products of tile t; fb: fragments of tile t+1 (DB)
+    if (!DB) fb.load(ar + (t + 1) * TS, h);
+    fb.mma(xf, xn, cb);
+    fa.load(ar + (t + 2) * TS, h);
+    sl.push(ca, vmask, tb0 + t, ninf);
+    fa.mma(xf, xn, ca);
+    if (DB) fb.load(ar + min(t + 3, nt - 1) * TS, h);
+    sl.push(cb, vmask, tb0 + t + 1, ninf);
+  }
+  if (t + 1 < nt) {
+    if (!DB) fb.load(ar + (t + 1) * TS, h);
+    fb.mma(xf, xn, cb);
+    sl.push(ca, vmask, tb0 + t, ninf);
+    sl.push(cb, vmask, tb0 + t + 1, ninf);
+  } else {
+    sl.push(ca, vmask, tb0 + t, ninf);
+  }
+}
+
+// Half-row of the wave's training vector: lane (j, h) loads dimensions
+// [h LP/2, (h+1) LP/2) of vector row0 + j (zero beyond L or M).
+template <int LP, bool VEC>
+__device__ __forceinline__ void load_x(const float* __restrict__ X, int64_t M, int L,
+                                       int64_t row0, int h, int j, float (&v)[LP / 2]) {
+  const int64_t m = row0 + j;
+  if (m < M) {
+    const float* xr = X + m * (int64_t)L + h * (LP / 2);
+    if (VEC) {
+#pragma unroll
+      for (int s = 0; s < LP / 2; s += 4) {
+        const float4 q = *reinterpret_cast<const float4*>(xr + s);
+        v[s] = q.x;
+        v[s + 1] = q.y;
+        v[s + 2] = q.z;
+        v[s + 3] = q.w;
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < LP / 2; ++s) v[s] = (h * (LP / 2) + s < L) ? xr[s] : 0.0f;
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < LP / 2; ++s) v[s] = 0.0f;
+  }
+}
+
 template <class SC, bool VEC>
-__global__ __launch_bounds__(kAssignThreads, 2) void assign_kernel(
+__global__ __launch_bounds__(kAssignThreads, SC::OCC) void assign_kernel(
     const float* __restrict__ X, int64_t M, int L, const float* __restrict__ C, int n,
     const typename SC::elem* __restrict__ Cp, int n_pad, int CR, int32_t* __restrict__ idx,
     float* __restrict__ mind, double* __restrict__ dpart, unsigned long long* __restrict__ nfb,
@@ -603,11 +905,11 @@ __global__ __launch_bounds__(kAssignThreads, 2) void assign_kernel(
     n_pad = (n + 31) & ~31;
     tile_bits = tile_bits_of(n);
   }
-  constexpr int XT = SC::XT;
   constexpr int LP = SC::LP;
   constexpr int S = SC::S;
   constexpr int NS = SC::NS;
-  constexpr int ROWS = rows_per_tile<SC>();
+  constexpr bool PF = LP <= 32;  // prefetch the next row tile's vectors
+  if (VEC) L = LP;  // vector loads only for rows of exactly LP floats
   typedef typename SC::elem E;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   E* sA = reinterpret_cast<E*>(smem);
@@ -616,75 +918,68 @@ __global__ __launch_bounds__(kAssignThreads, 2) void assign_kernel(
   const int wave = threadIdx.x >> 6;
   const int h = lane >> 5;
   const int j = lane & 31;
-  const int64_t ntiles_rows = (M + ROWS - 1) / ROWS;
+  const int64_t ntiles_rows = (M + kRowsPerTile - 1) / kRowsPerTile;
   const bool resident = CR >= n_pad;
-  // key mask in a VGPR, so that the and-or reads a single SGPR (tile bits)
+  // key mask and -inf in VGPRs the compiler cannot see through
   uint32_t vmask = ~((1u << tile_bits) - 1u);
   asm volatile("v_mov_b32 %0, %1" : "=v"(vmask) : "v"(vmask));
-  const float ninf = -INFINITY;
+  float ninf = -INFINITY;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(ninf) : "v"(ninf));
+  const Bound bd = bound_of(L, tile_bits);
 
+  float xv[LP / 2];
+  int64_t rt = blockIdx.x;
+  if (PF && rt < ntiles_rows)
+    load_x<LP, VEC>(X, M, L, rt * kRowsPerTile + (int64_t)wave * 32, h, j, xv);
   if (resident) stage_from_C<SC, VEC>(C, n, L, n_pad, sA);
 
   double wsum = 0.0;
-  for (int64_t rt = blockIdx.x; rt < ntiles_rows; rt += gridDim.x) {
-    const int64_t row0 = rt * ROWS + (int64_t)wave * 32 * XT;
+  for (; rt < ntiles_rows; rt += gridDim.x) {
+    const int64_t row0 = rt * kRowsPerTile + (int64_t)wave * 32;
+    if (!PF) load_x<LP, VEC>(X, M, L, row0, h, j, xv);
 
-    // Training-vector fragments: lane (j, h) keeps dims [h*LP/2, (h+1)*LP/2)
-    // of vector j of each of its tiles, as the B operand of the K-steps.
+    // B operand: lane (j, h) keeps dims [h*LP/2, (h+1)*LP/2) of vector j and
+    // the norm step's [1, |x|^2] (FP32) or [1, 1, 1, hi, mid, lo, 0, 0] /
+    // zeros (BF16).
     typedef typename std::conditional<SC::EXACT, float, bf16x8>::type BF;
-    BF xf[XT][NS];
-    BF xn[XT];
+    BF xf[NS];
+    BF xn;
+    double ss = 0.0;
+    if constexpr (SC::EXACT) {
 #pragma unroll
-    for (int xt = 0; xt < XT; ++xt) {
-      const int64_t m = row0 + xt * 32 + j;
-      float v[LP / 2];
-      if (m < M) {
-        const float* xr = X + m * (int64_t)L + h * (LP / 2);
-        if (VEC) {
-#pragma unroll
-          for (int s = 0; s < LP / 2; s += 4) {
-            const float4 q = *reinterpret_cast<const float4*>(xr + s);
-            v[s] = q.x;
-            v[s + 1] = q.y;
-            v[s + 2] = q.z;
-            v[s + 3] = q.w;
-          }
-        } else {
-#pragma unroll
-          for (int s = 0; s < LP / 2; ++s) v[s] = (h * (LP / 2) + s < L) ? xr[s] : 0.0f;
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < LP / 2; ++s) v[s] = 0.0f;
+      for (int s = 0; s < LP / 2; ++s) {
+        xf[s] = xv[s];
+        ss += (double)xv[s] * (double)xv[s];
       }
-      double ss = 0.0;
-      if constexpr (SC::EXACT) {
+      ss += xor_lane<32>(ss);
+      xn = h ? (float)ss : 1.0f;
+    } else {
 #pragma unroll
-        for (int s = 0; s < LP / 2; ++s) {
-          xf[xt][s] = v[s];
-          ss += (double)v[s] * (double)v[s];
-        }
-        ss += __shfl_xor(ss, 32);
-        xn[xt] = h ? (float)ss : 1.0f;
-      } else {
-#pragma unroll
-        for (int s = 0; s < LP / 2; ++s) {
-          const __bf16 b = (__bf16)v[s];
-          xf[xt][s >> 3][s & 7] = b;
-          const double r = (double)(float)b;
-          ss += r * r;
-        }
-        ss += __shfl_xor(ss, 32);
-        __bf16 hi, mid, lo;
-        split3((float)ss, hi, mid, lo);
-        const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
-        const bf16x8 nv = {one, one, one, hi, mid, lo, zero, zero};
-        const bf16x8 zv = {zero, zero, zero, zero, zero, zero, zero, zero};
-        xn[xt] = h ? zv : nv;
+      for (int s = 0; s < LP / 2; ++s) {
+        const __bf16 b = (__bf16)xv[s];
+        xf[s >> 3][s & 7] = b;
+        const double r = (double)(float)b;
+        ss += r * r;
       }
+      ss += xor_lane<32>(ss);
+      __bf16 hi, mid, lo;
+      split3((float)ss, hi, mid, lo);
+      const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
+      const bf16x8 nv = {one, one, one, hi, mid, lo, zero, zero};
+      const bf16x8 zv = {zero, zero, zero, zero, zero, zero, zero, zero};
+      xn = h ? zv : nv;
     }
+    const float xsq = (float)ss;
+    // the FP32 rescore needs this tile's vectors after the screen
+    float xk[LP / 2];
+    if constexpr (SC::EXACT) {
+#pragma unroll
+      for (int s = 0; s < LP / 2; ++s) xk[s] = xv[s];
+    }
+    if (PF && rt + gridDim.x < ntiles_rows)
+      load_x<LP, VEC>(X, M, L, row0 + (int64_t)gridDim.x * kRowsPerTile, h, j, xv);
 
-    Slots<XT> sl;
+    Slots sl;
     sl.init();
     for (int c0 = 0; c0 < n_pad; c0 += CR) {
       const int cr = min(CR, n_pad - c0);
@@ -694,56 +989,15 @@ __global__ __launch_bounds__(kAssignThreads, 2) void assign_kernel(
         __syncthreads();
       }
       const E* base = resident ? sA + (int64_t)c0 * S : sA;
-      const int nt = cr >> 5;
-      for (int t = 0; t < nt; ++t) {
-        const E* ar = base + (t * 32 + j) * S;
-        f16v acc[XT];
-        if constexpr (SC::EXACT) {
-          const float an = h ? 1.0f : ar[LP];
-#pragma unroll
-          for (int xt = 0; xt < XT; ++xt)
-            acc[xt] = __builtin_amdgcn_mfma_f32_32x32x2f32(an, xn[xt], f16v{}, 0, 0, 0);
-          const float* a = ar + h * (LP / 2);
-#pragma unroll
-          for (int s = 0; s < NS; s += 4) {
-            const float4 a4 = *reinterpret_cast<const float4*>(a + s);
-#pragma unroll
-            for (int xt = 0; xt < XT; ++xt) {
-              acc[xt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, xf[xt][s], acc[xt], 0, 0, 0);
-              acc[xt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, xf[xt][s + 1], acc[xt], 0, 0, 0);
-              acc[xt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, xf[xt][s + 2], acc[xt], 0, 0, 0);
-              acc[xt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, xf[xt][s + 3], acc[xt], 0, 0, 0);
-            }
-          }
-        } else {
-          const __bf16 zero = (__bf16)0.0f;
-          const bf16x8 zv = {zero, zero, zero, zero, zero, zero, zero, zero};
-          const bf16x8 an = h ? zv : *reinterpret_cast<const bf16x8*>(ar + LP);
-#pragma unroll
-          for (int xt = 0; xt < XT; ++xt)
-            acc[xt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an, xn[xt], f16v{}, 0, 0, 0);
-          const __bf16* a = ar + h * (LP / 2);
-#pragma unroll
-          for (int s = 0; s < NS; ++s) {
-            const bf16x8 a8 = *reinterpret_cast<const bf16x8*>(a + 8 * s);
-#pragma unroll
-            for (int xt = 0; xt < XT; ++xt)
-              acc[xt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, xf[xt][s], acc[xt], 0, 0, 0);
-          }
-        }
-        const uint32_t tb = (uint32_t)((c0 >> 5) + t);
-#pragma unroll
-        for (int xt = 0; xt < XT; ++xt) sl.push(xt, acc[xt], vmask, tb, ninf);
-      }
+      screen_tiles<SC>(base + j * S, cr >> 5, (uint32_t)(c0 >> 5), h, xf, xn, sl, vmask, ninf);
     }
 
-    wsum += finish_rows<SC, VEC, BF>(sl, X, M, L, C, n, idx, mind, row0, tile_bits, nfb,
-                                     resident ? sA : nullptr, xf);
+    wsum += finish_rows<SC, VEC>(sl, X, M, L, C, n, idx, mind, row0, tile_bits, nfb,
+                                 resident ? sA : nullptr, xk, xsq, bd, ninf);
   }
   // per-wave partial of the distortion over the block's row tiles (in order),
   // lanes added by a fixed butterfly
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) wsum += __shfl_xor(wsum, off);
+  wsum = wave_sum(wsum);
   if (dpart && lane == 0) dpart[blockIdx.x * 4 + wave] = wsum;
 }
 
@@ -764,11 +1018,10 @@ int launch_screen(const float* X, int64_t M, int L, const float* C, int n, int32
                        st, cbp);
     LBG_TRY_HIP(hipGetLastError());
   }
-  constexpr int ROWS = rows_per_tile<SC>();
-  const int64_t tiles = (M + ROWS - 1) / ROWS;
-  // Persistent grid of two workgroups per CU: a resident codebook is staged
+  const int64_t tiles = (M + kRowsPerTile - 1) / kRowsPerTile;
+  // Persistent grid of OCC workgroups per CU: a resident codebook is staged
   // once per workgroup, a chunked one per row tile.
-  const int64_t grid = std::min<int64_t>(tiles, kPersistBlocks);
+  const int64_t grid = std::min<int64_t>(tiles, persist_blocks<SC>());
   const size_t lds = (size_t)CR * SC::S * SC::ESZ;
   const int tb = tile_bits_for(n);
   bool vec = (L == SC::LP) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
