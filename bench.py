@@ -29,6 +29,13 @@ import numpy as np
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+# Sources of the allocation kernel: counters taken on an older build of them
+# are not reported.
+ASSIGN_SOURCES = ("paper_0910_4711_amd/csrc/assign_common.h",
+                  "paper_0910_4711_amd/csrc/assign.hip")
+TRAFFIC_FILE = "profiles/assign_fp32_img16x512x512_b4_traffic.txt"
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -39,6 +46,53 @@ def workload():
     cfg = synth.CONFIG1
     X = synth.image_training_set(cfg["seeds"], cfg["W"], cfg["H"], cfg["b"])
     return cfg, X
+
+
+def assign_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ASSIGN_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per allocation launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
+    reading for a plain copy of known size), or None when the summary is
+    missing or was taken on other kernel sources."""
+    path = os.path.join(HERE, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != assign_source_hash():
+        return None
+    try:
+        return dict(bytes=float(kv["traffic_bytes_per_launch"]),
+                    fetch=float(kv["fetch_bytes_per_launch"]),
+                    write=float(kv["write_bytes_per_launch"]),
+                    algorithmic=float(kv["algorithmic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib):
+    """A plain device copy of known size, for scaling the HBM counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
 
 
 def cpu_baseline(X, N, images):
@@ -67,7 +121,12 @@ def main():
     ap.add_argument("--cpu-images", type=int, default=16,
                     help="images of the workload the CPU oracle baseline runs on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, metavar="MIB", default=0,
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py: this benchmark runs on exactly one GPU; --gpus {args.gpus} "
               "is not supported (the library has no multi-GPU path)", file=sys.stderr)
@@ -115,6 +174,7 @@ def main():
     log(f"timed {args.steps} steps in {elapsed:.4f} s")
 
     D, st = last
+    traffic = measured_traffic()
     flops = 2.0 * L * tot["dist"]  # 2L flops per vector-codeword distance
     assign_s = tot["ms_assign"] / 1e3
     achieved_tf = flops / assign_s / 1e12
@@ -146,8 +206,10 @@ def main():
             "peak": PEAK_FP32_MFMA_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tf / PEAK_FP32_MFMA_TFLOPS,
-            "traffic": None,
-            "kernel": "allocation (assign_fp32_kernel<16,2>)",
+            "traffic": traffic["bytes"] if traffic else None,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                            "copy-calibrated)",
+            "kernel": "allocation: assign_kernel<Fp32Screen<16>, vector loads>",
             "launches": tot["assigns"],
             "avg_launch_us": tot["ms_assign"] / tot["assigns"] * 1e3,
             "flops_per_launch_avg": flops / tot["assigns"],

@@ -915,7 +915,7 @@ __global__ __launch_bounds__(kAssignThreads, SC::OCC) void assign_kernel(
   E* sA = reinterpret_cast<E*>(smem);
 
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (SGPR)
   const int h = lane >> 5;
   const int j = lane & 31;
   const int64_t ntiles_rows = (M + kRowsPerTile - 1) / kRowsPerTile;

@@ -80,14 +80,24 @@ int enqueue_piece(const Batch& b, int piece, hipStream_t s) {
                     ctl, cbp);
 }
 
-// kBatchIters iterations launched directly; ev (nullable) brackets the
-// allocation and the update of every iteration.
+// Timing events of iteration i (nullable): ev[i][0][0] before the
+// allocation, ev[i][0][1] between the allocation and the update, ev[i][1][1]
+// after the update (three records per iteration).
+inline hipEvent_t event_before(hipEvent_t (*ev)[3][2], int i, int piece) {
+  return piece == 0 ? ev[i][0][0] : nullptr;
+}
+inline hipEvent_t event_after(hipEvent_t (*ev)[3][2], int i, int piece) {
+  return piece == 0 ? ev[i][0][1] : ev[i][1][1];
+}
+
+// kBatchIters iterations launched directly.
 int enqueue_batch(const Batch& b, hipStream_t s, hipEvent_t (*ev)[3][2]) {
   for (int i = 0; i < kBatchIters; ++i)
     for (int piece = 0; piece < kPieces; ++piece) {
-      if (ev) LBG_TRY_HIP(hipEventRecord(ev[i][piece][0], s));
+      if (ev && event_before(ev, i, piece))
+        LBG_TRY_HIP(hipEventRecord(event_before(ev, i, piece), s));
       LBG_TRY(enqueue_piece(b, piece, s));
-      if (ev) LBG_TRY_HIP(hipEventRecord(ev[i][piece][1], s));
+      if (ev) LBG_TRY_HIP(hipEventRecord(event_after(ev, i, piece), s));
     }
   return LBG_OK;
 }
@@ -124,9 +134,9 @@ int build_batch_graph(const Batch& b, hipStream_t s, hipEvent_t (*ev)[3][2], hip
     for (int piece = 0; piece < kPieces && rc == LBG_OK; ++piece) {
       hipGraphNode_t node;
       hipError_t e;
-      if (ev) {
+      if (ev && event_before(ev, i, piece)) {
         e = hipGraphAddEventRecordNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0,
-                                       ev[i][piece][0]);
+                                       event_before(ev, i, piece));
         if (e != hipSuccess) { rc = hip_fail(e, "hipGraphAddEventRecordNode"); break; }
         prev = node;
       }
@@ -134,7 +144,7 @@ int build_batch_graph(const Batch& b, hipStream_t s, hipEvent_t (*ev)[3][2], hip
       if (e != hipSuccess) { rc = hip_fail(e, "hipGraphAddChildGraphNode"); break; }
       prev = node;
       if (ev) {
-        e = hipGraphAddEventRecordNode(&node, g, &prev, 1, ev[i][piece][1]);
+        e = hipGraphAddEventRecordNode(&node, g, &prev, 1, event_after(ev, i, piece));
         if (e != hipSuccess) { rc = hip_fail(e, "hipGraphAddEventRecordNode"); break; }
         prev = node;
       }
@@ -316,7 +326,7 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
         float t = 0.0f;
         if (hipEventElapsedTime(&t, ev[i][0][0], ev[i][0][1]) == hipSuccess) ms[0] += t;
         const int act = a < kTraceCap ? acts[a] : kActNone;
-        if (act == kActUpdate && hipEventElapsedTime(&t, ev[i][1][0], ev[i][1][1]) == hipSuccess)
+        if (act == kActUpdate && hipEventElapsedTime(&t, ev[i][0][1], ev[i][1][1]) == hipSuccess)
           ms[1] += t;
       }
     }
