@@ -212,6 +212,81 @@ int lbg_train(const float* X, int64_t M, int64_t L, int64_t N,
               double* D_out, lbg_stats* st, void* ws, size_t ws_bytes,
               void* stream);
 
+/* ------------------------------------------------------------ batched --
+ * Many independent LBG runs (Algorithm 1 on each instance) advanced together:
+ * every round performs one Lloyd iteration of every unfinished instance with
+ * one persistent allocation launch, one accumulation launch and one update
+ * launch for all of them.  Each instance's codebook, allocation, distortion,
+ * level and iteration counts are bit-identical to lbg_train on that
+ * instance alone with the same parameters.
+ */
+typedef struct lbg_instance {
+  const float* X;    /* DEVICE, M x L FP32 row-major; 16-byte aligned for
+                        vector loads (4-byte aligned at least) */
+  int64_t M;         /* 1 <= M <= LBG_MAX_M */
+  int64_t L;         /* 1 <= L <= 64 */
+  int64_t N;         /* power of two; the N x L codebook must fit the
+                        allocation's LDS (N <= 1024 at L <= 16, N <= 256 at
+                        L <= 64) */
+  float* C_out;      /* DEVICE, N x L: the final codebook */
+  int32_t* idx_out;  /* DEVICE, M: its allocation */
+} lbg_instance;
+
+/* Launch configuration of the batched form.  grab: allocation items (one
+ * item = one instance's share of one workgroup of the single-run kernel) a
+ * workgroup takes per queue access; grid: workgroups of the persistent
+ * allocation launch.  0 selects them by the autotuner, which times the
+ * candidates on the instances' final codebook sizes once per workload
+ * signature (instance count, sum of M, sum of M*N*L, sum of N) and caches
+ * the result for the process.  graph != 0 (default) replays rounds from a
+ * hipGraph (non-NULL streams), else launches them directly;
+ * rounds_per_poll: rounds between host checks of the finished count
+ * (direct launches). */
+typedef struct lbg_batch_config {
+  int32_t grab;
+  int32_t grid;
+  int32_t graph;
+  int32_t rounds_per_poll;
+} lbg_batch_config;
+
+void lbg_batch_config_default(lbg_batch_config* cfg);
+
+/* Per-instance outcome (HOST). */
+typedef struct lbg_batch_result {
+  double D;               /* distortion of the final allocation */
+  int32_t status;         /* LBG_OK or LBG_WMAXITER */
+  int32_t n_levels;
+  int32_t n_assign;       /* allocations performed */
+  int32_t n_update;       /* updates performed */
+  int64_t fallback_rows;  /* rows searched again exhaustively */
+} lbg_batch_result;
+
+typedef struct lbg_batch_stats {
+  int32_t rounds;   /* rounds launched (multiple of the poll interval) */
+  int32_t grab;     /* configuration used */
+  int32_t grid;
+  int32_t graph;
+  int32_t tuned;    /* 1 if this call ran the autotuner */
+  int64_t total_distances;  /* sum over instances of sum M * n */
+  double ms_tune;   /* time spent timing candidates */
+} lbg_batch_stats;
+
+/* Workspace bytes for lbg_train_batched on these instances (0 on bad
+ * arguments). */
+size_t lbg_train_batched_workspace(const lbg_instance* inst, int32_t n_inst);
+
+/*
+ * Train every instance (HOST array inst[n_inst]) as lbg_train would, with
+ * the shared parameters p (precision LBG_FP32; C_init and forced_iters are
+ * not supported).  res (HOST, nullable) receives one lbg_batch_result per
+ * instance, st (HOST, nullable) the statistics.  Returns LBG_OK,
+ * LBG_WMAXITER if any instance hit the cap, or an error code (nothing is
+ * trained then).  Synchronises ``stream``.
+ */
+int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const lbg_params* p,
+                      const lbg_batch_config* cfg, lbg_batch_result* res,
+                      lbg_batch_stats* st, void* ws, size_t ws_bytes, void* stream);
+
 /* Bytes of workspace the operation ``op`` (LBG_OP_*) needs. */
 size_t lbg_workspace_size(int op, int64_t M, int64_t L, int64_t N,
                           int precision);

@@ -80,6 +80,49 @@ class Stats(ct.Structure):
     ]
 
 
+class Instance(ct.Structure):
+    _fields_ = [
+        ("X", ct.c_void_p),
+        ("M", ct.c_int64),
+        ("L", ct.c_int64),
+        ("N", ct.c_int64),
+        ("C_out", ct.c_void_p),
+        ("idx_out", ct.c_void_p),
+    ]
+
+
+class BatchConfig(ct.Structure):
+    _fields_ = [
+        ("grab", ct.c_int32),
+        ("grid", ct.c_int32),
+        ("graph", ct.c_int32),
+        ("rounds_per_poll", ct.c_int32),
+    ]
+
+
+class BatchResult(ct.Structure):
+    _fields_ = [
+        ("D", ct.c_double),
+        ("status", ct.c_int32),
+        ("n_levels", ct.c_int32),
+        ("n_assign", ct.c_int32),
+        ("n_update", ct.c_int32),
+        ("fallback_rows", ct.c_int64),
+    ]
+
+
+class BatchStats(ct.Structure):
+    _fields_ = [
+        ("rounds", ct.c_int32),
+        ("grab", ct.c_int32),
+        ("grid", ct.c_int32),
+        ("graph", ct.c_int32),
+        ("tuned", ct.c_int32),
+        ("total_distances", ct.c_int64),
+        ("ms_tune", ct.c_double),
+    ]
+
+
 def library_path() -> str:
     return _LIB_PATH
 
@@ -105,6 +148,9 @@ def load():
             "lbg_distortion_backward": [vp, i64, i64, vp, i64, vp, dbl, vp, vp, vp, sz, vp],
             "lbg_train": [vp, i64, i64, i64, ct.POINTER(Params), vp, vp,
                           ct.POINTER(ct.c_double), ct.POINTER(Stats), vp, sz, vp],
+            "lbg_train_batched": [ct.POINTER(Instance), i32, ct.POINTER(Params),
+                                  ct.POINTER(BatchConfig), ct.POINTER(BatchResult),
+                                  ct.POINTER(BatchStats), vp, sz, vp],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -118,6 +164,10 @@ def load():
         lib.lbg_version.restype = ct.c_char_p
         lib.lbg_params_default.argtypes = [ct.POINTER(Params)]
         lib.lbg_params_default.restype = None
+        lib.lbg_batch_config_default.argtypes = [ct.POINTER(BatchConfig)]
+        lib.lbg_batch_config_default.restype = None
+        lib.lbg_train_batched_workspace.argtypes = [ct.POINTER(Instance), i32]
+        lib.lbg_train_batched_workspace.restype = ct.c_size_t
         _lib = lib
         return lib
 
@@ -313,6 +363,60 @@ def train(X, N, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta=0.0,
         ms_split=st.ms_split,
     )
     return C, idx, D.value, stats
+
+
+def train_batched(Xs, Ns, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta=0.0,
+                  max_iter=1000, fixed_iters=0, grab=0, grid=0, graph=True,
+                  rounds_per_poll=8, workspace=None):
+    """Independent LBG runs (Algorithm 1 on every instance) advanced together
+    by the batched kernels.  Xs: list of [M_i x L_i] float32 device tensors,
+    Ns: list of powers of two.  Returns (results, stats): results[i] =
+    (C_i, idx_i, D_i, info_i), each bit-identical to train(Xs[i], Ns[i])."""
+    if len(Xs) != len(Ns) or len(Xs) == 0:
+        raise ValueError("need as many codebook sizes as training sets (at least one)")
+    Xs = [_f32_2d(f"Xs[{i}]", X) for i, X in enumerate(Xs)]
+    dev = Xs[0].device
+    if any(X.device != dev for X in Xs):
+        raise ValueError("all training sets must be on one device")
+    lib = load()
+    n = len(Xs)
+    inst = (Instance * n)()
+    outs = []
+    for i, (X, N) in enumerate(zip(Xs, Ns)):
+        M, L = X.shape
+        C = torch.empty((int(N), L), dtype=torch.float32, device=dev)
+        idx = torch.empty(M, dtype=torch.int32, device=dev)
+        inst[i].X, inst[i].M, inst[i].L, inst[i].N = X.data_ptr(), M, L, int(N)
+        inst[i].C_out, inst[i].idx_out = C.data_ptr(), idx.data_ptr()
+        outs.append((C, idx))
+    p = Params()
+    lib.lbg_params_default(ct.byref(p))
+    p.thr, p.eps_split, p.delta = float(thr), float(eps_split), float(delta)
+    p.split_mode, p.max_iter, p.fixed_iters = int(split_mode), int(max_iter), int(fixed_iters)
+    cfg = BatchConfig()
+    lib.lbg_batch_config_default(ct.byref(cfg))
+    cfg.grab, cfg.grid, cfg.graph = int(grab), int(grid), 1 if graph else 0
+    cfg.rounds_per_poll = int(rounds_per_poll)
+    nb = lib.lbg_train_batched_workspace(inst, n)
+    if nb == 0:
+        raise LBGError("lbg_train_batched_workspace: bad instances")
+    ws = workspace
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    res = (BatchResult * n)()
+    st = BatchStats()
+    rc = lib.lbg_train_batched(inst, n, ct.byref(p), ct.byref(cfg), res, ct.byref(st), _ptr(ws),
+                               nb, _stream(dev))
+    _check(rc, "lbg_train_batched")
+    results = []
+    for i, (C, idx) in enumerate(outs):
+        r = res[i]
+        results.append((C, idx, r.D, dict(status=r.status, n_levels=r.n_levels,
+                                          n_assign=r.n_assign, n_update=r.n_update,
+                                          fallback_rows=r.fallback_rows)))
+    stats = dict(status=rc, rounds=st.rounds, grab=st.grab, grid=st.grid, graph=st.graph,
+                 tuned=st.tuned, total_distances=st.total_distances, ms_tune=st.ms_tune)
+    return results, stats
 
 
 class Distortion(torch.autograd.Function):

@@ -1,0 +1,322 @@
+// Device bodies of the fixed-point Codebook Updation, shared by the
+// single-run kernels (update_afp.hip) and the batched kernels (batched.hip).
+// See update_afp.hip for the method.
+#pragma once
+
+#include <algorithm>
+
+#include "control.h"
+#include "lbg_internal.h"
+#include "misc_common.h"
+
+namespace lbg {
+namespace afp {
+
+constexpr int kT = 256;
+constexpr int kLdsBytes = 61440;
+constexpr int kUnroll = 8;  // rows in flight per group
+
+__device__ __forceinline__ void absmax_body(const float* __restrict__ X, int64_t n,
+                                            uint32_t* __restrict__ part, int64_t block,
+                                            int64_t nblocks) {
+  __shared__ uint32_t s[kT];
+  uint32_t m = 0;
+  for (int64_t i = block * kT + threadIdx.x; i < n; i += nblocks * kT) {
+    const uint32_t b = __float_as_uint(X[i]) & 0x7fffffffu;
+    m = (b > m && b < 0x7f800000u) ? b : m;  // ignore Inf / NaN
+  }
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = kT / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[block] = s[0];
+}
+
+__device__ __forceinline__ void shift_body(const uint32_t* __restrict__ part, int nparts,
+                                           int64_t M, int* __restrict__ shift) {
+  __shared__ uint32_t s[kT];
+  uint32_t m = 0;
+  for (int i = threadIdx.x; i < nparts; i += kT) m = max(m, part[i]);
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = kT / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int b = 0;
+    while (b < 63 && ((int64_t)1 << b) <= M) ++b;  // M < 2^b
+    const float mx = __uint_as_float(s[0]);
+    int e = 0;
+    if (mx > 0.0f) frexpf(mx, &e);  // mx < 2^e
+    *shift = (s[0] == 0) ? 0 : (61 - e - b);
+  }
+}
+
+
+__device__ __forceinline__ unsigned long long fixed(float v, int s) {
+  return (unsigned long long)llrint(ldexp((double)v, s));
+}
+
+// Row layout of the accumulation: a row is handled by G lanes; lane gl
+// covers dimensions (gl + q*G)*VW + v for v < VW (VW = 4: float4 loads) and
+// q < DPL.
+template <int VW>
+struct VLoad;
+template <>
+struct VLoad<4> {
+  static __device__ __forceinline__ void get(const float* p, float* v) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+  }
+};
+template <>
+struct VLoad<1> {
+  static __device__ __forceinline__ void get(const float* p, float* v) { v[0] = *p; }
+};
+
+template <int G, int VW, int DPL>
+__device__ __forceinline__ void add_row(unsigned long long* sacc, int32_t* scnt, const float* xrow,
+                                        int kk, int L, int gl, int s, const float (&v)[DPL][VW]) {
+#pragma unroll
+  for (int q = 0; q < DPL; ++q)
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      const int d = (gl + q * G) * VW + e;
+      if (d < L) atomicAdd(&sacc[kk * L + d], fixed(v[q][e], s));
+    }
+  if (gl == 0) atomicAdd(&scnt[kk], 1);
+}
+
+template <int G, int VW, int DPL>
+__device__ __forceinline__ void load_dims(const float* xrow, int L, int gl, bool on,
+                                          float (&v)[DPL][VW]) {
+#pragma unroll
+  for (int q = 0; q < DPL; ++q) {
+    const int d0 = (gl + q * G) * VW;
+    if (on && d0 < L) {
+      VLoad<VW>::get(xrow + d0, v[q]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < VW; ++e) v[q][e] = 0.0f;
+    }
+  }
+}
+
+
+// One block per (row chunk, cell slice), slices of one chunk adjacent.  Rows
+// stream in batches of kBatch.  With one slice every row is added: a group
+// of G lanes walks a contiguous sub-range of the batch, kUnroll rows (cell
+// index and coordinates) loaded together.  With several slices the batch's
+// cell indices are read first and the rows of this slice are gathered into
+// an LDS list (integer sums make the list order immaterial), then added.
+constexpr int kBatch = 1024;
+
+// Decision of this iteration from the allocation's partials (the same in every
+// block that calls it); the block with ``lead`` records the next state in
+// ctl.pend.  Returns true when this iteration updates; *N receives the
+// codebook size.
+__device__ __forceinline__ bool acc_decide(const Ctl& ctl, bool lead, int* N) {
+  __shared__ double red[kT];
+  __shared__ int s_act;
+  const DevState* st = ctl.st;
+  if (st->done) return false;
+  const double D = block_distortion(ctl.dpart, ctl.nparts, st->M, red);
+  if (threadIdx.x == 0) {
+    const Step r = step_of(st, D);
+    s_act = r.action;
+    if (lead) {
+      *ctl.pend = *st;
+      apply_step(st, ctl.pend, D, r, ctl.Dtrace, ctl.Atrace);
+    }
+  }
+  __syncthreads();
+  *N = st->n;
+  return s_act == kActUpdate;
+}
+
+// Accumulation of block ``blk`` = (row chunk, cell slice) of the update;
+// slist (kBatch entries) and snsel are the caller's LDS.
+template <int G, int VW, int DPL>
+__device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M, int L,
+                                         const int32_t* __restrict__ idx, int N, int cps,
+                                         int nslices, int64_t rows_per_chunk, int s,
+                                         unsigned long long* __restrict__ part,
+                                         int32_t* __restrict__ pcnt, int64_t blk,
+                                         unsigned long long* sacc, int32_t* slist,
+                                         int32_t& snsel) {
+  const int chunk = (int)(blk / nslices), slice = (int)(blk % nslices);
+  const int k0 = slice * cps, k1 = min(N, k0 + cps), nk = max(0, k1 - k0);
+  int32_t* scnt = reinterpret_cast<int32_t*>(sacc + (size_t)cps * L);
+  const int t = threadIdx.x;
+  for (int e = t; e < nk * L; e += kT) sacc[e] = 0ull;
+  for (int e = t; e < nk; e += kT) scnt[e] = 0;
+  if (t == 0) snsel = 0;
+  __syncthreads();
+  constexpr int NG = kT / G;  // rows in parallel
+  const int g = t / G, gl = t % G;
+  const int64_t r0 = (int64_t)chunk * rows_per_chunk;
+  const int64_t r1 = min(M, r0 + rows_per_chunk);
+  for (int64_t b0 = r0; b0 < r1; b0 += kBatch) {
+    const int nb = (int)min((int64_t)kBatch, r1 - b0);
+    if (nslices == 1) {
+      constexpr int PER = kBatch / NG;  // rows of one group per batch
+      const int64_t gb = b0 + (int64_t)g * PER;
+      for (int i0 = 0; i0 < PER; i0 += kUnroll) {
+        int k[kUnroll];
+        float v[kUnroll][DPL][VW];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int64_t m = gb + i0 + u;
+          const bool on = (i0 + u < PER) && (g * PER + i0 + u < nb);
+          k[u] = on ? idx[m] : -1;
+          load_dims<G, VW, DPL>(X + m * L, L, gl, on, v[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          if (k[u] >= k0 && k[u] < k1)
+            add_row<G, VW, DPL>(sacc, scnt, nullptr, k[u] - k0, L, gl, s, v[u]);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kBatch / kT; ++u) {
+        const int r = u * kT + t;
+        if (r < nb) {
+          const int k = idx[b0 + r];
+          if (k >= k0 && k < k1) slist[atomicAdd(&snsel, 1)] = r * 8192 + (k - k0);
+        }
+      }
+      __syncthreads();
+      const int nsel = snsel;
+      for (int e0 = g; e0 < nsel; e0 += NG * kUnroll) {
+        int kk[kUnroll];
+        float v[kUnroll][DPL][VW];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int e = e0 + u * NG;
+          const int packed = (e < nsel) ? slist[e] : -1;
+          const int r = packed >= 0 ? packed >> 13 : 0;
+          kk[u] = packed >= 0 ? (packed & 8191) : -1;
+          load_dims<G, VW, DPL>(X + (b0 + r) * L, L, gl, packed >= 0, v[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          if (kk[u] >= 0) add_row<G, VW, DPL>(sacc, scnt, nullptr, kk[u], L, gl, s, v[u]);
+      }
+      __syncthreads();
+      if (t == 0) snsel = 0;
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  unsigned long long* dst = part + ((int64_t)chunk * N + k0) * L;
+  for (int e = t; e < nk * L; e += kT) dst[e] = sacc[e];
+  int32_t* cdst = pcnt + (int64_t)chunk * N + k0;
+  for (int e = t; e < nk; e += kT) cdst[e] = scnt[e];
+}
+
+
+// One block per cell: thread (q, d) adds the partials of chunks q, q+Q, ...
+// (integers, so the order is immaterial), then the Q lane sums.
+// One block per cell: thread (q, d) adds the partials of chunks q, q+Q, ...
+// (integers, so the order is immaterial), then the Q lane sums.
+// Under device control: acts on the pending state for cell ``k`` (a split
+// of codevector k, or nothing); the block with ``lead`` commits the state.
+// Returns true when cell k is to be updated, with N, C_old and out set.
+// ``ndone`` (nullable) counts runs that finish with this commit.
+__device__ __forceinline__ bool fin_state(const Ctl& ctl, const CbPair& cbp, int64_t k, bool lead,
+                                          int L, int* N, const float** C_old, float** out,
+                                          unsigned* ndone = nullptr) {
+  if (ctl.st->done) return false;
+  const DevState* st = ctl.pend;
+  if (lead && threadIdx.x == 0) {
+    *ctl.st = *st;
+    if (ndone && st->done) atomicAdd(ndone, 1u);
+  }
+  if (st->action == kActSplit) {
+    // Codebook Splitting of codevector k (the split kernel's arithmetic):
+    // children 2k ("+") and 2k+1 ("-"), formed in FP64, rounded once.
+    if (k >= st->n_src) return false;
+    const float* Cs = cbp.c[st->src];
+    float* Cd = cbp.c[st->dst];
+    for (int d = threadIdx.x; d < L; d += kT)
+      misc::split_pair(Cs[k * L + d], st->split_mode, st->eps, st->delta, &Cd[(2 * k) * L + d],
+                       &Cd[(2 * k + 1) * L + d]);
+    return false;
+  }
+  if (st->action != kActUpdate) return false;
+  *N = st->n_src;
+  *C_old = cbp.c[st->src];
+  *out = cbp.c[st->dst];
+  return k < *N;
+}
+
+// Centroid (MODE 0) or gradient (MODE 1) of cell k from the chunk partials.
+template <int MODE>
+__device__ __forceinline__ void fin_body(const unsigned long long* __restrict__ part,
+                                         const int32_t* __restrict__ pcnt, int nchunks, int N,
+                                         int L, int s, const float* __restrict__ C_old,
+                                         float* __restrict__ out, int32_t* __restrict__ counts,
+                                         double g2, int k) {
+  __shared__ unsigned long long red[kT];
+  __shared__ long long scount;
+  const int t = threadIdx.x;
+  if (t < 64) {
+    long long c = 0;
+    for (int ch = t; ch < nchunks; ch += 64) c += pcnt[(int64_t)ch * N + k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+    if (t == 0) scount = c;
+  }
+  int G2 = 1;
+  while (G2 < L && G2 < kT) G2 <<= 1;
+  const int Q = kT / G2;
+  __syncthreads();
+  const long long cnt = scount;
+  if (counts && t == 0) counts[k] = (int32_t)cnt;
+  for (int d0 = 0; d0 < L; d0 += G2) {
+    const int q = t / G2, d = d0 + t % G2;
+    unsigned long long a0 = 0, a1 = 0;
+    if (d < L && cnt > 0) {
+      int ch = q;
+      for (; ch + Q < nchunks; ch += 2 * Q) {
+        a0 += part[((int64_t)ch * N + k) * L + d];
+        a1 += part[((int64_t)(ch + Q) * N + k) * L + d];
+      }
+      if (ch < nchunks) a0 += part[((int64_t)ch * N + k) * L + d];
+    }
+    red[t] = a0 + a1;
+    __syncthreads();
+    if (t < G2 && d < L) {
+      const int64_t e = (int64_t)k * L + d;
+      if (cnt == 0) {
+        if (MODE == 0) {
+          if (out != C_old) out[e] = C_old[e];
+        } else {
+          out[e] = 0.0f;
+        }
+      } else {
+        unsigned long long sum = 0;
+        for (int qi = 0; qi < Q; ++qi) sum += red[qi * G2 + t];
+        const long long S = (long long)sum;
+        if (MODE == 0) {
+          out[e] = (float)(ldexp((double)S, -s) / (double)cnt);
+        } else {
+          const long long ck = llrint(ldexp((double)C_old[e], s));
+          const long long diff = (long long)((unsigned long long)(cnt * ck) - (unsigned long long)S);
+          out[e] = (float)(g2 * ldexp((double)diff, -s));
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+
+}  // namespace afp
+}  // namespace lbg

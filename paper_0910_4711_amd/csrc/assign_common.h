@@ -87,7 +87,7 @@ template <class SC>
 constexpr int persist_blocks() { return 256 * SC::OCC; }
 
 template <class SC>
-constexpr int lds_budget() { return SC::OCC >= 4 ? 40960 : (SC::OCC == 3 ? 53248 : 61440); }
+constexpr int lds_budget() { return SC::OCC >= 4 ? 40960 : (SC::OCC == 3 ? 53248 : 81920); }
 
 // Rows of codevectors staged per chunk (multiple of 32) for a codebook of
 // n_pad rows: all of it when it fits the LDS budget.
@@ -891,6 +891,107 @@ __device__ __forceinline__ void load_x(const float* __restrict__ X, int64_t M, i
   }
 }
 
+// Per-wave constants of the allocation.  The key mask and -inf live in VGPRs
+// the compiler cannot see through (so that the and-or reads one SGPR and
+// the med3 stays a med3).
+struct WaveCtx {
+  int h, j, tile_bits;
+  uint32_t vmask;
+  float ninf;
+  Bound bd;
+};
+
+__device__ __forceinline__ WaveCtx wave_ctx(int L, int tile_bits) {
+  WaveCtx w;
+  const int lane = threadIdx.x & 63;
+  w.h = lane >> 5;
+  w.j = lane & 31;
+  w.tile_bits = tile_bits;
+  uint32_t vmask = ~((1u << tile_bits) - 1u);
+  asm volatile("v_mov_b32 %0, %1" : "=v"(vmask) : "v"(vmask));
+  float ninf = -INFINITY;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(ninf) : "v"(ninf));
+  w.vmask = vmask;
+  w.ninf = ninf;
+  w.bd = bound_of(L, tile_bits);
+  return w;
+}
+
+// The calling wave's tile of 32 training vectors (rows row0 .. row0+31):
+// screen against the codebook (resident in sA, or staged chunk by chunk from
+// Cp by the whole workgroup), then rescore, decide, fall back and store.
+// xv holds this lane's half-row on entry; with PF it receives the half-row
+// of the tile at next_row0 (when >= 0), loaded while the screen runs.
+// Returns this lane's winning distance (0 for lanes that finish no vector).
+template <class SC, bool VEC, bool PF>
+__device__ __forceinline__ double process_rows(
+    float (&xv)[SC::LP / 2], const float* __restrict__ X, int64_t M, int L, int64_t row0,
+    int64_t next_row0, const float* __restrict__ C, int n, int n_pad, int CR, bool resident,
+    const typename SC::elem* __restrict__ Cp, typename SC::elem* sA, int32_t* __restrict__ idx,
+    float* __restrict__ mind, unsigned long long* nfb, const WaveCtx& w) {
+  constexpr int LP = SC::LP;
+  constexpr int S = SC::S;
+  constexpr int NS = SC::NS;
+  typedef typename SC::elem E;
+  const int h = w.h, j = w.j;
+
+  // B operand: lane (j, h) keeps dims [h*LP/2, (h+1)*LP/2) of vector j and
+  // the norm step's [1, |x|^2] (FP32) or [1, 1, 1, hi, mid, lo, 0, 0] /
+  // zeros (BF16).
+  typedef typename std::conditional<SC::EXACT, float, bf16x8>::type BF;
+  BF xf[NS];
+  BF xn;
+  double ss = 0.0;
+  if constexpr (SC::EXACT) {
+#pragma unroll
+    for (int s = 0; s < LP / 2; ++s) {
+      xf[s] = xv[s];
+      ss += (double)xv[s] * (double)xv[s];
+    }
+    ss += xor_lane<32>(ss);
+    xn = h ? (float)ss : 1.0f;
+  } else {
+#pragma unroll
+    for (int s = 0; s < LP / 2; ++s) {
+      const __bf16 b = (__bf16)xv[s];
+      xf[s >> 3][s & 7] = b;
+      const double r = (double)(float)b;
+      ss += r * r;
+    }
+    ss += xor_lane<32>(ss);
+    __bf16 hi, mid, lo;
+    split3((float)ss, hi, mid, lo);
+    const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
+    const bf16x8 nv = {one, one, one, hi, mid, lo, zero, zero};
+    const bf16x8 zv = {zero, zero, zero, zero, zero, zero, zero, zero};
+    xn = h ? zv : nv;
+  }
+  const float xsq = (float)ss;
+  // the FP32 rescore needs this tile's vectors after the screen
+  float xk[LP / 2];
+  if constexpr (SC::EXACT) {
+#pragma unroll
+    for (int s = 0; s < LP / 2; ++s) xk[s] = xv[s];
+  }
+  if (PF && next_row0 >= 0) load_x<LP, VEC>(X, M, L, next_row0, h, j, xv);
+
+  Slots sl;
+  sl.init();
+  for (int c0 = 0; c0 < n_pad; c0 += CR) {
+    const int cr = min(CR, n_pad - c0);
+    if (!resident) {
+      __syncthreads();
+      stage(Cp + (int64_t)c0 * S, sA, cr * S * SC::ESZ);
+      __syncthreads();
+    }
+    const E* base = resident ? sA + (int64_t)c0 * S : sA;
+    screen_tiles<SC>(base + j * S, cr >> 5, (uint32_t)(c0 >> 5), h, xf, xn, sl, w.vmask,
+                     w.ninf);
+  }
+  return finish_rows<SC, VEC>(sl, X, M, L, C, n, idx, mind, row0, w.tile_bits, nfb,
+                              resident ? sA : nullptr, xk, xsq, w.bd, w.ninf);
+}
+
 template <class SC, bool VEC>
 __global__ __launch_bounds__(kAssignThreads, SC::OCC) void assign_kernel(
     const float* __restrict__ X, int64_t M, int L, const float* __restrict__ C, int n,
@@ -906,8 +1007,6 @@ __global__ __launch_bounds__(kAssignThreads, SC::OCC) void assign_kernel(
     tile_bits = tile_bits_of(n);
   }
   constexpr int LP = SC::LP;
-  constexpr int S = SC::S;
-  constexpr int NS = SC::NS;
   constexpr bool PF = LP <= 32;  // prefetch the next row tile's vectors
   if (VEC) L = LP;  // vector loads only for rows of exactly LP floats
   typedef typename SC::elem E;
@@ -916,84 +1015,24 @@ __global__ __launch_bounds__(kAssignThreads, SC::OCC) void assign_kernel(
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (SGPR)
-  const int h = lane >> 5;
-  const int j = lane & 31;
   const int64_t ntiles_rows = (M + kRowsPerTile - 1) / kRowsPerTile;
   const bool resident = CR >= n_pad;
-  // key mask and -inf in VGPRs the compiler cannot see through
-  uint32_t vmask = ~((1u << tile_bits) - 1u);
-  asm volatile("v_mov_b32 %0, %1" : "=v"(vmask) : "v"(vmask));
-  float ninf = -INFINITY;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(ninf) : "v"(ninf));
-  const Bound bd = bound_of(L, tile_bits);
+  const WaveCtx w = wave_ctx(L, tile_bits);
 
   float xv[LP / 2];
   int64_t rt = blockIdx.x;
   if (PF && rt < ntiles_rows)
-    load_x<LP, VEC>(X, M, L, rt * kRowsPerTile + (int64_t)wave * 32, h, j, xv);
+    load_x<LP, VEC>(X, M, L, rt * kRowsPerTile + (int64_t)wave * 32, w.h, w.j, xv);
   if (resident) stage_from_C<SC, VEC>(C, n, L, n_pad, sA);
 
   double wsum = 0.0;
   for (; rt < ntiles_rows; rt += gridDim.x) {
     const int64_t row0 = rt * kRowsPerTile + (int64_t)wave * 32;
-    if (!PF) load_x<LP, VEC>(X, M, L, row0, h, j, xv);
-
-    // B operand: lane (j, h) keeps dims [h*LP/2, (h+1)*LP/2) of vector j and
-    // the norm step's [1, |x|^2] (FP32) or [1, 1, 1, hi, mid, lo, 0, 0] /
-    // zeros (BF16).
-    typedef typename std::conditional<SC::EXACT, float, bf16x8>::type BF;
-    BF xf[NS];
-    BF xn;
-    double ss = 0.0;
-    if constexpr (SC::EXACT) {
-#pragma unroll
-      for (int s = 0; s < LP / 2; ++s) {
-        xf[s] = xv[s];
-        ss += (double)xv[s] * (double)xv[s];
-      }
-      ss += xor_lane<32>(ss);
-      xn = h ? (float)ss : 1.0f;
-    } else {
-#pragma unroll
-      for (int s = 0; s < LP / 2; ++s) {
-        const __bf16 b = (__bf16)xv[s];
-        xf[s >> 3][s & 7] = b;
-        const double r = (double)(float)b;
-        ss += r * r;
-      }
-      ss += xor_lane<32>(ss);
-      __bf16 hi, mid, lo;
-      split3((float)ss, hi, mid, lo);
-      const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
-      const bf16x8 nv = {one, one, one, hi, mid, lo, zero, zero};
-      const bf16x8 zv = {zero, zero, zero, zero, zero, zero, zero, zero};
-      xn = h ? zv : nv;
-    }
-    const float xsq = (float)ss;
-    // the FP32 rescore needs this tile's vectors after the screen
-    float xk[LP / 2];
-    if constexpr (SC::EXACT) {
-#pragma unroll
-      for (int s = 0; s < LP / 2; ++s) xk[s] = xv[s];
-    }
-    if (PF && rt + gridDim.x < ntiles_rows)
-      load_x<LP, VEC>(X, M, L, row0 + (int64_t)gridDim.x * kRowsPerTile, h, j, xv);
-
-    Slots sl;
-    sl.init();
-    for (int c0 = 0; c0 < n_pad; c0 += CR) {
-      const int cr = min(CR, n_pad - c0);
-      if (!resident) {
-        __syncthreads();
-        stage(Cp + (int64_t)c0 * S, sA, cr * S * SC::ESZ);
-        __syncthreads();
-      }
-      const E* base = resident ? sA + (int64_t)c0 * S : sA;
-      screen_tiles<SC>(base + j * S, cr >> 5, (uint32_t)(c0 >> 5), h, xf, xn, sl, vmask, ninf);
-    }
-
-    wsum += finish_rows<SC, VEC>(sl, X, M, L, C, n, idx, mind, row0, tile_bits, nfb,
-                                 resident ? sA : nullptr, xk, xsq, bd, ninf);
+    if (!PF) load_x<LP, VEC>(X, M, L, row0, w.h, w.j, xv);
+    const int64_t next =
+        (PF && rt + gridDim.x < ntiles_rows) ? row0 + (int64_t)gridDim.x * kRowsPerTile : -1;
+    wsum += process_rows<SC, VEC, PF>(xv, X, M, L, row0, next, C, n, n_pad, CR, resident, Cp, sA,
+                                      idx, mind, nfb, w);
   }
   // per-wave partial of the distortion over the block's row tiles (in order),
   // lanes added by a fixed butterfly
@@ -1030,6 +1069,15 @@ int launch_screen(const float* X, int64_t M, int L, const float* C, int n, int32
           ((reinterpret_cast<uintptr_t>(cbp.c[1]) & 15) == 0);
   else
     vec = vec && ((reinterpret_cast<uintptr_t>(C) & 15) == 0);
+  // workgroups may hold up to lds_budget bytes of LDS (above 64 KB on gfx950
+  // only after opting in, once per kernel)
+  static const hipError_t a1 = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&assign_kernel<SC, true>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget<SC>());
+  static const hipError_t a2 = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&assign_kernel<SC, false>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget<SC>());
+  LBG_TRY_HIP(vec ? a1 : a2);
   if (vec)
     hipLaunchKernelGGL((assign_kernel<SC, true>), dim3((unsigned)grid), dim3(kAssignThreads), lds,
                        s, X, M, L, C, n, Cp, n_pad, CR, idx, mind, dpart, nfb, tb, ctl, cbp);

@@ -1,0 +1,879 @@
+// Batched LBG: many independent training runs (instances of uneven M, L and
+// N), advanced together one Lloyd iteration per round (Algorithm 1 for every
+// instance).  A round is three launches for all instances:
+//
+//   b_assign  persistent: workgroups take allocation items from a queue (an
+//             item is one instance's slot b; a workgroup takes `grab` items
+//             per queue access), stage that instance's codebook into LDS and
+//             run the allocation of the tiles b, b + G, b + 2G, ... exactly as
+//             the single-run kernel's workgroup b does (same tiles, same
+//             per-wave partial sums, so the same distortion).
+//   b_acc     one workgroup per (instance, row chunk, cell slice): every
+//             instance's decision from its own partials, then the fixed-point
+//             cell sums (integers: exact, order-free).
+//   b_fin     one workgroup per (instance, cell): centroid, or split, or
+//             nothing; the instance's first workgroup commits its state.
+//
+// Each instance keeps its own device state, so instances stop and split
+// independently; finished instances cost one state read per launch.  Results
+// are bit-identical to lbg_train run on each instance alone.  The rounds are
+// replayed from a hipGraph (or launched directly), and the host reads a
+// finished-instance counter every few rounds.  The allocation's queue
+// granularity and grid are chosen by timing candidates on the instances'
+// final codebook sizes (autotuner, cached per workload signature).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "afp_common.h"
+#include "assign_common.h"
+#include "misc_common.h"
+
+namespace lbg {
+namespace {
+
+using namespace assign_detail;
+
+constexpr int kT = 256;
+constexpr int kBatchTrace = 1024;      // distortion trace entries per instance
+constexpr int kBatchLds = 81920;       // allocation LDS per workgroup (2 per CU)
+constexpr int kRoundsPerGraph = 8;
+
+// Device descriptor of one instance.
+struct BInst {
+  const float* X;
+  int64_t M;
+  int32_t L, LP, vec, N;
+  float* Cb[2];
+  float* C_out;
+  int32_t* idx;
+  DevState* st;
+  DevState* pend;
+  double* dpart;   // 4 per allocation slot
+  int64_t ntiles;  // row tiles of kRowsPerTile
+  int32_t G;       // allocation slots: the single-run kernel's grid
+  int32_t cps, nslices, nchunks, absmax_blocks, cnwg;
+  int64_t rows_per_chunk, crpb;
+  unsigned long long* part;
+  int32_t* pcnt;
+  uint32_t* amax;
+  int* shift;
+  double* cpart;
+  double* Dtrace;
+  int32_t* Atrace;
+  unsigned long long* nfb;
+};
+
+// Exclusive prefix sums of each launch's blocks (or items) over instances.
+enum { kPreItem, kPreAcc, kPreFin, kPreCol, kPreColFin, kPreAmax, kNumPre };
+
+// Largest i with pre[i] <= x (pre has n + 1 entries, pre[0] = 0).
+__device__ __forceinline__ int find_inst(const int64_t* __restrict__ pre, int n, int64_t x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------- allocation --
+// Slot b of instance B: the tiles and partials of the single-run kernel's
+// workgroup b.  The codebook is staged unless this workgroup staged the same
+// one last.
+template <class SC, bool VEC>
+__device__ __forceinline__ void alloc_item(const BInst& B, const DevState* st, int b, int i,
+                                           int* staged, unsigned char* smem) {
+  constexpr int LP = SC::LP;
+  constexpr bool PF = LP <= 32;
+  typedef typename SC::elem E;
+  E* sA = reinterpret_cast<E*>(smem);
+  const int n = st->n, cb = st->cb;
+  const float* C = B.Cb[cb];
+  const int n_pad = (n + 31) & ~31;
+  const int L = VEC ? LP : B.L;
+  const int key = (i << 1) | cb;
+  if (*staged != key) {
+    __syncthreads();  // the previous item's waves are done with the LDS copy
+    stage_from_C<SC, VEC>(C, n, L, n_pad, sA);
+    *staged = key;
+  }
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const WaveCtx w = wave_ctx(L, tile_bits_of(n));
+  float xv[LP / 2];
+  int64_t rt = b;
+  if (PF && rt < B.ntiles)
+    load_x<LP, VEC>(B.X, B.M, L, rt * kRowsPerTile + (int64_t)wave * 32, w.h, w.j, xv);
+  double wsum = 0.0;
+  for (; rt < B.ntiles; rt += B.G) {
+    const int64_t row0 = rt * kRowsPerTile + (int64_t)wave * 32;
+    if (!PF) load_x<LP, VEC>(B.X, B.M, L, row0, w.h, w.j, xv);
+    const int64_t next = (PF && rt + B.G < B.ntiles) ? row0 + (int64_t)B.G * kRowsPerTile : -1;
+    wsum += process_rows<SC, VEC, PF>(xv, B.X, B.M, L, row0, next, C, n, n_pad, n_pad, true,
+                                      nullptr, sA, B.idx, nullptr, B.nfb, w);
+  }
+  wsum = wave_sum(wsum);
+  if (lane == 0) B.dpart[b * 4 + wave] = wsum;
+}
+
+__global__ __launch_bounds__(kT, 2) void b_assign_kernel(const BInst* __restrict__ inst,
+                                                         int n_inst,
+                                                         const int64_t* __restrict__ pre,
+                                                         int grab, unsigned* __restrict__ qctr) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ int64_t s_first;
+  const int64_t* item_pre = pre + (int64_t)kPreItem * (n_inst + 1);
+  const int64_t total = item_pre[n_inst];
+  int staged = -1;
+  for (;;) {
+    __syncthreads();  // s_first of the previous access has been read
+    if (threadIdx.x == 0) s_first = (int64_t)atomicAdd(qctr, (unsigned)grab);
+    __syncthreads();
+    const int64_t first = s_first;
+    if (first >= total) break;
+    const int64_t last = min(total, first + grab);
+    for (int64_t it = first; it < last; ++it) {
+      const int i = find_inst(item_pre, n_inst, it);
+      const BInst& B = inst[i];
+      const DevState* st = B.st;
+      if (st->done) continue;
+      const int b = (int)(it - item_pre[i]);
+      if (B.LP == 16) {
+        if (B.vec)
+          alloc_item<Fp32Screen<16>, true>(B, st, b, i, &staged, smem);
+        else
+          alloc_item<Fp32Screen<16>, false>(B, st, b, i, &staged, smem);
+      } else {
+        if (B.vec)
+          alloc_item<Fp32Screen<64>, true>(B, st, b, i, &staged, smem);
+        else
+          alloc_item<Fp32Screen<64>, false>(B, st, b, i, &staged, smem);
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------- update --
+__global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ inst, int n_inst,
+                                                   const int64_t* __restrict__ pre) {
+  extern __shared__ unsigned long long sacc[];
+  __shared__ int32_t slist[afp::kBatch];
+  __shared__ int32_t snsel;
+  const int64_t* acc_pre = pre + (int64_t)kPreAcc * (n_inst + 1);
+  if ((int64_t)blockIdx.x >= acc_pre[n_inst]) return;
+  const int i = find_inst(acc_pre, n_inst, blockIdx.x);
+  const BInst& B = inst[i];
+  const int64_t local = (int64_t)blockIdx.x - acc_pre[i];
+  const Ctl ctl{B.st, B.pend, B.dpart, 4 * (int64_t)B.G, B.Dtrace, B.Atrace};
+  int N = B.N;
+  if (!afp::acc_decide(ctl, local == 0, &N)) return;
+  const int s = *B.shift;
+  const int L = B.L;
+#define LBG_BACC(GG, VV)                                                                    \
+  afp::acc_body<GG, VV, 1>(B.X, B.M, L, B.idx, N, B.cps, B.nslices, B.rows_per_chunk, s, \
+                           B.part, B.pcnt, local, sacc, slist, snsel)
+  if (B.vec && (L & 3) == 0) {
+    const int lanes = L / 4;
+    if (lanes <= 1)
+      LBG_BACC(1, 4);
+    else if (lanes <= 2)
+      LBG_BACC(2, 4);
+    else if (lanes <= 4)
+      LBG_BACC(4, 4);
+    else if (lanes <= 8)
+      LBG_BACC(8, 4);
+    else
+      LBG_BACC(16, 4);
+  } else {
+    if (L <= 1)
+      LBG_BACC(1, 1);
+    else if (L <= 2)
+      LBG_BACC(2, 1);
+    else if (L <= 4)
+      LBG_BACC(4, 1);
+    else if (L <= 8)
+      LBG_BACC(8, 1);
+    else if (L <= 16)
+      LBG_BACC(16, 1);
+    else if (L <= 32)
+      LBG_BACC(32, 1);
+    else
+      LBG_BACC(64, 1);
+  }
+#undef LBG_BACC
+}
+
+// Block 0 also rearms the allocation queue for the next round (the round's
+// allocation has completed before this launch starts).
+__global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ inst, int n_inst,
+                                                   const int64_t* __restrict__ pre,
+                                                   unsigned* __restrict__ qctr,
+                                                   unsigned* __restrict__ ndone) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *qctr = 0u;
+  const int64_t* fin_pre = pre + (int64_t)kPreFin * (n_inst + 1);
+  if ((int64_t)blockIdx.x >= fin_pre[n_inst]) return;
+  const int i = find_inst(fin_pre, n_inst, blockIdx.x);
+  const BInst& B = inst[i];
+  const int k = (int)((int64_t)blockIdx.x - fin_pre[i]);
+  const Ctl ctl{B.st, B.pend, B.dpart, 4 * (int64_t)B.G, B.Dtrace, B.Atrace};
+  const CbPair cbp{{B.Cb[0], B.Cb[1]}};
+  int N = B.N;
+  const float* c_old = nullptr;
+  float* dst = nullptr;
+  if (!afp::fin_state(ctl, cbp, k, k == 0, B.L, &N, &c_old, &dst, ndone)) return;
+  afp::fin_body<0>(B.part, B.pcnt, B.nchunks, N, B.L, *B.shift, c_old, dst, nullptr, 0.0, k);
+}
+
+// ------------------------------------------------------------- set-up, end --
+__global__ __launch_bounds__(kT) void b_colsum_kernel(const BInst* __restrict__ inst, int n_inst,
+                                                      const int64_t* __restrict__ pre) {
+  const int64_t* p = pre + (int64_t)kPreCol * (n_inst + 1);
+  if ((int64_t)blockIdx.x >= p[n_inst]) return;
+  const int i = find_inst(p, n_inst, blockIdx.x);
+  const BInst& B = inst[i];
+  misc::colsum_body(B.X, B.M, B.L, B.crpb, B.cpart, (int64_t)blockIdx.x - p[i]);
+}
+
+// Column d of instance i's centroid into Cb[0]; with N > 1 also its split
+// into rows 0 ("+") and 1 ("-") of Cb[1] (the split kernel's arithmetic on
+// the stored centroid).
+__global__ __launch_bounds__(kT) void b_centroid_kernel(const BInst* __restrict__ inst,
+                                                        int n_inst,
+                                                        const int64_t* __restrict__ pre,
+                                                        int split_mode, double eps,
+                                                        double delta) {
+  const int64_t* p = pre + (int64_t)kPreColFin * (n_inst + 1);
+  if ((int64_t)blockIdx.x >= p[n_inst]) return;
+  const int i = find_inst(p, n_inst, blockIdx.x);
+  const BInst& B = inst[i];
+  const int d = (int)((int64_t)blockIdx.x - p[i]);
+  misc::colsum_final_body(B.cpart, B.cnwg, B.L, B.M, B.Cb[0], d);
+  if (threadIdx.x == 0 && B.N > 1)
+    misc::split_pair(B.Cb[0][d], split_mode, eps, delta, &B.Cb[1][d], &B.Cb[1][B.L + d]);
+}
+
+__global__ __launch_bounds__(kT) void b_absmax_kernel(const BInst* __restrict__ inst, int n_inst,
+                                                      const int64_t* __restrict__ pre) {
+  const int64_t* p = pre + (int64_t)kPreAmax * (n_inst + 1);
+  if ((int64_t)blockIdx.x >= p[n_inst]) return;
+  const int i = find_inst(p, n_inst, blockIdx.x);
+  const BInst& B = inst[i];
+  afp::absmax_body(B.X, B.M * B.L, B.amax, (int64_t)blockIdx.x - p[i], B.absmax_blocks);
+}
+
+__global__ __launch_bounds__(kT) void b_shift_kernel(const BInst* __restrict__ inst) {
+  const BInst& B = inst[blockIdx.x];
+  afp::shift_body(B.amax, B.absmax_blocks, B.M, B.shift);
+}
+
+// Row k of every instance's current codebook into its C_out.
+__global__ __launch_bounds__(kT) void b_output_kernel(const BInst* __restrict__ inst, int n_inst,
+                                                      const int64_t* __restrict__ pre) {
+  const int64_t* p = pre + (int64_t)kPreFin * (n_inst + 1);
+  if ((int64_t)blockIdx.x >= p[n_inst]) return;
+  const int i = find_inst(p, n_inst, blockIdx.x);
+  const BInst& B = inst[i];
+  const int64_t k = (int64_t)blockIdx.x - p[i];
+  const float* src = B.Cb[B.st->cb];
+  for (int d = threadIdx.x; d < B.L; d += kT) B.C_out[k * B.L + d] = src[k * B.L + d];
+}
+
+// Autotuning set-up: every instance at its final codebook size, codevector k
+// = training vector k mod M (allocation only; the states are set again
+// before the run).
+__global__ __launch_bounds__(kT) void b_tune_setup_kernel(const BInst* __restrict__ inst,
+                                                          int n_inst,
+                                                          const int64_t* __restrict__ pre) {
+  const int64_t* p = pre + (int64_t)kPreFin * (n_inst + 1);
+  if ((int64_t)blockIdx.x >= p[n_inst]) return;
+  const int i = find_inst(p, n_inst, blockIdx.x);
+  const BInst& B = inst[i];
+  const int64_t k = (int64_t)blockIdx.x - p[i];
+  const float* src = B.X + (k % B.M) * B.L;
+  for (int d = threadIdx.x; d < B.L; d += kT) B.Cb[0][k * B.L + d] = src[d];
+  if (k == 0 && threadIdx.x == 0) {
+    B.st->n = B.N;
+    B.st->cb = 0;
+    B.st->done = 0;
+  }
+}
+
+// ---------------------------------------------------------------- planning --
+struct InstPlan {
+  int LP, vec, G, cnwg;
+  int64_t ntiles, crpb;
+  AfpWs afp;
+  float* Cb[2];
+  double* dpart;
+  double* cpart;
+  double* Dtrace;
+  int32_t* Atrace;
+};
+
+struct BatchWs {
+  BInst* inst;      // device descriptors
+  int64_t* pre;     // kNumPre x (n + 1)
+  DevState* st;     // n
+  DevState* pend;   // n
+  unsigned* ctr;    // [0] allocation queue, [1] finished instances
+  unsigned long long* nfb;  // n
+  std::vector<InstPlan> plans;
+};
+
+int lp_of(int64_t L) { return L <= 16 ? 16 : 64; }
+
+// Slots of the single-run allocation kernel for this instance.
+int slots_of(int64_t M, int64_t L) {
+  const int64_t tiles = (M + kRowsPerTile - 1) / kRowsPerTile;
+  int64_t cap;
+  switch (padded_dim(L)) {
+    case 8: cap = persist_blocks<Fp32Screen<8>>(); break;
+    case 16: cap = persist_blocks<Fp32Screen<16>>(); break;
+    case 32: cap = persist_blocks<Fp32Screen<32>>(); break;
+    case 64: cap = persist_blocks<Fp32Screen<64>>(); break;
+    default: cap = persist_blocks<Fp32Screen<128>>(); break;
+  }
+  return (int)std::min<int64_t>(tiles, cap);
+}
+
+void plan_batch(Carver& c, const lbg_instance* in, int n, BatchWs* w) {
+  w->inst = c.take<BInst>((size_t)n);
+  w->pre = c.take<int64_t>((size_t)kNumPre * (n + 1));
+  w->st = c.take<DevState>((size_t)n);
+  w->pend = c.take<DevState>((size_t)n);
+  w->ctr = c.take<unsigned>(2);
+  w->nfb = c.take<unsigned long long>((size_t)n);
+  w->plans.resize((size_t)n);
+  for (int i = 0; i < n; ++i) {
+    InstPlan& q = w->plans[(size_t)i];
+    const int64_t M = in[i].M, L = in[i].L, N = in[i].N;
+    q.LP = lp_of(L);
+    q.vec = (L == q.LP) && ((reinterpret_cast<uintptr_t>(in[i].X) & 15) == 0);
+    q.ntiles = (M + kRowsPerTile - 1) / kRowsPerTile;
+    q.G = slots_of(M, L);
+    q.cnwg = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (M + 255) / 256));
+    q.crpb = (M + q.cnwg - 1) / q.cnwg;
+    q.Cb[0] = c.take<float>((size_t)(N * L));
+    q.Cb[1] = c.take<float>((size_t)(N * L));
+    q.dpart = c.take<double>((size_t)(4 * q.G));
+    q.cpart = c.take<double>((size_t)(q.cnwg * L));
+    q.Dtrace = c.take<double>(kBatchTrace);
+    q.Atrace = c.take<int32_t>(kBatchTrace);
+    plan_afp(c, M, L, N, &q.afp);
+  }
+}
+
+// Pinned host staging for the descriptors and states of one call.
+unsigned char* pinned_stage(size_t bytes) {
+  static thread_local unsigned char* p = nullptr;
+  static thread_local size_t have = 0;
+  if (have < bytes) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    have = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&p), bytes, hipHostMallocDefault) != hipSuccess)
+      return nullptr;
+    have = bytes;
+  }
+  return p;
+}
+
+struct Launch {
+  const BInst* inst;
+  int n;
+  const int64_t* pre;
+  int64_t blocks[kNumPre];  // totals
+  unsigned* ctr;
+  size_t acc_lds;
+};
+
+int launch_round(const Launch& l, int grab, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(b_assign_kernel, dim3((unsigned)grid), dim3(kT), kBatchLds, s, l.inst, l.n,
+                     l.pre, grab, l.ctr);
+  LBG_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(b_acc_kernel, dim3((unsigned)l.blocks[kPreAcc]), dim3(kT), l.acc_lds, s,
+                     l.inst, l.n, l.pre);
+  LBG_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(b_fin_kernel, dim3((unsigned)l.blocks[kPreFin]), dim3(kT), 0, s, l.inst,
+                     l.n, l.pre, l.ctr, l.ctr + 1);
+  LBG_TRY_HIP(hipGetLastError());
+  return LBG_OK;
+}
+
+// Autotuner: candidate (grab, grid) pairs timed on the allocation at every
+// instance's final codebook size; the fastest is cached per workload.
+struct TuneKey {
+  int n;
+  int64_t sumM, work, sumN;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(n, sumM, work, sumN) < std::tie(o.n, o.sumM, o.work, o.sumN);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;
+
+int autotune(const Launch& l, hipStream_t s, int* grab_out, int* grid_out, double* ms_out) {
+  static const int grabs[] = {1, 2, 4, 8, 16};
+  static const int grids[] = {256, 512};
+  hipLaunchKernelGGL(b_tune_setup_kernel, dim3((unsigned)l.blocks[kPreFin]), dim3(kT), 0, s,
+                     l.inst, l.n, l.pre);
+  LBG_TRY_HIP(hipGetLastError());
+  hipEvent_t e0, e1;
+  LBG_TRY_HIP(hipEventCreate(&e0));
+  LBG_TRY_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bg = 4, bgrid = 512;
+  double total = 0.0;
+  int rc = LBG_OK;
+  for (int gr : grids)
+    for (int g : grabs) {
+      float ms_min = 1e30f;
+      for (int rep = 0; rep < 3 && rc == LBG_OK; ++rep) {
+        hipError_t e = hipMemsetAsync(l.ctr, 0, sizeof(unsigned), s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        if (e == hipSuccess) {
+          hipLaunchKernelGGL(b_assign_kernel, dim3((unsigned)gr), dim3(kT), kBatchLds, s, l.inst,
+                             l.n, l.pre, g, l.ctr);
+          e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          rc = hip_fail(e, "autotune");
+          break;
+        }
+        total += ms;
+        if (rep > 0) ms_min = std::min(ms_min, ms);  // first run warms up
+      }
+      if (ms_min < best) {
+        best = ms_min;
+        bg = g;
+        bgrid = gr;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *grab_out = bg;
+  *grid_out = bgrid;
+  *ms_out = total;
+  return rc;
+}
+
+// Graph of kRoundsPerGraph rounds, cached per (workspace, stream, config).
+struct BGraph {
+  bool used = false;
+  const void* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int n = 0, grab = 0, grid = 0;
+  int64_t blocks[kNumPre] = {};
+  size_t acc_lds = 0;
+  hipGraphExec_t exec = nullptr;
+  uint64_t stamp = 0;
+};
+std::mutex g_bgraph_mu;
+BGraph g_bgraph[4];
+uint64_t g_bstamp = 0;
+
+int get_graph(const Launch& l, const void* ws, int grab, int grid, hipStream_t s,
+              hipGraphExec_t* out) {
+  for (auto& e : g_bgraph)
+    if (e.used && e.ws == ws && e.stream == s && e.n == l.n && e.grab == grab &&
+        e.grid == grid && e.acc_lds == l.acc_lds &&
+        memcmp(e.blocks, l.blocks, sizeof(e.blocks)) == 0) {
+      e.stamp = ++g_bstamp;
+      *out = e.exec;
+      return LBG_OK;
+    }
+  BGraph* slot = &g_bgraph[0];
+  for (auto& e : g_bgraph) {
+    if (!e.used) {
+      slot = &e;
+      break;
+    }
+    if (e.stamp < slot->stamp) slot = &e;
+  }
+  if (slot->used && slot->exec) (void)hipGraphExecDestroy(slot->exec);
+  slot->used = false;
+  hipGraph_t g = nullptr;
+  LBG_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int rc = LBG_OK;
+  for (int r = 0; r < kRoundsPerGraph && rc == LBG_OK; ++r) rc = launch_round(l, grab, grid, s);
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (rc != LBG_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  LBG_TRY_HIP(e);
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  LBG_TRY_HIP(e2);
+  slot->used = true;
+  slot->ws = ws;
+  slot->stream = s;
+  slot->n = l.n;
+  slot->grab = grab;
+  slot->grid = grid;
+  memcpy(slot->blocks, l.blocks, sizeof(slot->blocks));
+  slot->acc_lds = l.acc_lds;
+  slot->exec = ex;
+  slot->stamp = ++g_bstamp;
+  *out = ex;
+  return LBG_OK;
+}
+
+int validate(const lbg_instance* in, int32_t n, const lbg_params* p) {
+  if (!in || n < 1) {
+    set_error("lbg_train_batched: need at least one instance (n_inst = %d)", (int)n);
+    return LBG_EINVAL;
+  }
+  for (int i = 0; i < n; ++i) {
+    const lbg_instance& a = in[i];
+    if (!a.X || !a.C_out || !a.idx_out) {
+      set_error("lbg_train_batched: instance %d has a NULL pointer", i);
+      return LBG_EINVAL;
+    }
+    if (a.M < 1 || a.M > LBG_MAX_M || a.L < 1 || a.L > 64) {
+      set_error("lbg_train_batched: instance %d: M = %lld, L = %lld (need M >= 1, 1 <= L <= 64)",
+                i, (long long)a.M, (long long)a.L);
+      return LBG_EINVAL;
+    }
+    if (a.N < 1 || (a.N & (a.N - 1)) != 0) {
+      set_error("lbg_train_batched: instance %d: N = %lld is not a power of two", i,
+                (long long)a.N);
+      return LBG_EINVAL;
+    }
+    const int64_t npad = (a.N + 31) & ~(int64_t)31;
+    if (npad * (lp_of(a.L) + 4) * 4 > kBatchLds) {
+      set_error("lbg_train_batched: instance %d: codebook of %lld x %lld does not fit the "
+                "allocation's LDS (%d bytes)", i, (long long)a.N, (long long)a.L, kBatchLds);
+      return LBG_EINVAL;
+    }
+    if (!afp_usable(a.L, a.N)) {
+      set_error("lbg_train_batched: instance %d: N * L too large for the update", i);
+      return LBG_EINVAL;
+    }
+    if ((reinterpret_cast<uintptr_t>(a.X) & 3) || (reinterpret_cast<uintptr_t>(a.C_out) & 3) ||
+        (reinterpret_cast<uintptr_t>(a.idx_out) & 3)) {
+      set_error("lbg_train_batched: instance %d: pointers must be 4-byte aligned", i);
+      return LBG_EINVAL;
+    }
+  }
+  if (p) {
+    if (!(p->thr >= 0.0) || !std::isfinite(p->thr)) {
+      set_error("lbg_train_batched: thr must be finite and >= 0");
+      return LBG_EINVAL;
+    }
+    if (p->split_mode == LBG_SPLIT_MULT && !(p->eps_split > 0.0 && p->eps_split < 1.0)) {
+      set_error("lbg_train_batched: eps_split must lie in (0, 1)");
+      return LBG_EINVAL;
+    }
+    if (p->split_mode != LBG_SPLIT_MULT && p->split_mode != LBG_SPLIT_ADD) {
+      set_error("lbg_train_batched: unknown split_mode %d", (int)p->split_mode);
+      return LBG_EINVAL;
+    }
+    if (p->precision != LBG_FP32) {
+      set_error("lbg_train_batched: only LBG_FP32 is supported");
+      return LBG_EINVAL;
+    }
+    if (p->C_init || p->n_forced > 0) {
+      set_error("lbg_train_batched: C_init and forced_iters are not supported");
+      return LBG_EINVAL;
+    }
+    if (p->max_iter < 1) {
+      set_error("lbg_train_batched: max_iter must be >= 1");
+      return LBG_EINVAL;
+    }
+  }
+  return LBG_OK;
+}
+
+}  // namespace
+}  // namespace lbg
+
+using namespace lbg;
+
+extern "C" size_t lbg_train_batched_workspace(const lbg_instance* inst, int32_t n_inst) {
+  if (!inst || n_inst < 1) return 0;
+  Carver c{nullptr, 0};
+  BatchWs w;
+  plan_batch(c, inst, n_inst, &w);
+  return c.off + 256;
+}
+
+extern "C" void lbg_batch_config_default(lbg_batch_config* cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->grab = 0;
+  cfg->grid = 0;
+  cfg->graph = 1;
+  cfg->rounds_per_poll = kRoundsPerGraph;
+}
+
+extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const lbg_params* p,
+                                 const lbg_batch_config* cfg, lbg_batch_result* res,
+                                 lbg_batch_stats* stats, void* ws, size_t ws_bytes,
+                                 void* stream) {
+  clear_error();
+  lbg_params def;
+  lbg_params_default(&def);
+  if (!p) p = &def;
+  lbg_batch_config cdef;
+  lbg_batch_config_default(&cdef);
+  if (!cfg) cfg = &cdef;
+  LBG_TRY(validate(inst, n_inst, p));
+  if (!ws) {
+    set_error("lbg_train_batched: workspace is NULL");
+    return LBG_EINVAL;
+  }
+  if (reinterpret_cast<uintptr_t>(ws) & 255) {
+    set_error("lbg_train_batched: workspace must be 256-byte aligned");
+    return LBG_EINVAL;
+  }
+  const size_t need = lbg_train_batched_workspace(inst, n_inst);
+  if (ws_bytes < need) {
+    set_error("lbg_train_batched: workspace of %zu bytes, %zu needed", ws_bytes, need);
+    return LBG_ENOWS;
+  }
+  if (cfg->grab < 0 || cfg->grid < 0 || cfg->rounds_per_poll < 0) {
+    set_error("lbg_train_batched: negative configuration value");
+    return LBG_EINVAL;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int n = n_inst;
+
+  Carver c{reinterpret_cast<char*>(ws), 0};
+  BatchWs w;
+  plan_batch(c, inst, n, &w);
+
+  // host images: descriptors, prefix sums, initial states
+  const size_t b_inst = sizeof(BInst) * (size_t)n;
+  const size_t b_pre = sizeof(int64_t) * (size_t)kNumPre * (n + 1);
+  const size_t b_st = sizeof(DevState) * (size_t)n;
+  unsigned char* host = pinned_stage(b_inst + b_pre + b_st + 64);
+  if (!host) {
+    set_error("lbg_train_batched: could not allocate pinned host memory");
+    return LBG_EHIP;
+  }
+  BInst* hi = reinterpret_cast<BInst*>(host);
+  int64_t* hp = reinterpret_cast<int64_t*>(host + b_inst);
+  DevState* hs = reinterpret_cast<DevState*>(host + b_inst + b_pre);
+  int64_t tot[kNumPre];
+  for (int k = 0; k < kNumPre; ++k) {
+    hp[(int64_t)k * (n + 1)] = 0;
+    tot[k] = 0;
+  }
+  size_t acc_lds = 0;
+  int64_t work = 0, sumM = 0, sumN = 0;
+  for (int i = 0; i < n; ++i) {
+    const lbg_instance& a = inst[i];
+    const InstPlan& q = w.plans[(size_t)i];
+    BInst& B = hi[i];
+    memset(&B, 0, sizeof(B));
+    B.X = a.X;
+    B.M = a.M;
+    B.L = (int32_t)a.L;
+    B.LP = q.LP;
+    B.vec = q.vec;
+    B.N = (int32_t)a.N;
+    B.Cb[0] = q.Cb[0];
+    B.Cb[1] = q.Cb[1];
+    B.C_out = a.C_out;
+    B.idx = a.idx_out;
+    B.st = w.st + i;
+    B.pend = w.pend + i;
+    B.dpart = q.dpart;
+    B.ntiles = q.ntiles;
+    B.G = q.G;
+    B.cps = q.afp.cps;
+    B.nslices = q.afp.nslices;
+    B.nchunks = q.afp.nchunks;
+    B.absmax_blocks = q.afp.absmax_blocks;
+    B.cnwg = q.cnwg;
+    B.rows_per_chunk = q.afp.rows_per_chunk;
+    B.crpb = q.crpb;
+    B.part = q.afp.part;
+    B.pcnt = q.afp.pcnt;
+    B.amax = q.afp.amax;
+    B.shift = q.afp.shift;
+    B.cpart = q.cpart;
+    B.Dtrace = q.Dtrace;
+    B.Atrace = q.Atrace;
+    B.nfb = w.nfb + i;
+    const int64_t cnt[kNumPre] = {q.G, (int64_t)q.afp.nchunks * q.afp.nslices, a.N, q.cnwg, a.L,
+                                  q.afp.absmax_blocks};
+    for (int k = 0; k < kNumPre; ++k) {
+      tot[k] += cnt[k];
+      hp[(int64_t)k * (n + 1) + i + 1] = tot[k];
+    }
+    acc_lds = std::max(acc_lds, (size_t)q.afp.cps * a.L * 8 + (size_t)q.afp.cps * 4);
+    work += a.M * a.N * a.L;
+    sumM += a.M;
+    sumN += a.N;
+
+    DevState& d = hs[i];
+    memset(&d, 0, sizeof(d));
+    d.N = (int32_t)a.N;
+    d.M = a.M;
+    d.max_iter = p->max_iter;
+    d.fixed_iters = p->fixed_iters;
+    d.split_mode = p->split_mode;
+    d.thr = p->thr;
+    d.eps = p->eps_split;
+    d.delta = p->delta;
+    d.D_cap = kBatchTrace;
+    d.first = 1;
+    d.D_prev = INFINITY;
+    d.status = LBG_OK;
+    if (a.N == 1) {
+      d.cb = 0;
+      d.n = 1;
+      d.n_forced = 1;
+      d.forced[0] = 0;
+    } else {
+      d.cb = 1;
+      d.n = 2;
+    }
+  }
+  for (int k = 0; k < kNumPre; ++k)
+    if (tot[k] > 0x7fffffff) {
+      set_error("lbg_train_batched: too many blocks for one launch");
+      return LBG_EINVAL;
+    }
+
+  Launch l{w.inst, n, w.pre, {}, w.ctr, acc_lds};
+  for (int k = 0; k < kNumPre; ++k) l.blocks[k] = tot[k];
+
+  static const hipError_t lds_ok = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&b_assign_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+      kBatchLds);
+  LBG_TRY_HIP(lds_ok);
+
+  LBG_TRY_HIP(hipMemcpyAsync(w.inst, hi, b_inst + 0, hipMemcpyHostToDevice, s));
+  LBG_TRY_HIP(hipMemcpyAsync(w.pre, hp, b_pre, hipMemcpyHostToDevice, s));
+
+  // autotune (before the states are set: it uses them as scratch)
+  int grab = cfg->grab, grid = cfg->grid;
+  bool tuned = false;
+  double ms_tune = 0.0;
+  if (grab == 0 || grid == 0) {
+    const TuneKey key{n, sumM, work, sumN};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      if (grab == 0) grab = it->second.first;
+      if (grid == 0) grid = it->second.second;
+    } else {
+      int tg = 0, tgrid = 0;
+      LBG_TRY_HIP(hipMemsetAsync(w.st, 0, b_st, s));
+      LBG_TRY(autotune(l, s, &tg, &tgrid, &ms_tune));
+      g_tune[key] = {tg, tgrid};
+      tuned = true;
+      if (grab == 0) grab = tg;
+      if (grid == 0) grid = tgrid;
+    }
+  }
+
+  // set-up: states, counters, centroids and first split, fixed-point shifts
+  LBG_TRY_HIP(hipMemcpyAsync(w.st, hs, b_st, hipMemcpyHostToDevice, s));
+  LBG_TRY_HIP(hipMemcpyAsync(w.pend, hs, b_st, hipMemcpyHostToDevice, s));
+  LBG_TRY_HIP(hipMemsetAsync(w.ctr, 0, 2 * sizeof(unsigned), s));
+  LBG_TRY_HIP(hipMemsetAsync(w.nfb, 0, sizeof(unsigned long long) * (size_t)n, s));
+  hipLaunchKernelGGL(b_colsum_kernel, dim3((unsigned)tot[kPreCol]), dim3(kT), 0, s, w.inst, n,
+                     w.pre);
+  LBG_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(b_centroid_kernel, dim3((unsigned)tot[kPreColFin]), dim3(kT), 0, s, w.inst,
+                     n, w.pre, p->split_mode, p->eps_split, p->delta);
+  LBG_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(b_absmax_kernel, dim3((unsigned)tot[kPreAmax]), dim3(kT), 0, s, w.inst, n,
+                     w.pre);
+  LBG_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(b_shift_kernel, dim3((unsigned)n), dim3(kT), 0, s, w.inst);
+  LBG_TRY_HIP(hipGetLastError());
+
+  // rounds until every instance has finished
+  const bool use_graph = cfg->graph != 0 && s != nullptr;
+  const int per_poll = use_graph ? kRoundsPerGraph
+                                 : (cfg->rounds_per_poll > 0 ? cfg->rounds_per_poll
+                                                             : kRoundsPerGraph);
+  unsigned* ndone_host = reinterpret_cast<unsigned*>(host + b_inst + b_pre + b_st);
+  int rounds = 0;
+  // every instance finishes within (levels) x (max_iter + 1) allocations
+  int64_t max_rounds = 0;
+  for (int i = 0; i < n; ++i) {
+    int lv = 1;
+    while ((int64_t)1 << (lv - 1) < inst[i].N) ++lv;
+    const int64_t per = p->fixed_iters > 0 ? p->fixed_iters : p->max_iter;
+    max_rounds = std::max<int64_t>(max_rounds, lv * (per + 2));
+  }
+  std::unique_lock<std::mutex> glk(g_bgraph_mu, std::defer_lock);
+  hipGraphExec_t gexec = nullptr;
+  if (use_graph) {
+    glk.lock();
+    LBG_TRY(get_graph(l, ws, grab, grid, s, &gexec));
+  }
+  for (;;) {
+    if (use_graph) {
+      LBG_TRY_HIP(hipGraphLaunch(gexec, s));
+    } else {
+      for (int r = 0; r < per_poll; ++r) LBG_TRY(launch_round(l, grab, grid, s));
+    }
+    rounds += per_poll;
+    LBG_TRY_HIP(hipMemcpyAsync(ndone_host, w.ctr + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    LBG_TRY_HIP(hipStreamSynchronize(s));
+    if ((int)*ndone_host >= n) break;
+    if (rounds > max_rounds + 2 * kRoundsPerGraph) {
+      set_error("lbg_train_batched: %d of %d instances unfinished after %d rounds",
+                n - (int)*ndone_host, n, rounds);
+      return LBG_EHIP;
+    }
+  }
+  if (glk.owns_lock()) glk.unlock();
+
+  hipLaunchKernelGGL(b_output_kernel, dim3((unsigned)tot[kPreFin]), dim3(kT), 0, s, w.inst, n,
+                     w.pre);
+  LBG_TRY_HIP(hipGetLastError());
+  // states and fallback counters back to the host
+  LBG_TRY_HIP(hipMemcpyAsync(hs, w.st, b_st, hipMemcpyDeviceToHost, s));
+  std::vector<unsigned long long> nf((size_t)n);
+  LBG_TRY_HIP(hipMemcpyAsync(nf.data(), w.nfb, sizeof(unsigned long long) * (size_t)n,
+                             hipMemcpyDeviceToHost, s));
+  LBG_TRY_HIP(hipStreamSynchronize(s));
+  int status = LBG_OK;
+  int64_t dist = 0;
+  for (int i = 0; i < n; ++i) {
+    const DevState& d = hs[i];
+    if (d.status != LBG_OK) status = d.status;
+    dist += d.distances;
+    if (res) {
+      res[i].D = d.D;
+      res[i].status = d.status;
+      res[i].n_levels = d.level;
+      res[i].n_assign = d.n_assign;
+      res[i].n_update = d.n_update;
+      res[i].fallback_rows = (int64_t)nf[(size_t)i];
+    }
+  }
+  if (stats) {
+    stats->rounds = rounds;
+    stats->grab = grab;
+    stats->grid = grid;
+    stats->graph = use_graph ? 1 : 0;
+    stats->tuned = tuned ? 1 : 0;
+    stats->total_distances = dist;
+    stats->ms_tune = ms_tune;
+  }
+  return status;
+}

@@ -5,6 +5,7 @@
 
 #include "control.h"
 #include "lbg_internal.h"
+#include "misc_common.h"
 
 namespace lbg {
 namespace {
@@ -29,61 +30,21 @@ __global__ __launch_bounds__(kThreads) void split_kernel(const float* __restrict
   if (e >= n * L) return;
   const int64_t i = e / L;
   const int d = (int)(e % L);
-  const double c = (double)C[e];
-  double up, dn;
-  if (mode == LBG_SPLIT_ADD) {
-    up = c + delta;
-    dn = c - delta;
-  } else {
-    up = c * (1.0 + eps);
-    dn = c * (1.0 - eps);
-  }
-  C2[(2 * i) * L + d] = (float)up;
-  C2[(2 * i + 1) * L + d] = (float)dn;
+  misc::split_pair(C[e], mode, eps, delta, &C2[(2 * i) * L + d], &C2[(2 * i + 1) * L + d]);
 }
 
-// Per-block column sums of a row range, FP64, fixed order: thread (q, d)
-// adds rows q, q + R, q + 2R, ... of the block's range (R = 256 / L rows in
-// flight, L <= 256), then the R partial sums of each column are added in q
-// order.
 __global__ __launch_bounds__(kThreads) void colsum_kernel(const float* __restrict__ X,
                                                           int64_t M, int L,
                                                           int64_t rows_per_block,
                                                           double* __restrict__ part) {
-  __shared__ double s[kThreads];
-  const int R = kThreads / L;
-  const int t = threadIdx.x;
-  const int q = t / L, d = t % L;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-  const int64_t r1 = min(M, r0 + rows_per_block);
-  double acc = 0.0;
-  if (q < R)
-    for (int64_t r = r0 + q; r < r1; r += R) acc += (double)X[r * L + d];
-  s[t] = acc;
-  __syncthreads();
-  if (t < L) {
-    double v = 0.0;
-    for (int qi = 0; qi < R; ++qi) v += s[qi * L + t];
-    part[(int64_t)blockIdx.x * L + t] = v;
-  }
+  misc::colsum_body(X, M, L, rows_per_block, part, blockIdx.x);
 }
 
-// One block per column: thread t adds the block partials t, t+256, ... in
-// order, then a fixed tree adds the 256 thread sums.
+// One block per column.
 __global__ __launch_bounds__(kThreads) void colsum_final_kernel(
     const double* __restrict__ part, int64_t nparts, int L, int64_t M,
     float* __restrict__ c0) {
-  __shared__ double s[kThreads];
-  const int d = blockIdx.x;
-  double acc = 0.0;
-  for (int64_t p = threadIdx.x; p < nparts; p += kThreads) acc += part[p * L + d];
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) c0[d] = (float)(s[0] / (double)M);
+  misc::colsum_final_body(part, nparts, L, M, c0, blockIdx.x);
 }
 
 // Fixed-order sum of FP64 partials: thread t adds parts t, t+256, ...; the

@@ -118,3 +118,38 @@ def test_binding_refuses_cpu_tensors():
     X = torch.zeros(8, 4)
     with pytest.raises(TypeError):
         P.assign(X, X)
+
+
+def test_batched_argument_checks():
+    P, lib = _lib()
+    inst = (P.Instance * 2)()
+    for i in range(2):
+        inst[i].X, inst[i].C_out, inst[i].idx_out = FAKE.value, FAKE.value, FAKE.value
+        inst[i].M, inst[i].L, inst[i].N = 100, 16, 8
+    need = lib.lbg_train_batched_workspace(inst, 2)
+    assert need > 0
+    call = lambda n, ws, nb, p=None: lib.lbg_train_batched(inst, n, p, None, None, None, ws, nb,
+                                                           None)
+    assert call(2, FAKE, need - 1) == P.ENOWS
+    assert b"workspace" in lib.lbg_last_error()
+    assert call(2, None, need) == P.EINVAL
+    assert call(0, FAKE, need) == P.EINVAL
+    inst[1].N = 6
+    assert call(2, FAKE, need) == P.EINVAL
+    assert b"power of two" in lib.lbg_last_error()
+    inst[1].N, inst[1].L = 8, 65
+    assert call(2, FAKE, need) == P.EINVAL
+    inst[1].L, inst[1].N = 64, 512
+    assert call(2, FAKE, need) == P.EINVAL
+    assert b"LDS" in lib.lbg_last_error()
+    inst[1].N = 8
+    p = P.Params()
+    lib.lbg_params_default(ct.byref(p))
+    p.precision = P.BF16_RESCORE
+    assert call(2, FAKE, need, ct.byref(p)) == P.EINVAL
+    inst[1].idx_out = None
+    assert call(2, FAKE, need) == P.EINVAL
+    assert b"NULL" in lib.lbg_last_error()
+    cfg = P.BatchConfig()
+    lib.lbg_batch_config_default(ct.byref(cfg))
+    assert cfg.graph == 1 and cfg.grab == 0 and cfg.grid == 0

@@ -1,0 +1,128 @@
+"""Batched form (many independent LBG runs per launch) on the GPU.
+
+Bar: every instance's codebook, allocation, distortion and iteration counts
+are bit-identical to lbg_train on that instance alone (the batched kernels
+reproduce the single run's tiles, partial sums and integer cell sums), for
+any launch configuration; on integer-valued data the runs also equal the
+FP64 oracle with FP32 codebook storage.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_0910_4711_amd as P
+    P.load()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return P
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+# (M, L, N, seed): mixed dimensions (vector and scalar loads), codebook
+# sizes from 1 to 256, more codevectors than vectors, one row, ragged tiles.
+CASES = [
+    (3000, 16, 64, 1),
+    (500, 64, 16, 2),
+    (40000, 16, 256, 3),
+    (7000, 64, 256, 4),
+    (100, 5, 8, 5),
+    (2048, 33, 32, 6),
+    (50, 16, 128, 7),
+    (4096, 64, 1, 8),
+    (1, 16, 1, 9),
+    (9000, 8, 2, 10),
+    (130, 12, 4, 11),
+]
+
+
+def _data(cases):
+    out = []
+    for M, L, N, seed in cases:
+        X = synth.gmm(seed, M, L, max(1, min(N, 32)))
+        out.append((X, N))
+    return out
+
+
+def _single(P, X, N):
+    C, idx, D, st = P.train(dev(X), N)
+    return C, idx, D, st
+
+
+def _same(P, got, X, N, where):
+    C, idx, D, info = got
+    C1, idx1, D1, st1 = _single(P, X, N)
+    assert torch.equal(C, C1), f"{where}: codebook differs"
+    assert torch.equal(idx, idx1), f"{where}: allocation differs"
+    assert D == D1, f"{where}: D {D!r} vs {D1!r}"
+    assert info["n_assign"] == st1["total_assigns"], where
+    assert info["n_update"] == st1["total_updates"], where
+    assert info["n_levels"] == len(st1["level_n"]), where
+    assert info["status"] == st1["status"], where
+
+
+def test_batched_equals_single_runs(P):
+    data = _data(CASES)
+    res, stats = P.train_batched([dev(X) for X, _ in data], [N for _, N in data])
+    assert stats["grab"] >= 1 and stats["grid"] >= 1
+    for (X, N), got, case in zip(data, res, CASES):
+        _same(P, got, X, N, f"case {case}")
+
+
+@pytest.mark.parametrize("grab,grid,graph", [(1, 256, False), (16, 512, True), (3, 97, True)])
+def test_batched_configuration_does_not_change_results(P, grab, grid, graph):
+    data = _data(CASES[:6])
+    ref, _ = P.train_batched([dev(X) for X, _ in data], [N for _, N in data], grab=1, grid=512,
+                             graph=False)
+    # graphs are captured on non-default streams only
+    side = torch.cuda.Stream()
+    Xs = [dev(X) for X, _ in data]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        got, st = P.train_batched(Xs, [N for _, N in data], grab=grab, grid=grid, graph=graph)
+        got2, _ = P.train_batched(Xs, [N for _, N in data], grab=grab, grid=grid, graph=graph)
+    side.synchronize()
+    assert st["grab"] == grab and st["grid"] == grid and st["graph"] == (1 if graph else 0)
+    for a, b in zip(got, got2):  # a second call replays the cached graph
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[2] == b[2]
+    for a, b in zip(ref, got):
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_batched_matches_oracle_on_images(P):
+    img = synth.blocks(synth.image(0, 512, 512), 4).astype(np.float32)
+    sets = [(img[:4096], 64), (img[4096:6144], 16), (img[8192:20480], 128)]
+    res, _ = P.train_batched([dev(X) for X, _ in sets], [N for _, N in sets])
+    for (X, N), (C, idx, D, info) in zip(sets, res):
+        r = oracle.train(X, N, store_fp32=True)
+        np.testing.assert_array_equal(C.cpu().numpy(), r["C"].astype(np.float32))
+        np.testing.assert_array_equal(idx.cpu().numpy(), r["idx"])
+        assert abs(D - r["D"]) <= 1e-12 * max(1.0, abs(r["D"]))
+
+
+def test_batched_many_instances(P):
+    inst = synth.batched_instances(48, scale=0.05)
+    res, st = P.train_batched([dev(X) for X, _ in inst], [N for _, N in inst])
+    assert st["total_distances"] > 0
+    for k in (0, 7, 19, 33, 47):
+        X, N = inst[k]
+        _same(P, res[k], X, N, f"instance {k}")
+
+
+def test_batched_rejects_bad_instances(P):
+    X = dev(np.zeros((100, 16), np.float32))
+    with pytest.raises(Exception):
+        P.train_batched([X], [6])          # not a power of two
+    with pytest.raises(Exception):
+        P.train_batched([dev(np.zeros((10, 65), np.float32))], [4])  # L > 64
+    with pytest.raises(Exception):
+        P.train_batched([dev(np.zeros((10, 64), np.float32))], [512])  # codebook too large
