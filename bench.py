@@ -95,6 +95,80 @@ def copy_calibration(mib):
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
 
 
+def _instances_worker(args):
+    import synth
+    n, base, scale, lo = args
+    return synth.batched_instances(n, base_seed=base, scale=scale)
+
+
+def form_batched(args):
+    """Batched form: 512 independent LBG instances (M_i ~ U{2048..65536},
+    L_i in {16, 64}, N_i in {16..256}, Gaussian-mixture data) trained by
+    lbg_train_batched (one persistent allocation launch per round, hipGraph
+    rounds, autotuned queue) versus one lbg_train per instance on the same
+    GPU.  Prints one JSON line."""
+    import concurrent.futures as cf
+    import torch
+    import paper_0910_4711_amd as P
+    n_inst = args.instances
+    chunks = [(16, 10_000 + k, args.scale, k) for k in range(0, n_inst, 16)]
+    t0 = time.perf_counter()
+    inst = []
+    with cf.ProcessPoolExecutor(max_workers=min(16, len(chunks))) as ex:
+        for k, part in zip(range(0, n_inst, 16), ex.map(_instances_worker, chunks)):
+            inst.extend(part[: max(0, min(16, n_inst - k))])
+    log(f"generated {len(inst)} instances in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    Xs = [torch.from_numpy(X).to(dev) for X, _ in inst]
+    Ns = [N for _, N in inst]
+    side = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize(dev)
+    with torch.cuda.stream(side):
+        res, st0 = P.train_batched(Xs, Ns)  # warm-up (runs the autotuner once)
+    side.synchronize()
+    log(f"warm-up done (autotuned grab={st0['grab']} grid={st0['grid']}, "
+        f"{st0['ms_tune']:.1f} ms of candidate timing)")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        with torch.cuda.stream(side):
+            res, st = P.train_batched(Xs, Ns)
+    side.synchronize()
+    t_b = (time.perf_counter() - t0) / args.steps
+    dist = st["total_distances"]
+    # one lbg_train per instance, same data, same GPU
+    ws = None
+    for X, N in zip(Xs[:2], Ns[:2]):
+        P.train(X, N)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    D_single = []
+    for X, N in zip(Xs, Ns):
+        C, idx, D, _ = P.train(X, N)
+        D_single.append(D)
+    torch.cuda.synchronize(dev)
+    t_s = time.perf_counter() - t0
+    same = sum(1 for r, d in zip(res, D_single) if r[2] == d)
+    out = {
+        "metric": "batched LBG vector-codeword distances/s",
+        "value": dist / t_b,
+        "unit": "distances/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "ms_per_step": t_b * 1e3,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched{len(inst)}_gmm_M2048-65536_L16-64_N16-256",
+                   "instances": len(inst), "sum_M": int(sum(x.shape[0] for x in Xs)),
+                   "grab": st["grab"], "grid": st["grid"], "graph": st["graph"],
+                   "rounds": st["rounds"]},
+        "per_instance_launches": {"value": dist / t_s, "ms_total": t_s * 1e3},
+        "speedup_vs_per_instance": t_s / t_b,
+        "identical_D_to_per_instance": f"{same}/{len(inst)}",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(X, N, images):
     """The FP64 oracle, as it stands, on the first ``images`` pictures' rows
     with all host cores; distances/s of the full LBG run."""
@@ -123,9 +197,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, metavar="MIB", default=0,
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--form", choices=["batched"], default=None,
+                    help="benchmark one of the forms instead of the main workload")
+    ap.add_argument("--instances", type=int, default=512, help="instances of --form batched")
+    ap.add_argument("--scale", type=float, default=1.0, help="row-count scale of --form batched")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.form == "batched":
+        if args.gpus != 1:
+            sys.exit("bench.py: the forms run on one GPU")
+        form_batched(args)
         return
     if args.gpus != 1:
         print(f"bench.py: this benchmark runs on exactly one GPU; --gpus {args.gpus} "

@@ -152,14 +152,23 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
                                          int32_t& snsel) {
   const int chunk = (int)(blk / nslices), slice = (int)(blk % nslices);
   const int k0 = slice * cps, k1 = min(N, k0 + cps), nk = max(0, k1 - k0);
+  constexpr int NG = kT / G;  // rows in parallel
+  // With a single slice and few cells, R private copies of the table (row
+  // group g adds into copy g % R) keep rows of one cell from meeting in the
+  // same LDS atomic; the copies are added (integers) at the end.
+  int R = 1;
+  if (nslices == 1 && nk > 0)
+    while (R < 16 && 2 * R <= NG && 2 * R * nk <= cps) R *= 2;
+  const int TL = nk * L;  // entries of one copy
   int32_t* scnt = reinterpret_cast<int32_t*>(sacc + (size_t)cps * L);
   const int t = threadIdx.x;
-  for (int e = t; e < nk * L; e += kT) sacc[e] = 0ull;
-  for (int e = t; e < nk; e += kT) scnt[e] = 0;
+  for (int e = t; e < R * TL; e += kT) sacc[e] = 0ull;
+  for (int e = t; e < R * nk; e += kT) scnt[e] = 0;
   if (t == 0) snsel = 0;
   __syncthreads();
-  constexpr int NG = kT / G;  // rows in parallel
   const int g = t / G, gl = t % G;
+  unsigned long long* my_acc = sacc + (g % R) * TL;
+  int32_t* my_cnt = scnt + (g % R) * nk;
   const int64_t r0 = (int64_t)chunk * rows_per_chunk;
   const int64_t r1 = min(M, r0 + rows_per_chunk);
   for (int64_t b0 = r0; b0 < r1; b0 += kBatch) {
@@ -180,7 +189,7 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
           if (k[u] >= k0 && k[u] < k1)
-            add_row<G, VW, DPL>(sacc, scnt, nullptr, k[u] - k0, L, gl, s, v[u]);
+            add_row<G, VW, DPL>(my_acc, my_cnt, nullptr, k[u] - k0, L, gl, s, v[u]);
       }
     } else {
 #pragma unroll
@@ -215,14 +224,19 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
   }
   __syncthreads();
   unsigned long long* dst = part + ((int64_t)chunk * N + k0) * L;
-  for (int e = t; e < nk * L; e += kT) dst[e] = sacc[e];
+  for (int e = t; e < TL; e += kT) {
+    unsigned long long a = sacc[e];
+    for (int r = 1; r < R; ++r) a += sacc[r * TL + e];
+    dst[e] = a;
+  }
   int32_t* cdst = pcnt + (int64_t)chunk * N + k0;
-  for (int e = t; e < nk; e += kT) cdst[e] = scnt[e];
+  for (int e = t; e < nk; e += kT) {
+    int32_t c = scnt[e];
+    for (int r = 1; r < R; ++r) c += scnt[r * nk + e];
+    cdst[e] = c;
+  }
 }
 
-
-// One block per cell: thread (q, d) adds the partials of chunks q, q+Q, ...
-// (integers, so the order is immaterial), then the Q lane sums.
 // One block per cell: thread (q, d) adds the partials of chunks q, q+Q, ...
 // (integers, so the order is immaterial), then the Q lane sums.
 // Under device control: acts on the pending state for cell ``k`` (a split

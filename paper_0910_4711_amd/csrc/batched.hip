@@ -70,8 +70,16 @@ struct BInst {
   unsigned long long* nfb;
 };
 
-// Exclusive prefix sums of each launch's blocks (or items) over instances.
+// Exclusive prefix sums of each launch's blocks (or items) over instances;
+// for every family but the allocation items also a block -> instance table
+// (offset tab_off[family] into one int32 array), so that a block finds its
+// instance with one load.
 enum { kPreItem, kPreAcc, kPreFin, kPreCol, kPreColFin, kPreAmax, kNumPre };
+
+struct Tabs {
+  const int32_t* b2i;         // block -> instance, all families
+  int64_t off[kNumPre];       // start of each family in b2i
+};
 
 // Largest i with pre[i] <= x (pre has n + 1 entries, pre[0] = 0).
 __device__ __forceinline__ int find_inst(const int64_t* __restrict__ pre, int n, int64_t x) {
@@ -142,8 +150,10 @@ __global__ __launch_bounds__(kT, 2) void b_assign_kernel(const BInst* __restrict
     const int64_t first = s_first;
     if (first >= total) break;
     const int64_t last = min(total, first + grab);
+    int i = find_inst(item_pre, n_inst, first);  // once per queue access
+    int64_t next_start = item_pre[i + 1];
     for (int64_t it = first; it < last; ++it) {
-      const int i = find_inst(item_pre, n_inst, it);
+      while (it >= next_start) next_start = item_pre[++i + 1];
       const BInst& B = inst[i];
       const DevState* st = B.st;
       if (st->done) continue;
@@ -165,13 +175,13 @@ __global__ __launch_bounds__(kT, 2) void b_assign_kernel(const BInst* __restrict
 
 // ----------------------------------------------------------------- update --
 __global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ inst, int n_inst,
-                                                   const int64_t* __restrict__ pre) {
+                                                   const int64_t* __restrict__ pre, Tabs tb) {
   extern __shared__ unsigned long long sacc[];
   __shared__ int32_t slist[afp::kBatch];
   __shared__ int32_t snsel;
   const int64_t* acc_pre = pre + (int64_t)kPreAcc * (n_inst + 1);
   if ((int64_t)blockIdx.x >= acc_pre[n_inst]) return;
-  const int i = find_inst(acc_pre, n_inst, blockIdx.x);
+  const int i = tb.b2i[tb.off[kPreAcc] + blockIdx.x];
   const BInst& B = inst[i];
   const int64_t local = (int64_t)blockIdx.x - acc_pre[i];
   const Ctl ctl{B.st, B.pend, B.dpart, 4 * (int64_t)B.G, B.Dtrace, B.Atrace};
@@ -216,13 +226,13 @@ __global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ ins
 // Block 0 also rearms the allocation queue for the next round (the round's
 // allocation has completed before this launch starts).
 __global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ inst, int n_inst,
-                                                   const int64_t* __restrict__ pre,
+                                                   const int64_t* __restrict__ pre, Tabs tb,
                                                    unsigned* __restrict__ qctr,
                                                    unsigned* __restrict__ ndone) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *qctr = 0u;
   const int64_t* fin_pre = pre + (int64_t)kPreFin * (n_inst + 1);
   if ((int64_t)blockIdx.x >= fin_pre[n_inst]) return;
-  const int i = find_inst(fin_pre, n_inst, blockIdx.x);
+  const int i = tb.b2i[tb.off[kPreFin] + blockIdx.x];
   const BInst& B = inst[i];
   const int k = (int)((int64_t)blockIdx.x - fin_pre[i]);
   const Ctl ctl{B.st, B.pend, B.dpart, 4 * (int64_t)B.G, B.Dtrace, B.Atrace};
@@ -236,10 +246,10 @@ __global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ ins
 
 // ------------------------------------------------------------- set-up, end --
 __global__ __launch_bounds__(kT) void b_colsum_kernel(const BInst* __restrict__ inst, int n_inst,
-                                                      const int64_t* __restrict__ pre) {
+                                                      const int64_t* __restrict__ pre, Tabs tb) {
   const int64_t* p = pre + (int64_t)kPreCol * (n_inst + 1);
   if ((int64_t)blockIdx.x >= p[n_inst]) return;
-  const int i = find_inst(p, n_inst, blockIdx.x);
+  const int i = tb.b2i[tb.off[kPreCol] + blockIdx.x];
   const BInst& B = inst[i];
   misc::colsum_body(B.X, B.M, B.L, B.crpb, B.cpart, (int64_t)blockIdx.x - p[i]);
 }
@@ -249,12 +259,12 @@ __global__ __launch_bounds__(kT) void b_colsum_kernel(const BInst* __restrict__ 
 // the stored centroid).
 __global__ __launch_bounds__(kT) void b_centroid_kernel(const BInst* __restrict__ inst,
                                                         int n_inst,
-                                                        const int64_t* __restrict__ pre,
+                                                        const int64_t* __restrict__ pre, Tabs tb,
                                                         int split_mode, double eps,
                                                         double delta) {
   const int64_t* p = pre + (int64_t)kPreColFin * (n_inst + 1);
   if ((int64_t)blockIdx.x >= p[n_inst]) return;
-  const int i = find_inst(p, n_inst, blockIdx.x);
+  const int i = tb.b2i[tb.off[kPreColFin] + blockIdx.x];
   const BInst& B = inst[i];
   const int d = (int)((int64_t)blockIdx.x - p[i]);
   misc::colsum_final_body(B.cpart, B.cnwg, B.L, B.M, B.Cb[0], d);
@@ -263,10 +273,10 @@ __global__ __launch_bounds__(kT) void b_centroid_kernel(const BInst* __restrict_
 }
 
 __global__ __launch_bounds__(kT) void b_absmax_kernel(const BInst* __restrict__ inst, int n_inst,
-                                                      const int64_t* __restrict__ pre) {
+                                                      const int64_t* __restrict__ pre, Tabs tb) {
   const int64_t* p = pre + (int64_t)kPreAmax * (n_inst + 1);
   if ((int64_t)blockIdx.x >= p[n_inst]) return;
-  const int i = find_inst(p, n_inst, blockIdx.x);
+  const int i = tb.b2i[tb.off[kPreAmax] + blockIdx.x];
   const BInst& B = inst[i];
   afp::absmax_body(B.X, B.M * B.L, B.amax, (int64_t)blockIdx.x - p[i], B.absmax_blocks);
 }
@@ -278,10 +288,10 @@ __global__ __launch_bounds__(kT) void b_shift_kernel(const BInst* __restrict__ i
 
 // Row k of every instance's current codebook into its C_out.
 __global__ __launch_bounds__(kT) void b_output_kernel(const BInst* __restrict__ inst, int n_inst,
-                                                      const int64_t* __restrict__ pre) {
+                                                      const int64_t* __restrict__ pre, Tabs tb) {
   const int64_t* p = pre + (int64_t)kPreFin * (n_inst + 1);
   if ((int64_t)blockIdx.x >= p[n_inst]) return;
-  const int i = find_inst(p, n_inst, blockIdx.x);
+  const int i = tb.b2i[tb.off[kPreFin] + blockIdx.x];
   const BInst& B = inst[i];
   const int64_t k = (int64_t)blockIdx.x - p[i];
   const float* src = B.Cb[B.st->cb];
@@ -293,10 +303,10 @@ __global__ __launch_bounds__(kT) void b_output_kernel(const BInst* __restrict__ 
 // before the run).
 __global__ __launch_bounds__(kT) void b_tune_setup_kernel(const BInst* __restrict__ inst,
                                                           int n_inst,
-                                                          const int64_t* __restrict__ pre) {
+                                                          const int64_t* __restrict__ pre, Tabs tb) {
   const int64_t* p = pre + (int64_t)kPreFin * (n_inst + 1);
   if ((int64_t)blockIdx.x >= p[n_inst]) return;
-  const int i = find_inst(p, n_inst, blockIdx.x);
+  const int i = tb.b2i[tb.off[kPreFin] + blockIdx.x];
   const BInst& B = inst[i];
   const int64_t k = (int64_t)blockIdx.x - p[i];
   const float* src = B.X + (k % B.M) * B.L;
@@ -327,8 +337,21 @@ struct BatchWs {
   DevState* pend;   // n
   unsigned* ctr;    // [0] allocation queue, [1] finished instances
   unsigned long long* nfb;  // n
+  int32_t* b2i;             // block -> instance tables
+  int64_t b2i_n;
+  int64_t tot[kNumPre];     // blocks (items) of each family
   std::vector<InstPlan> plans;
 };
+
+// Blocks (allocation items) of each launch family for one instance.
+void family_counts(const InstPlan& q, int64_t N, int64_t L, int64_t cnt[kNumPre]) {
+  cnt[kPreItem] = q.G;
+  cnt[kPreAcc] = (int64_t)q.afp.nchunks * q.afp.nslices;
+  cnt[kPreFin] = N;
+  cnt[kPreCol] = q.cnwg;
+  cnt[kPreColFin] = L;
+  cnt[kPreAmax] = q.afp.absmax_blocks;
+}
 
 int lp_of(int64_t L) { return L <= 16 ? 16 : 64; }
 
@@ -371,6 +394,16 @@ void plan_batch(Carver& c, const lbg_instance* in, int n, BatchWs* w) {
     q.Atrace = c.take<int32_t>(kBatchTrace);
     plan_afp(c, M, L, N, &q.afp);
   }
+  for (int k = 0; k < kNumPre; ++k) w->tot[k] = 0;
+  for (int i = 0; i < n; ++i) {
+    int64_t cnt[kNumPre];
+    family_counts(w->plans[(size_t)i], in[i].N, in[i].L, cnt);
+    for (int k = 0; k < kNumPre; ++k) w->tot[k] += cnt[k];
+  }
+  w->b2i_n = 0;
+  for (int k = 0; k < kNumPre; ++k)
+    if (k != kPreItem) w->b2i_n += w->tot[k];
+  w->b2i = c.take<int32_t>((size_t)w->b2i_n);
 }
 
 // Pinned host staging for the descriptors and states of one call.
@@ -392,6 +425,7 @@ struct Launch {
   const BInst* inst;
   int n;
   const int64_t* pre;
+  Tabs tb;
   int64_t blocks[kNumPre];  // totals
   unsigned* ctr;
   size_t acc_lds;
@@ -402,10 +436,10 @@ int launch_round(const Launch& l, int grab, int grid, hipStream_t s) {
                      l.pre, grab, l.ctr);
   LBG_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(b_acc_kernel, dim3((unsigned)l.blocks[kPreAcc]), dim3(kT), l.acc_lds, s,
-                     l.inst, l.n, l.pre);
+                     l.inst, l.n, l.pre, l.tb);
   LBG_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(b_fin_kernel, dim3((unsigned)l.blocks[kPreFin]), dim3(kT), 0, s, l.inst,
-                     l.n, l.pre, l.ctr, l.ctr + 1);
+                     l.n, l.pre, l.tb, l.ctr, l.ctr + 1);
   LBG_TRY_HIP(hipGetLastError());
   return LBG_OK;
 }
@@ -426,7 +460,7 @@ int autotune(const Launch& l, hipStream_t s, int* grab_out, int* grid_out, doubl
   static const int grabs[] = {1, 2, 4, 8, 16};
   static const int grids[] = {256, 512};
   hipLaunchKernelGGL(b_tune_setup_kernel, dim3((unsigned)l.blocks[kPreFin]), dim3(kT), 0, s,
-                     l.inst, l.n, l.pre);
+                     l.inst, l.n, l.pre, l.tb);
   LBG_TRY_HIP(hipGetLastError());
   hipEvent_t e0, e1;
   LBG_TRY_HIP(hipEventCreate(&e0));
@@ -662,7 +696,8 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
   const size_t b_inst = sizeof(BInst) * (size_t)n;
   const size_t b_pre = sizeof(int64_t) * (size_t)kNumPre * (n + 1);
   const size_t b_st = sizeof(DevState) * (size_t)n;
-  unsigned char* host = pinned_stage(b_inst + b_pre + b_st + 64);
+  const size_t b_tab = sizeof(int32_t) * (size_t)w.b2i_n;
+  unsigned char* host = pinned_stage(b_inst + b_pre + b_st + 64 + b_tab);
   if (!host) {
     set_error("lbg_train_batched: could not allocate pinned host memory");
     return LBG_EHIP;
@@ -712,8 +747,8 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
     B.Dtrace = q.Dtrace;
     B.Atrace = q.Atrace;
     B.nfb = w.nfb + i;
-    const int64_t cnt[kNumPre] = {q.G, (int64_t)q.afp.nchunks * q.afp.nslices, a.N, q.cnwg, a.L,
-                                  q.afp.absmax_blocks};
+    int64_t cnt[kNumPre];
+    family_counts(q, a.N, a.L, cnt);
     for (int k = 0; k < kNumPre; ++k) {
       tot[k] += cnt[k];
       hp[(int64_t)k * (n + 1) + i + 1] = tot[k];
@@ -753,7 +788,22 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
       return LBG_EINVAL;
     }
 
-  Launch l{w.inst, n, w.pre, {}, w.ctr, acc_lds};
+  // block -> instance tables
+  int32_t* htab = reinterpret_cast<int32_t*>(host + b_inst + b_pre + b_st + 64);
+  Tabs tb;
+  tb.b2i = w.b2i;
+  {
+    int64_t off = 0;
+    for (int k = 0; k < kNumPre; ++k) {
+      tb.off[k] = off;
+      if (k == kPreItem) continue;
+      for (int i = 0; i < n; ++i)
+        for (int64_t b = hp[(int64_t)k * (n + 1) + i]; b < hp[(int64_t)k * (n + 1) + i + 1]; ++b)
+          htab[off + b] = i;
+      off += tot[k];
+    }
+  }
+  Launch l{w.inst, n, w.pre, tb, {}, w.ctr, acc_lds};
   for (int k = 0; k < kNumPre; ++k) l.blocks[k] = tot[k];
 
   static const hipError_t lds_ok = hipFuncSetAttribute(
@@ -763,6 +813,7 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
 
   LBG_TRY_HIP(hipMemcpyAsync(w.inst, hi, b_inst + 0, hipMemcpyHostToDevice, s));
   LBG_TRY_HIP(hipMemcpyAsync(w.pre, hp, b_pre, hipMemcpyHostToDevice, s));
+  LBG_TRY_HIP(hipMemcpyAsync(w.b2i, htab, b_tab, hipMemcpyHostToDevice, s));
 
   // autotune (before the states are set: it uses them as scratch)
   int grab = cfg->grab, grid = cfg->grid;
@@ -792,13 +843,13 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
   LBG_TRY_HIP(hipMemsetAsync(w.ctr, 0, 2 * sizeof(unsigned), s));
   LBG_TRY_HIP(hipMemsetAsync(w.nfb, 0, sizeof(unsigned long long) * (size_t)n, s));
   hipLaunchKernelGGL(b_colsum_kernel, dim3((unsigned)tot[kPreCol]), dim3(kT), 0, s, w.inst, n,
-                     w.pre);
+                     w.pre, tb);
   LBG_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(b_centroid_kernel, dim3((unsigned)tot[kPreColFin]), dim3(kT), 0, s, w.inst,
-                     n, w.pre, p->split_mode, p->eps_split, p->delta);
+                     n, w.pre, tb, p->split_mode, p->eps_split, p->delta);
   LBG_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(b_absmax_kernel, dim3((unsigned)tot[kPreAmax]), dim3(kT), 0, s, w.inst, n,
-                     w.pre);
+                     w.pre, tb);
   LBG_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(b_shift_kernel, dim3((unsigned)n), dim3(kT), 0, s, w.inst);
   LBG_TRY_HIP(hipGetLastError());
@@ -843,7 +894,7 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
   if (glk.owns_lock()) glk.unlock();
 
   hipLaunchKernelGGL(b_output_kernel, dim3((unsigned)tot[kPreFin]), dim3(kT), 0, s, w.inst, n,
-                     w.pre);
+                     w.pre, tb);
   LBG_TRY_HIP(hipGetLastError());
   // states and fallback counters back to the host
   LBG_TRY_HIP(hipMemcpyAsync(hs, w.st, b_st, hipMemcpyDeviceToHost, s));
