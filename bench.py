@@ -169,6 +169,165 @@ def form_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def _image_blocks_worker(args):
+    import synth
+    seed, W, H, b = args
+    return synth.blocks(synth.image(seed, W, H), b)
+
+
+def _image_set_parallel(seeds, W, H, b):
+    import concurrent.futures as cf
+    with cf.ProcessPoolExecutor(max_workers=16) as ex:
+        parts = list(ex.map(_image_blocks_worker, [(s_, W, H, b) for s_ in seeds]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _events_ms(fn, stream, reps):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+    stream.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def form_precision(args):
+    """Precision form at the 8x8-block workload: M = 4,194,304 vectors of
+    L = 64 from 256 synthetic 1024 x 1024 images, N = 1024 initial
+    codevectors = distinct training vectors, 10 Lloyd iterations in exact FP32
+    and with the BF16 screen + FP64 top-2 rescore; errors against the FP64
+    oracle on a 65,536-vector subsample."""
+    import torch
+    import oracle
+    import synth
+    import paper_0910_4711_amd as P
+    cfg = synth.CONFIG2
+    n_img = args.images if args.images else len(cfg["seeds"])
+    t0 = time.perf_counter()
+    X = _image_set_parallel(tuple(range(n_img)), cfg["W"], cfg["H"], cfg["b"])
+    M, L = X.shape
+    N = cfg["N"]
+    log(f"generated M={M} L={L} in {time.perf_counter() - t0:.1f} s")
+    C0 = X[synth.distinct_rows(X, N, 1000)]
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    C0d = torch.from_numpy(np.ascontiguousarray(C0)).to(dev)
+    stream = torch.cuda.Stream(device=dev)
+    out = {"metric": "precision form: allocation vector-codeword distances/s, BF16 screen + "
+                     "FP64 top-2 rescore vs exact FP32",
+           "unit": "distances/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": f"img{n_img}x1024x1024_b8_M{M}_L{L}_N{N}_10iters",
+                      "M": M, "L": L, "N": N, "iterations": 10}}
+    runs = {}
+    for prec in (P.FP32, P.BF16_RESCORE):
+        name = "fp32" if prec == P.FP32 else "bf16"
+        with torch.cuda.stream(stream):
+            P.train(Xd, N, C_init=C0d, fixed_iters=10, precision=prec)  # warm-up
+        stream.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            C, idx, D, st = P.train(Xd, N, C_init=C0d, fixed_iters=10, precision=prec,
+                                    timing=True)
+        stream.synchronize()
+        wall = time.perf_counter() - t0
+        dist = st["total_distances"]
+        flops = 2.0 * L * dist
+        ms_a = st["ms_assign"]
+        peak = PEAK_FP32_MFMA_TFLOPS if prec == P.FP32 else 2500.0
+        tf = flops / (ms_a * 1e-3) / 1e12
+        runs[name] = (C, idx, D, st)
+        out[name] = {"distances_per_s_assign": dist / (ms_a * 1e-3),
+                     "assign_ms_total": ms_a, "update_ms_total": st["ms_update"],
+                     "wall_ms": wall * 1e3, "assigns": st["total_assigns"],
+                     "roofline": {"bound": "mfma", "achieved": tf, "peak": peak,
+                                  "unit": "TFLOP/s", "frac": tf / peak},
+                     "update_GBs": (st["total_updates"] * M * (4 * L + 4)
+                                    / (st["ms_update"] * 1e-3) / 1e9
+                                    if st["ms_update"] > 0 else None),
+                     "D": D}
+    out["value"] = out["bf16"]["distances_per_s_assign"]
+    out["speedup_bf16_vs_fp32_assign"] = (out["fp32"]["assign_ms_total"]
+                                          / out["bf16"]["assign_ms_total"])
+    # errors against the FP64 oracle on a subsample, for the BF16 run's final
+    # codebook and allocation (the FP32 run is exact by construction)
+    rows = np.random.default_rng(1001).choice(M, min(M, 65536), replace=False)
+    rows.sort()
+    Cb, idxb, Db, _ = runs["bf16"]
+    Cb_h = Cb.cpu().numpy()
+    idx_o, d1, d2 = oracle.assign(X[rows], Cb_h.astype(np.float64))
+    ib = idxb.cpu().numpy()[rows]
+    xx = (X[rows].astype(np.float64) ** 2).sum(1)
+    wrong = ib != idx_o
+    near = (d2 - d1) < 1e-6 * xx
+    Xr = X[rows].astype(np.float64)
+    dsel = ((Xr - Cb_h.astype(np.float64)[ib]) ** 2).sum(1)
+    Cf = runs["fp32"][0].cpu().numpy().astype(np.float64)
+    rel_c = np.linalg.norm(Cb_h - Cf, axis=1) / np.maximum(np.linalg.norm(Cf, axis=1), 1e-30)
+    out["bf16_errors_vs_fp64_oracle"] = {
+        "subsample_rows": int(rows.size),
+        "assign_mismatch_rate": float(wrong.mean()),
+        "assign_mismatch_outside_tie_band": int((wrong & ~near).sum()),
+        "distance_excess_rel_max": float(((dsel - d1) / np.maximum(d1, 1e-30)).max()),
+        "codebook_rel_vs_exact_run_max": float(rel_c.max()),
+        "codebook_rel_vs_exact_run_median": float(np.median(rel_c)),
+        "D_rel_vs_exact_run": abs(Db - runs["fp32"][2]) / runs["fp32"][2],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def form_differentiation(args):
+    """Differentiation form: D = mean_m min_k ||x_m - c_k||^2 with X
+    [1,048,576 x 64] from a 512-component diagonal Gaussian mixture and C
+    [4096 x 64] distinct training vectors: forward (allocation + FP64
+    distortion) and backward (dD/dX, dD/dC) through the autograd function."""
+    import torch
+    import synth
+    import paper_0910_4711_amd as P
+    M, L, K, N = 1_048_576, 64, 512, 4096
+    t0 = time.perf_counter()
+    X = synth.gmm_diag(20000, M, L, K)
+    C = np.ascontiguousarray(X[synth.distinct_rows(X, N, 20001)])
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev).requires_grad_(True)
+    Cd = torch.from_numpy(C).to(dev).requires_grad_(True)
+    stream = torch.cuda.Stream(device=dev)
+
+    def fwd():
+        return P.Distortion.apply(Xd, Cd)
+
+    def fwd_bwd():
+        Xd.grad = None
+        Cd.grad = None
+        fwd().backward()
+
+    for _ in range(2):
+        with torch.cuda.stream(stream):
+            fwd_bwd()
+    stream.synchronize()
+    ms_f = _events_ms(fwd, stream, args.steps)
+    ms_fb = _events_ms(fwd_bwd, stream, args.steps)
+    ms_b = ms_fb - ms_f
+    dist = M * N
+    tf = 2.0 * L * dist / (ms_f * 1e-3) / 1e12
+    bwd_bytes = M * L * 4 * 2 + M * 4 + M * L * 4 + N * L * 4  # read X (twice), idx; write gX, gC
+    out = {"metric": "differentiation form: forward vector-codeword distances/s",
+           "value": dist / (ms_f * 1e-3), "unit": "distances/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"gmmdiag512_M{M}_L{L}_N{N}", "M": M, "L": L, "N": N},
+           "forward_ms": ms_f, "backward_ms": ms_b,
+           "forward_roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_FP32_MFMA_TFLOPS,
+                                "unit": "TFLOP/s", "frac": tf / PEAK_FP32_MFMA_TFLOPS},
+           "backward_roofline": {"bound": "hbm", "achieved": bwd_bytes / (ms_b * 1e-3) / 1e9,
+                                 "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                 "frac": bwd_bytes / (ms_b * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                 "algorithmic_bytes": bwd_bytes}}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(X, N, images):
     """The FP64 oracle, as it stands, on the first ``images`` pictures' rows
     with all host cores; distances/s of the full LBG run."""
@@ -197,18 +356,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, metavar="MIB", default=0,
                     help="only run a plain device copy of MIB MiB (counter calibration)")
-    ap.add_argument("--form", choices=["batched"], default=None,
-                    help="benchmark one of the forms instead of the main workload")
+    ap.add_argument("--form", choices=["batched", "precision", "differentiation"],
+                    default=None, help="benchmark one of the forms instead of the main workload")
+    ap.add_argument("--images", type=int, default=0,
+                    help="images of --form precision (default: all 256)")
     ap.add_argument("--instances", type=int, default=512, help="instances of --form batched")
     ap.add_argument("--scale", type=float, default=1.0, help="row-count scale of --form batched")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
-    if args.form == "batched":
+    if args.form:
         if args.gpus != 1:
             sys.exit("bench.py: the forms run on one GPU")
-        form_batched(args)
+        {"batched": form_batched, "precision": form_precision,
+         "differentiation": form_differentiation}[args.form](args)
         return
     if args.gpus != 1:
         print(f"bench.py: this benchmark runs on exactly one GPU; --gpus {args.gpus} "
