@@ -251,29 +251,49 @@ def form_precision(args):
     out["value"] = out["bf16"]["distances_per_s_assign"]
     out["speedup_bf16_vs_fp32_assign"] = (out["fp32"]["assign_ms_total"]
                                           / out["bf16"]["assign_ms_total"])
-    # errors against the FP64 oracle on a subsample, for the BF16 run's final
-    # codebook and allocation (the FP32 run is exact by construction)
+    # Per-step errors: the same FP32 codebook (the exact run's final one) into
+    # one BF16 and one FP32 allocation + update; allocation errors against the
+    # FP64 oracle on a 65,536-vector subsample.
+    Cref = runs["fp32"][0]
+    idx_b, mind_b = P.assign(Xd, Cref, P.BF16_RESCORE)
+    idx_f, _ = P.assign(Xd, Cref, P.FP32)
+    Cb1, _ = P.update(Xd, idx_b, Cref)
+    Cf1, _ = P.update(Xd, idx_f, Cref)
+    D_b = float(P.distortion(Xd, Cref, idx_b).item())
+    D_f = float(P.distortion(Xd, Cref, idx_f).item())
+    torch.cuda.synchronize()
     rows = np.random.default_rng(1001).choice(M, min(M, 65536), replace=False)
     rows.sort()
-    Cb, idxb, Db, _ = runs["bf16"]
-    Cb_h = Cb.cpu().numpy()
-    idx_o, d1, d2 = oracle.assign(X[rows], Cb_h.astype(np.float64))
-    ib = idxb.cpu().numpy()[rows]
+    Ch = Cref.cpu().numpy().astype(np.float64)
+    idx_o, d1, d2 = oracle.assign(X[rows], Ch)
+    ib = idx_b.cpu().numpy()[rows]
     xx = (X[rows].astype(np.float64) ** 2).sum(1)
     wrong = ib != idx_o
     near = (d2 - d1) < 1e-6 * xx
-    Xr = X[rows].astype(np.float64)
-    dsel = ((Xr - Cb_h.astype(np.float64)[ib]) ** 2).sum(1)
-    Cf = runs["fp32"][0].cpu().numpy().astype(np.float64)
-    rel_c = np.linalg.norm(Cb_h - Cf, axis=1) / np.maximum(np.linalg.norm(Cf, axis=1), 1e-30)
-    out["bf16_errors_vs_fp64_oracle"] = {
-        "subsample_rows": int(rows.size),
-        "assign_mismatch_rate": float(wrong.mean()),
-        "assign_mismatch_outside_tie_band": int((wrong & ~near).sum()),
-        "distance_excess_rel_max": float(((dsel - d1) / np.maximum(d1, 1e-30)).max()),
-        "codebook_rel_vs_exact_run_max": float(rel_c.max()),
-        "codebook_rel_vs_exact_run_median": float(np.median(rel_c)),
-        "D_rel_vs_exact_run": abs(Db - runs["fp32"][2]) / runs["fp32"][2],
+    dsel = ((X[rows].astype(np.float64) - Ch[ib]) ** 2).sum(1)
+
+    def rel_rows(A, B):
+        A = A.cpu().numpy().astype(np.float64)
+        B = B.cpu().numpy().astype(np.float64)
+        return np.linalg.norm(A - B, axis=1) / np.maximum(np.linalg.norm(B, axis=1), 1e-30)
+
+    r1 = rel_rows(Cb1, Cf1)
+    r10 = rel_rows(runs["bf16"][0], runs["fp32"][0])
+    out["bf16_errors"] = {
+        "per_step": {
+            "subsample_rows": int(rows.size),
+            "assign_mismatch_rate_vs_fp64_oracle": float(wrong.mean()),
+            "assign_mismatch_outside_tie_band": int((wrong & ~near).sum()),
+            "rescored_distance_excess_rel_max": float(((dsel - d1) / np.maximum(d1, 1e-30)).max()),
+            "codebook_rel_vs_exact_update_max": float(r1.max()),
+            "codebook_rel_vs_exact_update_median": float(np.median(r1)),
+            "D_rel_vs_exact": abs(D_b - D_f) / D_f,
+        },
+        "after_10_iterations": {
+            "codebook_rel_vs_exact_run_max": float(r10.max()),
+            "codebook_rel_vs_exact_run_median": float(np.median(r10)),
+            "D_rel_vs_exact_run": abs(runs["bf16"][2] - runs["fp32"][2]) / runs["fp32"][2],
+        },
     }
     print(json.dumps(out), flush=True)
 
