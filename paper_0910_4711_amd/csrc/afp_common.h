@@ -14,7 +14,7 @@ namespace afp {
 
 constexpr int kT = 256;
 constexpr int kLdsBytes = 61440;
-constexpr int kUnroll = 8;  // rows in flight per group
+constexpr int kUnroll = 16;  // rows in flight per group
 
 __device__ __forceinline__ void absmax_body(const float* __restrict__ X, int64_t n,
                                             uint32_t* __restrict__ part, int64_t block,
@@ -93,21 +93,18 @@ __device__ __forceinline__ void add_row(unsigned long long* sacc, int32_t* scnt,
   if (gl == 0) atomicAdd(&scnt[kk], 1);
 }
 
+// Loads are unconditional (no branch, so all rows of a batch are in flight
+// together): the caller passes a valid row, and lanes whose dimensions lie
+// beyond L read dimension 0 instead (add_row skips them).
 template <int G, int VW, int DPL>
-__device__ __forceinline__ void load_dims(const float* xrow, int L, int gl, bool on,
+__device__ __forceinline__ void load_dims(const float* xrow, int L, int gl,
                                           float (&v)[DPL][VW]) {
 #pragma unroll
   for (int q = 0; q < DPL; ++q) {
     const int d0 = (gl + q * G) * VW;
-    if (on && d0 < L) {
-      VLoad<VW>::get(xrow + d0, v[q]);
-    } else {
-#pragma unroll
-      for (int e = 0; e < VW; ++e) v[q][e] = 0.0f;
-    }
+    VLoad<VW>::get(xrow + (d0 < L ? d0 : 0), v[q]);
   }
 }
-
 
 // One block per (row chunk, cell slice), slices of one chunk adjacent.  Rows
 // stream in batches of kBatch.  With one slice every row is added: a group
@@ -181,10 +178,11 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
         float v[kUnroll][DPL][VW];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          const int64_t m = gb + i0 + u;
           const bool on = (i0 + u < PER) && (g * PER + i0 + u < nb);
-          k[u] = on ? idx[m] : -1;
-          load_dims<G, VW, DPL>(X + m * L, L, gl, on, v[u]);
+          const int64_t m = on ? gb + i0 + u : b0;  // b0: a row of this batch
+          const int kv = idx[m];
+          k[u] = on ? kv : -1;
+          load_dims<G, VW, DPL>(X + m * L, L, gl, v[u]);
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
@@ -192,13 +190,17 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
             add_row<G, VW, DPL>(my_acc, my_cnt, nullptr, k[u] - k0, L, gl, s, v[u]);
       }
     } else {
+      int kr[kBatch / kT];
+#pragma unroll
+      for (int u = 0; u < kBatch / kT; ++u) {  // loads first, all in flight
+        const int r = u * kT + t;
+        kr[u] = idx[b0 + (r < nb ? r : 0)];
+      }
 #pragma unroll
       for (int u = 0; u < kBatch / kT; ++u) {
         const int r = u * kT + t;
-        if (r < nb) {
-          const int k = idx[b0 + r];
-          if (k >= k0 && k < k1) slist[atomicAdd(&snsel, 1)] = r * 8192 + (k - k0);
-        }
+        const int k = kr[u];
+        if (r < nb && k >= k0 && k < k1) slist[atomicAdd(&snsel, 1)] = r * 8192 + (k - k0);
       }
       __syncthreads();
       const int nsel = snsel;
@@ -211,7 +213,7 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
           const int packed = (e < nsel) ? slist[e] : -1;
           const int r = packed >= 0 ? packed >> 13 : 0;
           kk[u] = packed >= 0 ? (packed & 8191) : -1;
-          load_dims<G, VW, DPL>(X + (b0 + r) * L, L, gl, packed >= 0, v[u]);
+          load_dims<G, VW, DPL>(X + (b0 + r) * L, L, gl, v[u]);
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
@@ -280,32 +282,42 @@ __device__ __forceinline__ void fin_body(const unsigned long long* __restrict__ 
   __shared__ unsigned long long red[kT];
   __shared__ long long scount;
   const int t = threadIdx.x;
-  if (t < 64) {
-    long long c = 0;
-    for (int ch = t; ch < nchunks; ch += 64) c += pcnt[(int64_t)ch * N + k];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
-    if (t == 0) scount = c;
-  }
   int G2 = 1;
   while (G2 < L && G2 < kT) G2 <<= 1;
   const int Q = kT / G2;
-  __syncthreads();
-  const long long cnt = scount;
-  if (counts && t == 0) counts[k] = (int32_t)cnt;
+  // the count and the first dimension block's partials are loaded together
+  long long c = 0;
+  if (t < 64) {
+    int ch = t;
+    for (; ch + 3 * 64 < nchunks; ch += 4 * 64) {  // four loads in flight
+      const int c0 = pcnt[(int64_t)ch * N + k], c1 = pcnt[(int64_t)(ch + 64) * N + k];
+      const int c2 = pcnt[(int64_t)(ch + 128) * N + k], c3 = pcnt[(int64_t)(ch + 192) * N + k];
+      c += (long long)c0 + c1 + c2 + c3;
+    }
+    for (; ch < nchunks; ch += 64) c += pcnt[(int64_t)ch * N + k];
+  }
   for (int d0 = 0; d0 < L; d0 += G2) {
     const int q = t / G2, d = d0 + t % G2;
-    unsigned long long a0 = 0, a1 = 0;
-    if (d < L && cnt > 0) {
+    unsigned long long a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (d < L) {
       int ch = q;
-      for (; ch + Q < nchunks; ch += 2 * Q) {
-        a0 += part[((int64_t)ch * N + k) * L + d];
-        a1 += part[((int64_t)(ch + Q) * N + k) * L + d];
+      for (; ch + 7 * Q < nchunks; ch += 8 * Q) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += part[((int64_t)(ch + u * Q) * N + k) * L + d];
       }
-      if (ch < nchunks) a0 += part[((int64_t)ch * N + k) * L + d];
+      for (; ch < nchunks; ch += Q) a[0] += part[((int64_t)ch * N + k) * L + d];
     }
-    red[t] = a0 + a1;
+    if (d0 == 0) {
+      if (t < 64) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+        if (t == 0) scount = c;
+      }
+    }
+    red[t] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     __syncthreads();
+    const long long cnt = scount;
+    if (d0 == 0 && counts && t == 0) counts[k] = (int32_t)cnt;
     if (t < G2 && d < L) {
       const int64_t e = (int64_t)k * L + d;
       if (cnt == 0) {

@@ -670,16 +670,21 @@ __device__ __forceinline__ void tile_partial(const double* sD, double* dpart, in
 // Copy ``bytes`` (multiple of 16) from global to LDS, eight 16-byte loads in
 // flight per thread before their stores.
 __device__ __forceinline__ void stage(const void* __restrict__ src, void* dst, int bytes) {
-  const uint4* s = reinterpret_cast<const uint4*>(src);
-  uint4* d = reinterpret_cast<uint4*>(dst);
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4* s = reinterpret_cast<const u32x4*>(src);
+  u32x4* d = reinterpret_cast<u32x4*>(dst);
   const int nv = bytes >> 4;
   for (int base = 0; base < nv; base += 8 * kAssignThreads) {
-    uint4 v[8];
+    u32x4 v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = base + u * kAssignThreads + threadIdx.x;
-      v[u] = e < nv ? s[e] : make_uint4(0u, 0u, 0u, 0u);
+      v[u] = s[e < nv ? e : 0];
     }
+    // the loads are used here unconditionally, so the compiler cannot sink
+    // them into the stores' branches (one wait for all eight, not eight)
+    asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]),
+                 "v"(v[6]), "v"(v[7]));
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = base + u * kAssignThreads + threadIdx.x;
@@ -703,13 +708,19 @@ __device__ __forceinline__ void stage_from_C(const float* __restrict__ C, int n,
     const int nv = n_pad * Q;
     for (int base = 0; base < nv; base += 4 * kAssignThreads) {
       float4 v[4];
+      bool on[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int e = base + u * kAssignThreads + threadIdx.x;
-        const int r = e / Q;
-        v[u] = (e < nv && r < n) ? *reinterpret_cast<const float4*>(C + (int64_t)e * 4)
-                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+        on[u] = e < nv && e / Q < n;
+        v[u] = *reinterpret_cast<const float4*>(C + (int64_t)(on[u] ? e : 0) * 4);
       }
+      // used unconditionally: the four loads stay in flight together instead
+      // of being sunk into (and waited for in) the branches below
+      asm volatile("" ::"v"(v[0].x), "v"(v[1].x), "v"(v[2].x), "v"(v[3].x));
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (!on[u]) v[u] = make_float4(0.f, 0.f, 0.f, 0.f);  // padding rows
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int e = base + u * kAssignThreads + threadIdx.x;

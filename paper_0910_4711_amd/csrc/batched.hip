@@ -2,12 +2,13 @@
 // N), advanced together one Lloyd iteration per round (Algorithm 1 for every
 // instance).  A round is three launches for all instances:
 //
-//   b_assign  persistent: workgroups take allocation items from a queue (an
-//             item is one instance's slot b; a workgroup takes `grab` items
-//             per queue access), stage that instance's codebook into LDS and
-//             run the allocation of the tiles b, b + G, b + 2G, ... exactly as
-//             the single-run kernel's workgroup b does (same tiles, same
-//             per-wave partial sums, so the same distortion).
+//   b_assign  persistent: workgroups take chunks of up to `grab` slots of
+//             one instance from a queue (slot b = the tiles b, b + G, b + 2G,
+//             ... of the single-run kernel's workgroup b), stage that
+//             instance's codebook into LDS and run the allocation of those
+//             tiles exactly as the single-run kernel does (same tiles, same
+//             per-wave partial sums, so the same distortion), each wave
+//             loading its next tile's rows while screening the current one.
 //   b_acc     one workgroup per (instance, row chunk, cell slice): every
 //             instance's decision from its own partials, then the fixed-point
 //             cell sums (integers: exact, order-free).
@@ -95,12 +96,14 @@ __device__ __forceinline__ int find_inst(const int64_t* __restrict__ pre, int n,
 }
 
 // ------------------------------------------------------------- allocation --
-// Slot b of instance B: the tiles and partials of the single-run kernel's
-// workgroup b.  The codebook is staged unless this workgroup staged the same
-// one last.
+// Slots [b0, b0 + cnt) of instance B: for each slot b the tiles b, b + G, ...
+// and partials of the single-run kernel's workgroup b.  Each wave walks its
+// rows of those tiles in order, loading the next tile's rows while the
+// current one is screened.  The codebook is staged unless this workgroup
+// staged the same one last.
 template <class SC, bool VEC>
-__device__ __forceinline__ void alloc_item(const BInst& B, const DevState* st, int b, int i,
-                                           int* staged, unsigned char* smem) {
+__device__ __forceinline__ void alloc_chunk(const BInst& B, const DevState* st, int b0, int cnt,
+                                            int i, int* staged, unsigned char* smem) {
   constexpr int LP = SC::LP;
   constexpr bool PF = LP <= 32;
   typedef typename SC::elem E;
@@ -111,64 +114,73 @@ __device__ __forceinline__ void alloc_item(const BInst& B, const DevState* st, i
   const int L = VEC ? LP : B.L;
   const int key = (i << 1) | cb;
   if (*staged != key) {
-    __syncthreads();  // the previous item's waves are done with the LDS copy
+    __syncthreads();  // the previous chunk's waves are done with the LDS copy
     stage_from_C<SC, VEC>(C, n, L, n_pad, sA);
     *staged = key;
   }
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const WaveCtx w = wave_ctx(L, tile_bits_of(n));
+  const int G = B.G;
+  const int64_t nt = B.ntiles;
   float xv[LP / 2];
+  int b = b0;
   int64_t rt = b;
-  if (PF && rt < B.ntiles)
-    load_x<LP, VEC>(B.X, B.M, L, rt * kRowsPerTile + (int64_t)wave * 32, w.h, w.j, xv);
+  if (PF) load_x<LP, VEC>(B.X, B.M, L, rt * kRowsPerTile + (int64_t)wave * 32, w.h, w.j, xv);
   double wsum = 0.0;
-  for (; rt < B.ntiles; rt += B.G) {
+  for (;;) {
+    // the tile after (b, rt): the slot's next tile, else the next slot's first
+    int nb = b;
+    int64_t nrt = rt + G;
+    if (nrt >= nt) {
+      nb = b + 1;
+      nrt = nb;
+    }
+    const bool more = nb < b0 + cnt;
     const int64_t row0 = rt * kRowsPerTile + (int64_t)wave * 32;
     if (!PF) load_x<LP, VEC>(B.X, B.M, L, row0, w.h, w.j, xv);
-    const int64_t next = (PF && rt + B.G < B.ntiles) ? row0 + (int64_t)B.G * kRowsPerTile : -1;
+    const int64_t next = (PF && more) ? nrt * kRowsPerTile + (int64_t)wave * 32 : -1;
     wsum += process_rows<SC, VEC, PF>(xv, B.X, B.M, L, row0, next, C, n, n_pad, n_pad, true,
                                       nullptr, sA, B.idx, nullptr, B.nfb, w);
+    if (nb != b) {
+      const double ws = wave_sum(wsum);
+      if (lane == 0) B.dpart[b * 4 + wave] = ws;
+      wsum = 0.0;
+    }
+    if (!more) break;
+    b = nb;
+    rt = nrt;
   }
-  wsum = wave_sum(wsum);
-  if (lane == 0) B.dpart[b * 4 + wave] = wsum;
 }
 
+// Persistent: workgroups take chunks (instance, first slot, slot count) from
+// the queue until none is left.
 __global__ __launch_bounds__(kT, 2) void b_assign_kernel(const BInst* __restrict__ inst,
-                                                         int n_inst,
-                                                         const int64_t* __restrict__ pre,
-                                                         int grab, unsigned* __restrict__ qctr) {
+                                                         const int32_t* __restrict__ chunks,
+                                                         int nchunks, unsigned* __restrict__ qctr) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ int64_t s_first;
-  const int64_t* item_pre = pre + (int64_t)kPreItem * (n_inst + 1);
-  const int64_t total = item_pre[n_inst];
+  __shared__ int s_c;
   int staged = -1;
   for (;;) {
-    __syncthreads();  // s_first of the previous access has been read
-    if (threadIdx.x == 0) s_first = (int64_t)atomicAdd(qctr, (unsigned)grab);
+    __syncthreads();  // s_c of the previous access has been read
+    if (threadIdx.x == 0) s_c = (int)atomicAdd(qctr, 1u);
     __syncthreads();
-    const int64_t first = s_first;
-    if (first >= total) break;
-    const int64_t last = min(total, first + grab);
-    int i = find_inst(item_pre, n_inst, first);  // once per queue access
-    int64_t next_start = item_pre[i + 1];
-    for (int64_t it = first; it < last; ++it) {
-      while (it >= next_start) next_start = item_pre[++i + 1];
-      const BInst& B = inst[i];
-      const DevState* st = B.st;
-      if (st->done) continue;
-      const int b = (int)(it - item_pre[i]);
-      if (B.LP == 16) {
-        if (B.vec)
-          alloc_item<Fp32Screen<16>, true>(B, st, b, i, &staged, smem);
-        else
-          alloc_item<Fp32Screen<16>, false>(B, st, b, i, &staged, smem);
-      } else {
-        if (B.vec)
-          alloc_item<Fp32Screen<64>, true>(B, st, b, i, &staged, smem);
-        else
-          alloc_item<Fp32Screen<64>, false>(B, st, b, i, &staged, smem);
-      }
+    const int c = s_c;
+    if (c >= nchunks) break;
+    const int i = chunks[3 * c], b0 = chunks[3 * c + 1], cnt = chunks[3 * c + 2];
+    const BInst& B = inst[i];
+    const DevState* st = B.st;
+    if (st->done) continue;
+    if (B.LP == 16) {
+      if (B.vec)
+        alloc_chunk<Fp32Screen<16>, true>(B, st, b0, cnt, i, &staged, smem);
+      else
+        alloc_chunk<Fp32Screen<16>, false>(B, st, b0, cnt, i, &staged, smem);
+    } else {
+      if (B.vec)
+        alloc_chunk<Fp32Screen<64>, true>(B, st, b0, cnt, i, &staged, smem);
+      else
+        alloc_chunk<Fp32Screen<64>, false>(B, st, b0, cnt, i, &staged, smem);
     }
   }
 }
@@ -186,7 +198,9 @@ __global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ ins
   const int64_t local = (int64_t)blockIdx.x - acc_pre[i];
   const Ctl ctl{B.st, B.pend, B.dpart, 4 * (int64_t)B.G, B.Dtrace, B.Atrace};
   int N = B.N;
-  if (!afp::acc_decide(ctl, local == 0, &N)) return;
+  if (B.st->done) return;
+  if (local == 0) (void)afp::acc_decide(ctl, true, &N);  // the instance's decision
+  N = B.st->n;
   const int s = *B.shift;
   const int L = B.L;
 #define LBG_BACC(GG, VV)                                                                    \
@@ -339,6 +353,7 @@ struct BatchWs {
   unsigned long long* nfb;  // n
   int32_t* b2i;             // block -> instance tables
   int64_t b2i_n;
+  int32_t* chunks;          // allocation chunks (instance, first slot, slots)
   int64_t tot[kNumPre];     // blocks (items) of each family
   std::vector<InstPlan> plans;
 };
@@ -404,6 +419,21 @@ void plan_batch(Carver& c, const lbg_instance* in, int n, BatchWs* w) {
   for (int k = 0; k < kNumPre; ++k)
     if (k != kPreItem) w->b2i_n += w->tot[k];
   w->b2i = c.take<int32_t>((size_t)w->b2i_n);
+  w->chunks = c.take<int32_t>((size_t)(3 * w->tot[kPreItem]));
+}
+
+// Allocation chunks of at most ``grab`` slots, never spanning two instances,
+// in instance order.  Returns their number.
+int build_chunks(const std::vector<InstPlan>& plans, int grab, int32_t* out) {
+  int nc = 0;
+  for (size_t i = 0; i < plans.size(); ++i)
+    for (int b0 = 0; b0 < plans[i].G; b0 += grab) {
+      out[3 * nc] = (int32_t)i;
+      out[3 * nc + 1] = b0;
+      out[3 * nc + 2] = std::min(grab, plans[i].G - b0);
+      ++nc;
+    }
+  return nc;
 }
 
 // Pinned host staging for the descriptors and states of one call.
@@ -429,11 +459,13 @@ struct Launch {
   int64_t blocks[kNumPre];  // totals
   unsigned* ctr;
   size_t acc_lds;
+  const int32_t* chunks;    // device chunk table for the current grab
+  int nchunks;
 };
 
-int launch_round(const Launch& l, int grab, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(b_assign_kernel, dim3((unsigned)grid), dim3(kT), kBatchLds, s, l.inst, l.n,
-                     l.pre, grab, l.ctr);
+int launch_round(const Launch& l, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(b_assign_kernel, dim3((unsigned)grid), dim3(kT), kBatchLds, s, l.inst,
+                     l.chunks, l.nchunks, l.ctr);
   LBG_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(b_acc_kernel, dim3((unsigned)l.blocks[kPreAcc]), dim3(kT), l.acc_lds, s,
                      l.inst, l.n, l.pre, l.tb);
@@ -456,7 +488,8 @@ struct TuneKey {
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<int, int>> g_tune;
 
-int autotune(const Launch& l, hipStream_t s, int* grab_out, int* grid_out, double* ms_out) {
+int autotune(Launch l, const std::vector<InstPlan>& plans, int32_t* chunk_host,
+             int32_t* chunk_dev, hipStream_t s, int* grab_out, int* grid_out, double* ms_out) {
   static const int grabs[] = {1, 2, 4, 8, 16};
   static const int grids[] = {256, 512};
   hipLaunchKernelGGL(b_tune_setup_kernel, dim3((unsigned)l.blocks[kPreFin]), dim3(kT), 0, s,
@@ -469,15 +502,24 @@ int autotune(const Launch& l, hipStream_t s, int* grab_out, int* grid_out, doubl
   int bg = 4, bgrid = 512;
   double total = 0.0;
   int rc = LBG_OK;
-  for (int gr : grids)
-    for (int g : grabs) {
+  for (int g : grabs) {
+    if (rc != LBG_OK) break;
+    // the previous candidate's copy has completed (its timing synchronised)
+    l.nchunks = build_chunks(plans, g, chunk_host);
+    const hipError_t ec = hipMemcpyAsync(chunk_dev, chunk_host, sizeof(int32_t) * 3 * l.nchunks,
+                                         hipMemcpyHostToDevice, s);
+    if (ec != hipSuccess) {
+      rc = hip_fail(ec, "autotune");
+      break;
+    }
+    for (int gr : grids) {
       float ms_min = 1e30f;
       for (int rep = 0; rep < 3 && rc == LBG_OK; ++rep) {
         hipError_t e = hipMemsetAsync(l.ctr, 0, sizeof(unsigned), s);
         if (e == hipSuccess) e = hipEventRecord(e0, s);
         if (e == hipSuccess) {
           hipLaunchKernelGGL(b_assign_kernel, dim3((unsigned)gr), dim3(kT), kBatchLds, s, l.inst,
-                             l.n, l.pre, g, l.ctr);
+                             l.chunks, l.nchunks, l.ctr);
           e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipEventRecord(e1, s);
@@ -497,6 +539,7 @@ int autotune(const Launch& l, hipStream_t s, int* grab_out, int* grid_out, doubl
         bgrid = gr;
       }
     }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *grab_out = bg;
@@ -513,6 +556,7 @@ struct BGraph {
   int n = 0, grab = 0, grid = 0;
   int64_t blocks[kNumPre] = {};
   size_t acc_lds = 0;
+  int nchunks = 0;
   hipGraphExec_t exec = nullptr;
   uint64_t stamp = 0;
 };
@@ -524,7 +568,7 @@ int get_graph(const Launch& l, const void* ws, int grab, int grid, hipStream_t s
               hipGraphExec_t* out) {
   for (auto& e : g_bgraph)
     if (e.used && e.ws == ws && e.stream == s && e.n == l.n && e.grab == grab &&
-        e.grid == grid && e.acc_lds == l.acc_lds &&
+        e.grid == grid && e.acc_lds == l.acc_lds && e.nchunks == l.nchunks &&
         memcmp(e.blocks, l.blocks, sizeof(e.blocks)) == 0) {
       e.stamp = ++g_bstamp;
       *out = e.exec;
@@ -543,7 +587,7 @@ int get_graph(const Launch& l, const void* ws, int grab, int grid, hipStream_t s
   hipGraph_t g = nullptr;
   LBG_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   int rc = LBG_OK;
-  for (int r = 0; r < kRoundsPerGraph && rc == LBG_OK; ++r) rc = launch_round(l, grab, grid, s);
+  for (int r = 0; r < kRoundsPerGraph && rc == LBG_OK; ++r) rc = launch_round(l, grid, s);
   const hipError_t e = hipStreamEndCapture(s, &g);
   if (rc != LBG_OK) {
     if (g) (void)hipGraphDestroy(g);
@@ -562,6 +606,7 @@ int get_graph(const Launch& l, const void* ws, int grab, int grid, hipStream_t s
   slot->grid = grid;
   memcpy(slot->blocks, l.blocks, sizeof(slot->blocks));
   slot->acc_lds = l.acc_lds;
+  slot->nchunks = l.nchunks;
   slot->exec = ex;
   slot->stamp = ++g_bstamp;
   *out = ex;
@@ -697,7 +742,8 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
   const size_t b_pre = sizeof(int64_t) * (size_t)kNumPre * (n + 1);
   const size_t b_st = sizeof(DevState) * (size_t)n;
   const size_t b_tab = sizeof(int32_t) * (size_t)w.b2i_n;
-  unsigned char* host = pinned_stage(b_inst + b_pre + b_st + 64 + b_tab);
+  const size_t b_chunk = sizeof(int32_t) * 3 * (size_t)w.tot[kPreItem];
+  unsigned char* host = pinned_stage(b_inst + b_pre + b_st + 64 + b_tab + b_chunk);
   if (!host) {
     set_error("lbg_train_batched: could not allocate pinned host memory");
     return LBG_EHIP;
@@ -803,7 +849,8 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
       off += tot[k];
     }
   }
-  Launch l{w.inst, n, w.pre, tb, {}, w.ctr, acc_lds};
+  int32_t* hchunk = reinterpret_cast<int32_t*>(host + b_inst + b_pre + b_st + 64 + b_tab);
+  Launch l{w.inst, n, w.pre, tb, {}, w.ctr, acc_lds, w.chunks, 0};
   for (int k = 0; k < kNumPre; ++k) l.blocks[k] = tot[k];
 
   static const hipError_t lds_ok = hipFuncSetAttribute(
@@ -829,13 +876,18 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
     } else {
       int tg = 0, tgrid = 0;
       LBG_TRY_HIP(hipMemsetAsync(w.st, 0, b_st, s));
-      LBG_TRY(autotune(l, s, &tg, &tgrid, &ms_tune));
+      LBG_TRY(autotune(l, w.plans, hchunk, w.chunks, s, &tg, &tgrid, &ms_tune));
       g_tune[key] = {tg, tgrid};
       tuned = true;
       if (grab == 0) grab = tg;
       if (grid == 0) grid = tgrid;
     }
   }
+
+  // the allocation chunks for the chosen grab
+  l.nchunks = build_chunks(w.plans, grab, hchunk);
+  LBG_TRY_HIP(hipMemcpyAsync(w.chunks, hchunk, sizeof(int32_t) * 3 * l.nchunks,
+                             hipMemcpyHostToDevice, s));
 
   // set-up: states, counters, centroids and first split, fixed-point shifts
   LBG_TRY_HIP(hipMemcpyAsync(w.st, hs, b_st, hipMemcpyHostToDevice, s));
@@ -879,7 +931,7 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
     if (use_graph) {
       LBG_TRY_HIP(hipGraphLaunch(gexec, s));
     } else {
-      for (int r = 0; r < per_poll; ++r) LBG_TRY(launch_round(l, grab, grid, s));
+      for (int r = 0; r < per_poll; ++r) LBG_TRY(launch_round(l, grid, s));
     }
     rounds += per_poll;
     LBG_TRY_HIP(hipMemcpyAsync(ndone_host, w.ctr + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));

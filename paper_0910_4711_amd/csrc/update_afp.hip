@@ -47,7 +47,13 @@ __global__ __launch_bounds__(kT) void acc_kernel(
   extern __shared__ unsigned long long sacc[];
   __shared__ int32_t slist[kBatch];
   __shared__ int32_t snsel;
-  if (ctl.st && !acc_decide(ctl, blockIdx.x == 0, &N)) return;
+  if (ctl.st) {
+    // the decision (block 0 writes it for the update's last kernel) does not
+    // change what is accumulated, so the other blocks do not wait for it
+    if (ctl.st->done) return;
+    if (blockIdx.x == 0) (void)acc_decide(ctl, true, &N);
+    N = ctl.st->n;
+  }
   acc_body<G, VW, DPL>(X, M, L, idx, N, cps, nslices, rows_per_chunk, *shift_p, part, pcnt,
                        blockIdx.x, sacc, slist, snsel);
 }
