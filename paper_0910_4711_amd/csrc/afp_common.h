@@ -20,11 +20,38 @@ __device__ __forceinline__ void absmax_body(const float* __restrict__ X, int64_t
                                             uint32_t* __restrict__ part, int64_t block,
                                             int64_t nblocks) {
   __shared__ uint32_t s[kT];
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   uint32_t m = 0;
-  for (int64_t i = block * kT + threadIdx.x; i < n; i += nblocks * kT) {
-    const uint32_t b = __float_as_uint(X[i]) & 0x7fffffffu;
+  auto upd = [&m](uint32_t b) {
+    b &= 0x7fffffffu;
     m = (b > m && b < 0x7f800000u) ? b : m;  // ignore Inf / NaN
+  };
+  // 16-byte loads, four per thread in flight, then the scalar tail
+  const int64_t nv = (reinterpret_cast<uintptr_t>(X) & 15) == 0 ? n / 4 : 0;
+  const u32x4* X4 = reinterpret_cast<const u32x4*>(X);
+  const int64_t stride = nblocks * kT;
+  int64_t i = block * kT + threadIdx.x;
+  for (; i + 3 * stride < nv; i += 4 * stride) {
+    u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = X4[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      upd(v[u].x);
+      upd(v[u].y);
+      upd(v[u].z);
+      upd(v[u].w);
+    }
   }
+  for (; i < nv; i += stride) {
+    const u32x4 v = X4[i];
+    upd(v.x);
+    upd(v.y);
+    upd(v.z);
+    upd(v.w);
+  }
+  for (int64_t e = 4 * nv + block * kT + threadIdx.x; e < n; e += stride)
+    upd(__float_as_uint(X[e]));
   s[threadIdx.x] = m;
   __syncthreads();
   for (int off = kT / 2; off > 0; off >>= 1) {

@@ -491,13 +491,13 @@ int lbg_train(const float* X, int64_t M, int64_t L, int64_t N, const lbg_params*
   }
 
   if (w.up.use_afp) LBG_TRY(launch_afp_shift(X, M, L, w.up.afp, s));
-  const int64_t nparts = assign_num_parts(M, L, p->precision);
   auto assign_and_D = [&](double* Dh) -> int {
     LBG_TRY(tm.begin(Timer::kAssign, s));
     LBG_TRY(launch_assign(X, M, L, w.Cb[cur], n, idx_out, nullptr, p->precision,
                           w.as.dpart, w.as.nfb, w.as.prep, s));
     LBG_TRY(tm.end(s));
-    LBG_TRY(launch_reduce_parts(w.as.dpart, nparts, (double)M, w.D, s));
+    LBG_TRY(launch_reduce_parts(w.as.dpart, assign_num_parts(M, L, n, p->precision), (double)M,
+                                w.D, s));
     LBG_TRY(read_scalar(w.D, Dh, s));
     LBG_TRY(tm.collect());
     if (st) {

@@ -49,7 +49,8 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr float kBig = 3.0e38f;    // squared norm of padding codevectors
-constexpr int kRowsPerTile = 128;  // training vectors per workgroup row tile
+constexpr int kRowsPerTile = 128;  // training vectors per four-wave row tile
+constexpr int kWideLds = 163840;   // LDS of a CU: one eight-wave workgroup
 
 // Row of the 32 x 32 matrix-core result held in accumulator register r of
 // ``lane``: four groups of four rows, the two half-waves interleaved by four.
@@ -69,6 +70,7 @@ struct Fp32Screen {
   static constexpr int NS = LP / 2;  // data K-steps per tile (half per lane half)
   static constexpr int OCC = LP <= 16 ? 3 : 2;
   static constexpr bool EXACT = true;
+  static constexpr bool PF = LP <= 32;  // registers for the next tile's vectors
   typedef float elem;
 };
 
@@ -80,6 +82,7 @@ struct Bf16Screen {
   static constexpr int NS = LP / 16;
   static constexpr int OCC = LP <= 16 ? 4 : (LP <= 32 ? 3 : 2);
   static constexpr bool EXACT = false;
+  static constexpr bool PF = LP <= 64;
   typedef __bf16 elem;
 };
 
@@ -352,54 +355,6 @@ __device__ __forceinline__ double d64(const float* x, const float* c, int L) {
   return s;
 }
 
-// Dimensions [l0, l0 + W) of the same sum, continuing from s; the rows are
-// read W elements at a time (zero beyond L).
-template <int W, bool VEC>
-__device__ __forceinline__ double d64_part(const float* __restrict__ x,
-                                           const float* __restrict__ c, int l0, int L,
-                                           double s) {
-  float xa[W], ca[W];
-  if (VEC) {
-#pragma unroll
-    for (int q = 0; q < W; q += 4) {
-      const float4 a = *reinterpret_cast<const float4*>(x + l0 + q);
-      const float4 b = *reinterpret_cast<const float4*>(c + l0 + q);
-      xa[q] = a.x; xa[q + 1] = a.y; xa[q + 2] = a.z; xa[q + 3] = a.w;
-      ca[q] = b.x; ca[q + 1] = b.y; ca[q + 2] = b.z; ca[q + 3] = b.w;
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < W; ++q) {
-      xa[q] = (l0 + q < L) ? x[l0 + q] : 0.0f;
-      ca[q] = (l0 + q < L) ? c[l0 + q] : 0.0f;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < W; ++q) {
-    if (l0 + q < L) {
-      const double t = (double)xa[q] - (double)ca[q];
-      s = s + t * t;
-    }
-  }
-  return s;
-}
-
-// Squared distance of two rows in memory, streamed 16 dimensions at a time
-// (rows of exactly LP floats) or one at a time.
-template <int LP, bool VEC>
-__device__ __forceinline__ double d64_mem(const float* __restrict__ x,
-                                          const float* __restrict__ c, int L) {
-  if constexpr (!VEC) {
-    return d64(x, c, L);
-  } else {
-    constexpr int W = LP < 16 ? LP : 16;
-    double s = 0.0;
-#pragma unroll
-    for (int l0 = 0; l0 < LP; l0 += W) s = d64_part<W, true>(x, c, l0, L, s);
-    return s;
-  }
-}
-
 // Rescore, decide, fall back and store for the vectors of this wave; lane
 // (j, 1) finishes vector j.
 //   EXACT (FP32 screen): accept the best candidate w only if
@@ -555,6 +510,37 @@ __device__ __forceinline__ void c_half(const float* __restrict__ C, int L,
   }
 }
 
+// FP64 squared distance of vector j to the codevector whose half-rows the
+// pair (j, 0), (j, 1) holds in cr, summed over the dimensions in order: lane
+// (j, 0) sums the first half, lane (j, 1) continues from that partial sum
+// (the result is valid in lane (j, 1)).
+template <int LP>
+__device__ __forceinline__ double pair_dist(const float (&xv)[LP / 2], const float (&cr)[LP / 2],
+                                            int L) {
+  double s0 = 0.0;
+#pragma unroll
+  for (int q = 0; q < LP / 2; ++q) {
+    if (q < L) {
+      const double u = (double)xv[q] - (double)cr[q];
+      s0 = s0 + u * u;
+    }
+  }
+  const uint64_t b0 = (uint64_t)__double_as_longlong(s0);
+  float lo_a, hi_a, lo_b, hi_b;
+  pair_values(__uint_as_float((uint32_t)b0), lo_a, hi_a);
+  pair_values(__uint_as_float((uint32_t)(b0 >> 32)), lo_b, hi_b);
+  double s1 = __longlong_as_double(
+      (long long)(((uint64_t)__float_as_uint(lo_b) << 32) | __float_as_uint(lo_a)));
+#pragma unroll
+  for (int q = 0; q < LP / 2; ++q) {
+    if (LP / 2 + q < L) {
+      const double u = (double)xv[q] - (double)cr[q];
+      s1 = s1 + u * u;
+    }
+  }
+  return s1;
+}
+
 // Returns the winning distance of the vector this lane finished (0 for the
 // other lanes).  xv: lane (j, h) holds dimensions [h LP/2, (h+1) LP/2) of
 // vector j (FP32); xsq: the vector's squared norm (FP32).  Lane (j, 0) sums
@@ -586,29 +572,7 @@ __device__ __forceinline__ double finish_rows(const Slots& sl, const float* __re
   if constexpr (SC::EXACT) {
     float cr[LP / 2];
     c_half<SC, VEC>(C, L, reinterpret_cast<const float*>(resident), win, h, cr);
-    double s0 = 0.0;
-#pragma unroll
-    for (int q = 0; q < LP / 2; ++q) {
-      if (q < L) {
-        const double u = (double)xv[q] - (double)cr[q];
-        s0 = s0 + u * u;
-      }
-    }
-    // lane (j, 1) continues from lane (j, 0)'s partial sum
-    const uint64_t b0 = (uint64_t)__double_as_longlong(s0);
-    float lo_a, hi_a, lo_b, hi_b;
-    pair_values(__uint_as_float((uint32_t)b0), lo_a, hi_a);
-    pair_values(__uint_as_float((uint32_t)(b0 >> 32)), lo_b, hi_b);
-    double s1 = __longlong_as_double(
-        (long long)(((uint64_t)__float_as_uint(lo_b) << 32) | __float_as_uint(lo_a)));
-#pragma unroll
-    for (int q = 0; q < LP / 2; ++q) {
-      if (LP / 2 + q < L) {
-        const double u = (double)xv[q] - (double)cr[q];
-        s1 = s1 + u * u;
-      }
-    }
-    d = s1;
+    d = pair_dist<LP>(xv, cr, L);
     if (live) {
       const float rf = 2.0f * __builtin_sqrtf(xsq) + __builtin_sqrtf((float)d);
       const double E = (double)(bd.cE * rf * rf) + 1e-30;
@@ -616,17 +580,20 @@ __device__ __forceinline__ double finish_rows(const Slots& sl, const float* __re
       flag = bad || !(d * bd.dslack < lim);
     }
   } else {
-    if (live) {
-      const float* xrow = X + m * (int64_t)L;
-      d = d64_mem<LP, VEC>(xrow, C + (int64_t)win * L, L);
-      const int i2 = t.i2;
-      if (i2 >= 0 && i2 < n && i2 != win) {
-        const double d2 = d64_mem<LP, VEC>(xrow, C + (int64_t)i2 * L, L);
-        if (d2 < d || (d2 == d && i2 < win)) {
-          d = d2;
-          win = i2;
-        }
-      }
+    // both candidates' half-rows loaded together, then the two distances
+    // (the pair holds the same candidates)
+    int i2 = t.i2;
+    const bool two = i2 >= 0 && i2 < n && i2 != win;
+    if (!two) i2 = win;
+    float ca[LP / 2], cb[LP / 2];
+    c_half<SC, VEC>(C, L, nullptr, win, h, ca);
+    c_half<SC, VEC>(C, L, nullptr, i2, h, cb);
+    const double da = pair_dist<LP>(xv, ca, L);
+    const double db = pair_dist<LP>(xv, cb, L);
+    d = da;
+    if (two && (db < da || (db == da && i2 < win))) {
+      d = db;
+      win = i2;
     }
   }
   if constexpr (SC::EXACT) {
@@ -667,18 +634,19 @@ __device__ __forceinline__ void tile_partial(const double* sD, double* dpart, in
   }
 }
 
-// Copy ``bytes`` (multiple of 16) from global to LDS, eight 16-byte loads in
-// flight per thread before their stores.
+// Copy ``bytes`` (multiple of 16) from global to LDS with the NT threads of
+// the workgroup, eight 16-byte loads in flight per thread before their stores.
+template <int NT = kAssignThreads>
 __device__ __forceinline__ void stage(const void* __restrict__ src, void* dst, int bytes) {
   typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   const u32x4* s = reinterpret_cast<const u32x4*>(src);
   u32x4* d = reinterpret_cast<u32x4*>(dst);
   const int nv = bytes >> 4;
-  for (int base = 0; base < nv; base += 8 * kAssignThreads) {
+  for (int base = 0; base < nv; base += 8 * NT) {
     u32x4 v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int e = base + u * kAssignThreads + threadIdx.x;
+      const int e = base + u * NT + threadIdx.x;
       v[u] = s[e < nv ? e : 0];
     }
     // the loads are used here unconditionally, so the compiler cannot sink
@@ -687,7 +655,7 @@ __device__ __forceinline__ void stage(const void* __restrict__ src, void* dst, i
                  "v"(v[6]), "v"(v[7]));
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int e = base + u * kAssignThreads + threadIdx.x;
+      const int e = base + u * NT + threadIdx.x;
       if (e < nv) d[e] = v[u];
     }
   }
@@ -697,7 +665,7 @@ __device__ __forceinline__ void stage(const void* __restrict__ src, void* dst, i
 // dimensions and n_pad rows, then each row's squared norm (FP64, rounded to
 // FP32) in its padding, as prep_kernel writes it.  Loads are issued four at a
 // time per thread before their stores.
-template <class SC, bool VEC>
+template <class SC, bool VEC, int NT = kAssignThreads>
 __device__ __forceinline__ void stage_from_C(const float* __restrict__ C, int n, int L,
                                              int n_pad, typename SC::elem* sA) {
   constexpr int LP = SC::LP;
@@ -706,12 +674,12 @@ __device__ __forceinline__ void stage_from_C(const float* __restrict__ C, int n,
   if (VEC) {
     constexpr int Q = LP / 4;
     const int nv = n_pad * Q;
-    for (int base = 0; base < nv; base += 4 * kAssignThreads) {
+    for (int base = 0; base < nv; base += 4 * NT) {
       float4 v[4];
       bool on[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int e = base + u * kAssignThreads + threadIdx.x;
+        const int e = base + u * NT + threadIdx.x;
         on[u] = e < nv && e / Q < n;
         v[u] = *reinterpret_cast<const float4*>(C + (int64_t)(on[u] ? e : 0) * 4);
       }
@@ -723,7 +691,7 @@ __device__ __forceinline__ void stage_from_C(const float* __restrict__ C, int n,
         if (!on[u]) v[u] = make_float4(0.f, 0.f, 0.f, 0.f);  // padding rows
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int e = base + u * kAssignThreads + threadIdx.x;
+        const int e = base + u * NT + threadIdx.x;
         if (e < nv) {
           E* dst = sA + (e / Q) * S + (e % Q) * 4;
           dst[0] = (E)(-2.0f * v[u].x);
@@ -734,14 +702,14 @@ __device__ __forceinline__ void stage_from_C(const float* __restrict__ C, int n,
       }
     }
   } else {
-    for (int e = threadIdx.x; e < n_pad * LP; e += kAssignThreads) {
+    for (int e = threadIdx.x; e < n_pad * LP; e += NT) {
       const int r = e / LP, d = e % LP;
       const float v = (r < n && d < L) ? C[(int64_t)r * L + d] : 0.0f;
       sA[r * S + d] = (E)(-2.0f * v);
     }
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < n_pad; r += kAssignThreads) {
+  for (int r = threadIdx.x; r < n_pad; r += NT) {
     double q = 0.0;
 #pragma unroll 8
     for (int d = 0; d < LP; ++d) {
@@ -856,14 +824,18 @@ __device__ __forceinline__ void screen_tiles(const typename SC::elem* ar, int nt
   if (DB && nt > 1) fb.load(ar + TS, h);
   int t = 0;
   for (; t + 2 < nt; t += 2) {
-    // ca: products of tile t; fb: fragments of tile t+1 (DB)
+    // ca: products of tile t; fb: fragments of tile t+1 (DB).  The two
+    // phases stay apart, so that each tile's key updates run beside the
+    // other tile's products instead of after both.
     if (!DB) fb.load(ar + (t + 1) * TS, h);
     fb.mma(xf, xn, cb);
     fa.load(ar + (t + 2) * TS, h);
     sl.push(ca, vmask, tb0 + t, ninf);
+    __builtin_amdgcn_sched_barrier(0);
     fa.mma(xf, xn, ca);
     if (DB) fb.load(ar + min(t + 3, nt - 1) * TS, h);
     sl.push(cb, vmask, tb0 + t + 1, ninf);
+    __builtin_amdgcn_sched_barrier(0);
   }
   if (t + 1 < nt) {
     if (!DB) fb.load(ar + (t + 1) * TS, h);
@@ -934,7 +906,7 @@ __device__ __forceinline__ WaveCtx wave_ctx(int L, int tile_bits) {
 // xv holds this lane's half-row on entry; with PF it receives the half-row
 // of the tile at next_row0 (when >= 0), loaded while the screen runs.
 // Returns this lane's winning distance (0 for lanes that finish no vector).
-template <class SC, bool VEC, bool PF>
+template <class SC, bool VEC, bool PF, int NT = kAssignThreads>
 __device__ __forceinline__ double process_rows(
     float (&xv)[SC::LP / 2], const float* __restrict__ X, int64_t M, int L, int64_t row0,
     int64_t next_row0, const float* __restrict__ C, int n, int n_pad, int CR, bool resident,
@@ -978,12 +950,10 @@ __device__ __forceinline__ double process_rows(
     xn = h ? zv : nv;
   }
   const float xsq = (float)ss;
-  // the FP32 rescore needs this tile's vectors after the screen
+  // the rescore needs this tile's vectors after the screen
   float xk[LP / 2];
-  if constexpr (SC::EXACT) {
 #pragma unroll
-    for (int s = 0; s < LP / 2; ++s) xk[s] = xv[s];
-  }
+  for (int s = 0; s < LP / 2; ++s) xk[s] = xv[s];
   if (PF && next_row0 >= 0) load_x<LP, VEC>(X, M, L, next_row0, h, j, xv);
 
   Slots sl;
@@ -992,7 +962,7 @@ __device__ __forceinline__ double process_rows(
     const int cr = min(CR, n_pad - c0);
     if (!resident) {
       __syncthreads();
-      stage(Cp + (int64_t)c0 * S, sA, cr * S * SC::ESZ);
+      stage<NT>(Cp + (int64_t)c0 * S, sA, cr * S * SC::ESZ);
       __syncthreads();
     }
     const E* base = resident ? sA + (int64_t)c0 * S : sA;
@@ -1003,8 +973,10 @@ __device__ __forceinline__ double process_rows(
                               resident ? sA : nullptr, xk, xsq, w.bd, w.ninf);
 }
 
-template <class SC, bool VEC>
-__global__ __launch_bounds__(kAssignThreads, SC::OCC) void assign_kernel(
+// W waves per workgroup: 4 (OCC workgroups per CU), or 8 with one workgroup
+// per CU holding a codebook of up to kWideLds bytes resident.
+template <class SC, bool VEC, int W>
+__global__ __launch_bounds__(64 * W, W == 4 ? SC::OCC : 1) void assign_kernel(
     const float* __restrict__ X, int64_t M, int L, const float* __restrict__ C, int n,
     const typename SC::elem* __restrict__ Cp, int n_pad, int CR, int32_t* __restrict__ idx,
     float* __restrict__ mind, double* __restrict__ dpart, unsigned long long* __restrict__ nfb,
@@ -1018,37 +990,69 @@ __global__ __launch_bounds__(kAssignThreads, SC::OCC) void assign_kernel(
     tile_bits = tile_bits_of(n);
   }
   constexpr int LP = SC::LP;
-  constexpr bool PF = LP <= 32;  // prefetch the next row tile's vectors
+  constexpr bool PF = SC::PF;  // prefetch the next row tile's vectors
   if (VEC) L = LP;  // vector loads only for rows of exactly LP floats
   typedef typename SC::elem E;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   E* sA = reinterpret_cast<E*>(smem);
 
+  constexpr int NT = 64 * W;
+  constexpr int RT = 32 * W;  // training vectors per row tile
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (SGPR)
-  const int64_t ntiles_rows = (M + kRowsPerTile - 1) / kRowsPerTile;
+  const int64_t ntiles_rows = (M + RT - 1) / RT;
   const bool resident = CR >= n_pad;
   const WaveCtx w = wave_ctx(L, tile_bits);
 
   float xv[LP / 2];
   int64_t rt = blockIdx.x;
   if (PF && rt < ntiles_rows)
-    load_x<LP, VEC>(X, M, L, rt * kRowsPerTile + (int64_t)wave * 32, w.h, w.j, xv);
-  if (resident) stage_from_C<SC, VEC>(C, n, L, n_pad, sA);
+    load_x<LP, VEC>(X, M, L, rt * RT + (int64_t)wave * 32, w.h, w.j, xv);
+  if (resident) stage_from_C<SC, VEC, NT>(C, n, L, n_pad, sA);
 
   double wsum = 0.0;
   for (; rt < ntiles_rows; rt += gridDim.x) {
-    const int64_t row0 = rt * kRowsPerTile + (int64_t)wave * 32;
+    const int64_t row0 = rt * RT + (int64_t)wave * 32;
     if (!PF) load_x<LP, VEC>(X, M, L, row0, w.h, w.j, xv);
     const int64_t next =
-        (PF && rt + gridDim.x < ntiles_rows) ? row0 + (int64_t)gridDim.x * kRowsPerTile : -1;
-    wsum += process_rows<SC, VEC, PF>(xv, X, M, L, row0, next, C, n, n_pad, CR, resident, Cp, sA,
-                                      idx, mind, nfb, w);
+        (PF && rt + gridDim.x < ntiles_rows) ? row0 + (int64_t)gridDim.x * RT : -1;
+    wsum += process_rows<SC, VEC, PF, NT>(xv, X, M, L, row0, next, C, n, n_pad, CR, resident,
+                                          Cp, sA, idx, mind, nfb, w);
   }
   // per-wave partial of the distortion over the block's row tiles (in order),
   // lanes added by a fixed butterfly
   wsum = wave_sum(wsum);
-  if (dpart && lane == 0) dpart[blockIdx.x * 4 + wave] = wsum;
+  if (dpart && lane == 0) dpart[blockIdx.x * W + wave] = wsum;
+}
+
+// Launch shape of the allocation for a codebook of n_pad rows: waves per
+// workgroup, workgroups, codebook rows per LDS chunk and LDS bytes.  A
+// codebook that does not fit the LDS of OCC workgroups per CU but fits one
+// workgroup's kWideLds bytes runs resident in eight-wave workgroups.
+struct Shape {
+  int waves;
+  int64_t grid;
+  int cr;
+  size_t lds;
+};
+
+template <class SC>
+inline Shape shape_of(int64_t M, int n_pad) {
+  Shape sh;
+  const int CR = chunk_rows<SC>(n_pad);
+  const size_t full = (size_t)n_pad * SC::S * SC::ESZ;
+  if (CR < n_pad && full <= (size_t)kWideLds) {
+    sh.waves = 8;
+    sh.grid = std::min<int64_t>((M + 255) / 256, 256);
+    sh.cr = n_pad;
+    sh.lds = full;
+  } else {
+    sh.waves = 4;
+    sh.grid = std::min<int64_t>((M + kRowsPerTile - 1) / kRowsPerTile, persist_blocks<SC>());
+    sh.cr = CR;
+    sh.lds = (size_t)CR * SC::S * SC::ESZ;
+  }
+  return sh;
 }
 
 // Host side: prepare the codebook and launch.
@@ -1062,17 +1066,17 @@ int launch_screen(const float* X, int64_t M, int L, const float* C, int n, int32
   typedef typename SC::elem E;
   const int n_pad = (n + 31) & ~31;
   E* Cp = reinterpret_cast<E*>(prep);
-  const int CR = chunk_rows<SC>(n_pad);
+  const Shape sh = shape_of<SC>(M, n_pad);
+  const int CR = sh.cr;
   if (CR < n_pad) {  // chunked: stage from the prepared copy
     hipLaunchKernelGGL((prep_kernel<SC>), dim3((unsigned)n_pad), dim3(256), 0, s, C, n, L, Cp,
                        st, cbp);
     LBG_TRY_HIP(hipGetLastError());
   }
-  const int64_t tiles = (M + kRowsPerTile - 1) / kRowsPerTile;
-  // Persistent grid of OCC workgroups per CU: a resident codebook is staged
-  // once per workgroup, a chunked one per row tile.
-  const int64_t grid = std::min<int64_t>(tiles, persist_blocks<SC>());
-  const size_t lds = (size_t)CR * SC::S * SC::ESZ;
+  // Persistent grid: a resident codebook is staged once per workgroup, a
+  // chunked one per row tile.
+  const int64_t grid = sh.grid;
+  const size_t lds = sh.lds;
   const int tb = tile_bits_for(n);
   bool vec = (L == SC::LP) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
   if (st)
@@ -1080,21 +1084,38 @@ int launch_screen(const float* X, int64_t M, int L, const float* C, int n, int32
           ((reinterpret_cast<uintptr_t>(cbp.c[1]) & 15) == 0);
   else
     vec = vec && ((reinterpret_cast<uintptr_t>(C) & 15) == 0);
-  // workgroups may hold up to lds_budget bytes of LDS (above 64 KB on gfx950
-  // only after opting in, once per kernel)
+  // workgroups may hold more than 64 KB of LDS on gfx950 only after opting
+  // in, once per kernel
   static const hipError_t a1 = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&assign_kernel<SC, true>),
+      reinterpret_cast<const void*>(&assign_kernel<SC, true, 4>),
       hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget<SC>());
   static const hipError_t a2 = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&assign_kernel<SC, false>),
+      reinterpret_cast<const void*>(&assign_kernel<SC, false, 4>),
       hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget<SC>());
-  LBG_TRY_HIP(vec ? a1 : a2);
-  if (vec)
-    hipLaunchKernelGGL((assign_kernel<SC, true>), dim3((unsigned)grid), dim3(kAssignThreads), lds,
-                       s, X, M, L, C, n, Cp, n_pad, CR, idx, mind, dpart, nfb, tb, ctl, cbp);
-  else
-    hipLaunchKernelGGL((assign_kernel<SC, false>), dim3((unsigned)grid), dim3(kAssignThreads),
-                       lds, s, X, M, L, C, n, Cp, n_pad, CR, idx, mind, dpart, nfb, tb, ctl, cbp);
+  static const hipError_t a3 = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&assign_kernel<SC, true, 8>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, kWideLds);
+  static const hipError_t a4 = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&assign_kernel<SC, false, 8>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, kWideLds);
+  const dim3 g((unsigned)grid);
+  if (sh.waves == 8) {
+    LBG_TRY_HIP(vec ? a3 : a4);
+    if (vec)
+      hipLaunchKernelGGL((assign_kernel<SC, true, 8>), g, dim3(512), lds, s, X, M, L, C, n, Cp,
+                         n_pad, CR, idx, mind, dpart, nfb, tb, ctl, cbp);
+    else
+      hipLaunchKernelGGL((assign_kernel<SC, false, 8>), g, dim3(512), lds, s, X, M, L, C, n, Cp,
+                         n_pad, CR, idx, mind, dpart, nfb, tb, ctl, cbp);
+  } else {
+    LBG_TRY_HIP(vec ? a1 : a2);
+    if (vec)
+      hipLaunchKernelGGL((assign_kernel<SC, true, 4>), g, dim3(kAssignThreads), lds, s, X, M, L,
+                         C, n, Cp, n_pad, CR, idx, mind, dpart, nfb, tb, ctl, cbp);
+    else
+      hipLaunchKernelGGL((assign_kernel<SC, false, 4>), g, dim3(kAssignThreads), lds, s, X, M,
+                         L, C, n, Cp, n_pad, CR, idx, mind, dpart, nfb, tb, ctl, cbp);
+  }
   LBG_TRY_HIP(hipGetLastError());
   return LBG_OK;
 }

@@ -91,9 +91,6 @@ struct Carver {
 // ----------------------------------------------------------- allocation --
 constexpr int kAssignThreads = 256;
 
-// Rows handled by one workgroup of the matrix-core allocation kernels.
-int assign_rows_per_wg(int64_t L, int precision);
-
 struct AssignWs {
   double* dpart;           // per-wave distortion partial sums
   unsigned long long* nfb; // rows that fell back to the exhaustive search
@@ -112,7 +109,10 @@ int launch_assign(const float* X, int64_t M, int64_t L, const float* C,
                   double* dpart, unsigned long long* nfb, void* prep, hipStream_t s,
                   Ctl ctl = Ctl{nullptr, nullptr, nullptr, 0, nullptr, nullptr},
                   CbPair cbp = CbPair{{nullptr, nullptr}});
-int64_t assign_num_parts(int64_t M, int64_t L, int precision);
+// Partials the allocation writes for a codebook of N rows, and the most it
+// writes for any size up to N.
+int64_t assign_num_parts(int64_t M, int64_t L, int64_t N, int precision);
+int64_t assign_max_parts(int64_t M, int64_t L, int64_t N, int precision);
 
 // Sum ``nparts`` FP64 partials in a fixed order and divide by ``denom``.
 int launch_reduce_parts(const double* parts, int64_t nparts, double denom,

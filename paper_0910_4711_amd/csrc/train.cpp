@@ -230,7 +230,7 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
 
   const bool timed = p->timing != 0 && st != nullptr;
   Batch b{X, M, L, N, p->precision, p->split_mode, p->eps_split, p->delta, idx_out, &w,
-          assign_num_parts(M, L, p->precision)};
+          assign_num_parts(M, L, N, p->precision)};
   const bool use_graph = s != nullptr && p->graph != 0;
 
   GraphEntry* ge = nullptr;

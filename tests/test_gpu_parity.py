@@ -69,6 +69,11 @@ ASSIGN_CASES = [
     (800, 100, 20, "gmm"),
     (600, 128, 129, "gmm"),
     (300, 200, 9, "gmm"),
+    # codebooks resident only in one eight-wave workgroup's LDS, and larger
+    # ones staged chunk by chunk
+    (5000, 16, 700, "img"),
+    (3000, 64, 400, "gmm"),
+    (2000, 64, 700, "gmm"),
 ]
 
 
@@ -248,6 +253,18 @@ def test_train_small_cases(P):
     assert st["status"] == P.OK and D == 0.0 and list(host(C)[:, 0]) == [3.0, 1.0]
 
 
+def test_train_wide_codebook_matches_oracle(P):
+    # L = 64, N = 512: the device-side loop runs the allocation in eight-wave
+    # workgroups with the whole codebook resident
+    X = _img_rows(4096, 64, 11)
+    C, idx, D, st = P.train(dev(X), 512)
+    ref = oracle.train(X, 512, store_fp32=True)
+    np.testing.assert_array_equal(st["level_iters"], ref["level_iters"])
+    np.testing.assert_array_equal(host(idx), ref["idx"])
+    np.testing.assert_array_equal(host(C), ref["C"].astype(np.float32))
+    assert abs(D - ref["D"]) <= 1e-12 * ref["D"]
+
+
 def test_train_deterministic(P):
     X = _img_rows(30000, 16, 1)
     a = P.train(dev(X), 32)
@@ -255,10 +272,12 @@ def test_train_deterministic(P):
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[2] == b[2]
 
 
-def test_bf16_rescore_close_to_oracle(P):
-    X = synth.image_training_set((0, 1), 256, 256, 8)  # M = 2048, L = 64
-    rng = np.random.default_rng(1000)
-    C = X[synth.distinct_rows(X, 128, 1000)]
+# codebook resident in four-wave workgroups, resident in one eight-wave
+# workgroup, staged in chunks; ragged row counts
+@pytest.mark.parametrize("images,M,N", [(2, 2048, 128), (4, 4000, 1024), (4, 3001, 1200)])
+def test_bf16_rescore_close_to_oracle(P, images, M, N):
+    X = synth.image_training_set(tuple(range(images)), 256, 256, 8)[:M]  # L = 64
+    C = X[synth.distinct_rows(X, N, 1000)]
     idx, mind = P.assign(dev(X), dev(C), P.BF16_RESCORE)
     idx_o, d1, d2 = oracle.assign(X, C.astype(np.float64))
     h = host(idx)
