@@ -72,48 +72,17 @@ size_t prep_bytes(int64_t L, int64_t N, int precision) {
   }
 }
 
-namespace {
-template <class SC>
-int64_t parts_of(int64_t M, int64_t N) {
-  const Shape sh = shape_of<SC>(M, (int)((N + 31) & ~(int64_t)31));
-  return sh.waves * sh.grid;
-}
-}  // namespace
-
-// Matrix-core kernels: one partial per wave of every workgroup of the
-// persistent grid (whose shape depends on the codebook size); exhaustive
-// kernel: one per block of 256 rows.
+// Matrix-core kernels: one partial of the distortion per 32 vectors;
+// exhaustive kernel: one per block of 256 rows.
 int64_t assign_num_parts(int64_t M, int64_t L, int64_t N, int precision) {
-  const int LP = padded_dim(L);
-  if (LP == 0) return (M + 255) / 256;
-  if (precision == LBG_BF16_RESCORE) {
-    switch (LP) {
-      case 8:
-      case 16: return parts_of<Bf16Screen<16>>(M, N);
-      case 32: return parts_of<Bf16Screen<32>>(M, N);
-      case 64: return parts_of<Bf16Screen<64>>(M, N);
-      default: return parts_of<Bf16Screen<128>>(M, N);
-    }
-  }
-  switch (LP) {
-    case 8: return parts_of<Fp32Screen<8>>(M, N);
-    case 16: return parts_of<Fp32Screen<16>>(M, N);
-    case 32: return parts_of<Fp32Screen<32>>(M, N);
-    case 64: return parts_of<Fp32Screen<64>>(M, N);
-    default: return parts_of<Fp32Screen<128>>(M, N);
-  }
-}
-
-// Partials of any codebook size up to N (either workgroup shape).
-int64_t assign_max_parts(int64_t M, int64_t L, int64_t N, int precision) {
-  int64_t mx = 0;
-  for (int64_t n = 1; n <= N; n = (n < 32 ? 32 : n + 32))
-    mx = std::max(mx, assign_num_parts(M, L, n, precision));
-  return std::max(mx, assign_num_parts(M, L, N, precision));
+  (void)N;
+  (void)precision;
+  if (padded_dim(L) == 0) return (M + 255) / 256;
+  return (M + 31) / 32;
 }
 
 void plan_assign(Carver& c, int64_t M, int64_t L, int64_t N, int precision, AssignWs* ws) {
-  ws->dpart = c.take<double>((size_t)assign_max_parts(M, L, N, precision));
+  ws->dpart = c.take<double>((size_t)assign_num_parts(M, L, N, precision));
   ws->nfb = c.take<unsigned long long>(1);
   ws->prep = c.take<unsigned char>(prep_bytes(L, N, precision));
 }

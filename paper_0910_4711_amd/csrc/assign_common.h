@@ -1010,19 +1010,18 @@ __global__ __launch_bounds__(64 * W, W == 4 ? SC::OCC : 1) void assign_kernel(
     load_x<LP, VEC>(X, M, L, rt * RT + (int64_t)wave * 32, w.h, w.j, xv);
   if (resident) stage_from_C<SC, VEC, NT>(C, n, L, n_pad, sA);
 
-  double wsum = 0.0;
   for (; rt < ntiles_rows; rt += gridDim.x) {
     const int64_t row0 = rt * RT + (int64_t)wave * 32;
     if (!PF) load_x<LP, VEC>(X, M, L, row0, w.h, w.j, xv);
     const int64_t next =
         (PF && rt + gridDim.x < ntiles_rows) ? row0 + (int64_t)gridDim.x * RT : -1;
-    wsum += process_rows<SC, VEC, PF, NT>(xv, X, M, L, row0, next, C, n, n_pad, CR, resident,
-                                          Cp, sA, idx, mind, nfb, w);
+    const double d = process_rows<SC, VEC, PF, NT>(xv, X, M, L, row0, next, C, n, n_pad, CR,
+                                                   resident, Cp, sA, idx, mind, nfb, w);
+    // partial of the distortion per 32 vectors (lanes added by a fixed
+    // butterfly), indexed by the vectors: the same for every launch shape
+    const double ws = wave_sum(d);
+    if (dpart && lane == 0 && row0 < M) dpart[row0 >> 5] = ws;
   }
-  // per-wave partial of the distortion over the block's row tiles (in order),
-  // lanes added by a fixed butterfly
-  wsum = wave_sum(wsum);
-  if (dpart && lane == 0) dpart[blockIdx.x * W + wave] = wsum;
 }
 
 // Launch shape of the allocation for a codebook of n_pad rows: waves per

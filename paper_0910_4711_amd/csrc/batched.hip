@@ -56,7 +56,7 @@ struct BInst {
   int32_t* idx;
   DevState* st;
   DevState* pend;
-  double* dpart;   // 4 per allocation slot
+  double* dpart;   // distortion partial per 32 vectors
   int64_t ntiles;  // row tiles of kRowsPerTile
   int32_t G;       // allocation slots: the single-run kernel's grid
   int32_t cps, nslices, nchunks, absmax_blocks, cnwg;
@@ -127,7 +127,6 @@ __device__ __forceinline__ void alloc_chunk(const BInst& B, const DevState* st, 
   int b = b0;
   int64_t rt = b;
   if (PF) load_x<LP, VEC>(B.X, B.M, L, rt * kRowsPerTile + (int64_t)wave * 32, w.h, w.j, xv);
-  double wsum = 0.0;
   for (;;) {
     // the tile after (b, rt): the slot's next tile, else the next slot's first
     int nb = b;
@@ -140,13 +139,12 @@ __device__ __forceinline__ void alloc_chunk(const BInst& B, const DevState* st, 
     const int64_t row0 = rt * kRowsPerTile + (int64_t)wave * 32;
     if (!PF) load_x<LP, VEC>(B.X, B.M, L, row0, w.h, w.j, xv);
     const int64_t next = (PF && more) ? nrt * kRowsPerTile + (int64_t)wave * 32 : -1;
-    wsum += process_rows<SC, VEC, PF>(xv, B.X, B.M, L, row0, next, C, n, n_pad, n_pad, true,
-                                      nullptr, sA, B.idx, nullptr, B.nfb, w);
-    if (nb != b) {
-      const double ws = wave_sum(wsum);
-      if (lane == 0) B.dpart[b * 4 + wave] = ws;
-      wsum = 0.0;
-    }
+    const double d = process_rows<SC, VEC, PF>(xv, B.X, B.M, L, row0, next, C, n, n_pad,
+                                               n_pad, true, nullptr, sA, B.idx, nullptr,
+                                               B.nfb, w);
+    // the single-run kernel's partial of these 32 vectors
+    const double ws = wave_sum(d);
+    if (lane == 0 && row0 < B.M) B.dpart[row0 >> 5] = ws;
     if (!more) break;
     b = nb;
     rt = nrt;
@@ -196,7 +194,7 @@ __global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ ins
   const int i = tb.b2i[tb.off[kPreAcc] + blockIdx.x];
   const BInst& B = inst[i];
   const int64_t local = (int64_t)blockIdx.x - acc_pre[i];
-  const Ctl ctl{B.st, B.pend, B.dpart, 4 * (int64_t)B.G, B.Dtrace, B.Atrace};
+  const Ctl ctl{B.st, B.pend, B.dpart, (B.M + 31) / 32, B.Dtrace, B.Atrace};
   int N = B.N;
   if (B.st->done) return;
   if (local == 0) (void)afp::acc_decide(ctl, true, &N);  // the instance's decision
@@ -249,7 +247,7 @@ __global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ ins
   const int i = tb.b2i[tb.off[kPreFin] + blockIdx.x];
   const BInst& B = inst[i];
   const int k = (int)((int64_t)blockIdx.x - fin_pre[i]);
-  const Ctl ctl{B.st, B.pend, B.dpart, 4 * (int64_t)B.G, B.Dtrace, B.Atrace};
+  const Ctl ctl{B.st, B.pend, B.dpart, (B.M + 31) / 32, B.Dtrace, B.Atrace};
   const CbPair cbp{{B.Cb[0], B.Cb[1]}};
   int N = B.N;
   const float* c_old = nullptr;
@@ -403,7 +401,7 @@ void plan_batch(Carver& c, const lbg_instance* in, int n, BatchWs* w) {
     q.crpb = (M + q.cnwg - 1) / q.cnwg;
     q.Cb[0] = c.take<float>((size_t)(N * L));
     q.Cb[1] = c.take<float>((size_t)(N * L));
-    q.dpart = c.take<double>((size_t)(4 * q.G));
+    q.dpart = c.take<double>((size_t)((M + 31) / 32));
     q.cpart = c.take<double>((size_t)(q.cnwg * L));
     q.Dtrace = c.take<double>(kBatchTrace);
     q.Atrace = c.take<int32_t>(kBatchTrace);

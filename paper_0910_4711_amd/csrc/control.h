@@ -83,12 +83,16 @@ __device__ inline void apply_step(const DevState* in, DevState* out, double D, S
 
 // Block-wide D = sum(parts) / M in a fixed order: thread t adds parts t,
 // t+256, ..., then a fixed tree.  Every block that calls it gets the same
-// value.  ``red`` is 256 doubles of LDS; blockDim.x must be 256.
+// value.  ``red`` is 256 doubles of LDS; blockDim.x must be at least 256
+// (threads beyond the first 256 only take part in the barriers).
 __device__ inline double block_distortion(const double* __restrict__ parts, int64_t nparts,
                                           int64_t M, double* red) {
   double acc = 0.0;
-  for (int64_t p = threadIdx.x; p < nparts; p += 256) acc += parts[p];
-  red[threadIdx.x] = acc;
+  if (threadIdx.x < 256) {
+#pragma unroll 8
+    for (int64_t p = threadIdx.x; p < nparts; p += 256) acc += parts[p];
+    red[threadIdx.x] = acc;
+  }
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];

@@ -92,15 +92,16 @@ struct Carver {
 constexpr int kAssignThreads = 256;
 
 struct AssignWs {
-  double* dpart;           // per-wave distortion partial sums
+  double* dpart;           // distortion partial sums, one per 32 vectors
   unsigned long long* nfb; // rows that fell back to the exhaustive search
   unsigned char* prep;     // codebook in the screen's LDS row layout
 };
 void plan_assign(Carver& c, int64_t M, int64_t L, int64_t N, int precision,
                  AssignWs* ws);
 
-// Enqueue the allocation.  dpart (nullable) receives per-workgroup FP64
-// partial sums of the winning distances; nfb (nullable) counts fallback rows.
+// Enqueue the allocation.  dpart (nullable) receives FP64 partial sums of
+// the winning distances (assign_num_parts of them); nfb (nullable) counts
+// fallback rows.
 // With ``st`` set, the codebook and its size come from the device state
 // (buffer cbp.c[st->cb], st->n rows, N the largest size) and the launch does
 // nothing once the run is done.
@@ -109,10 +110,8 @@ int launch_assign(const float* X, int64_t M, int64_t L, const float* C,
                   double* dpart, unsigned long long* nfb, void* prep, hipStream_t s,
                   Ctl ctl = Ctl{nullptr, nullptr, nullptr, 0, nullptr, nullptr},
                   CbPair cbp = CbPair{{nullptr, nullptr}});
-// Partials the allocation writes for a codebook of N rows, and the most it
-// writes for any size up to N.
+// Partials of the distortion that the allocation writes.
 int64_t assign_num_parts(int64_t M, int64_t L, int64_t N, int precision);
-int64_t assign_max_parts(int64_t M, int64_t L, int64_t N, int precision);
 
 // Sum ``nparts`` FP64 partials in a fixed order and divide by ``denom``.
 int launch_reduce_parts(const double* parts, int64_t nparts, double denom,
