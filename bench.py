@@ -12,8 +12,11 @@ Prints one JSON line.  ``value`` is vector-codeword distances per second over
 the whole job (sum over every allocation of M * n, divided by the wall time
 of the timed steps).  ``roofline`` reports the allocation kernel (the
 dominant one) against the FP32 matrix-core peak, from its own HIP-event
-durations inside the timed steps; ``cpu_baseline`` times the FP64 CPU oracle
-on a bounded sample of the same workload on this host's cores.
+durations inside the timed region: the first ``--event-steps`` timed steps
+(default 1) record an event pair around every allocation and update (their
+recording cost is part of the measured wall time); ``cpu_baseline`` times
+the FP64 CPU oracle on a bounded sample of the same workload on this host's
+cores.
 """
 
 from __future__ import annotations
@@ -374,6 +377,8 @@ def main():
     ap.add_argument("--cpu-images", type=int, default=16,
                     help="images of the workload the CPU oracle baseline runs on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--event-steps", type=int, default=1,
+                    help="timed steps that record HIP events around every kernel")
     ap.add_argument("--copy-calibration", type=int, metavar="MIB", default=0,
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--form", choices=["batched", "precision", "differentiation"],
@@ -419,20 +424,27 @@ def main():
         stream.synchronize()
         log(f"warmup step {i + 1}/{args.warmup} done")
     torch.cuda.synchronize(dev)
-    tot = dict(dist=0, ms_assign=0.0, ms_update=0.0, ms_split=0.0, assigns=0, updates=0,
-               fallback=0)
+    tot = dict(dist=0, assigns=0, updates=0, fallback=0)
+    # the event-timed steps' kernel durations and the work they cover
+    ev = dict(steps=0, dist=0, ms_assign=0.0, ms_update=0.0, ms_split=0.0, assigns=0, updates=0)
+    n_ev = max(1, min(args.event_steps, args.steps))
     last = None
     t0 = time.perf_counter()
     for i in range(args.steps):
+        timed = i < n_ev
         with torch.cuda.stream(stream):
-            C, idx, D, st = P.train(Xd, N, workspace=ws, timing=True)
+            C, idx, D, st = P.train(Xd, N, workspace=ws, timing=timed)
         tot["dist"] += st["total_distances"]
-        tot["ms_assign"] += st["ms_assign"]
-        tot["ms_update"] += st["ms_update"]
-        tot["ms_split"] += st["ms_split"]
         tot["assigns"] += st["total_assigns"]
         tot["updates"] += st["total_updates"]
         tot["fallback"] += st["fallback_rows"]
+        if timed:
+            ev["steps"] += 1
+            ev["dist"] += st["total_distances"]
+            ev["assigns"] += st["total_assigns"]
+            ev["updates"] += st["total_updates"]
+            for k in ("ms_assign", "ms_update", "ms_split"):
+                ev[k] += st[k]
         last = (D, st)
     torch.cuda.synchronize(dev)
     elapsed = time.perf_counter() - t0
@@ -440,11 +452,11 @@ def main():
 
     D, st = last
     traffic = measured_traffic()
-    flops = 2.0 * L * tot["dist"]  # 2L flops per vector-codeword distance
-    assign_s = tot["ms_assign"] / 1e3
+    flops = 2.0 * L * ev["dist"]  # 2L flops per vector-codeword distance
+    assign_s = ev["ms_assign"] / 1e3
     achieved_tf = flops / assign_s / 1e12
-    upd_bytes = tot["updates"] * M * (4 * L + 4)  # X rows + cell index per update
-    upd_gbs = upd_bytes / (tot["ms_update"] / 1e3) / 1e9 if tot["ms_update"] > 0 else None
+    upd_bytes = ev["updates"] * M * (4 * L + 4)  # X rows + cell index per update
+    upd_gbs = upd_bytes / (ev["ms_update"] / 1e3) / 1e9 if ev["ms_update"] > 0 else None
 
     out = {
         "metric": "LBG iteration vector-codeword distances/s",
@@ -475,23 +487,24 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                             "copy-calibrated)",
             "kernel": "allocation: assign_kernel<Fp32Screen<16>, vector loads>",
-            "launches": tot["assigns"],
-            "avg_launch_us": tot["ms_assign"] / tot["assigns"] * 1e3,
-            "flops_per_launch_avg": flops / tot["assigns"],
+            "launches": ev["assigns"],
+            "event_steps": ev["steps"],
+            "avg_launch_us": ev["ms_assign"] / ev["assigns"] * 1e3,
+            "flops_per_launch_avg": flops / ev["assigns"],
         },
         "update": {
             "bound": "hbm",
             "achieved_gbs": upd_gbs,
             "peak_gbs": PEAK_HBM_GBS,
             "frac": (upd_gbs / PEAK_HBM_GBS) if upd_gbs else None,
-            "avg_update_us": tot["ms_update"] / max(1, tot["updates"]) * 1e3,
+            "avg_update_us": ev["ms_update"] / max(1, ev["updates"]) * 1e3,
         },
         "per_step": {
             "assigns": tot["assigns"] // args.steps,
             "updates": tot["updates"] // args.steps,
-            "ms_assign": tot["ms_assign"] / args.steps,
-            "ms_update": tot["ms_update"] / args.steps,
-            "ms_split": tot["ms_split"] / args.steps,
+            "ms_assign": ev["ms_assign"] / ev["steps"],
+            "ms_update": ev["ms_update"] / ev["steps"],
+            "ms_split": ev["ms_split"] / ev["steps"],
             "fallback_rows": tot["fallback"] // args.steps,
             "level_iters": st["level_iters"],
             "D": D,

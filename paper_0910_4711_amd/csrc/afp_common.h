@@ -134,12 +134,14 @@ __device__ __forceinline__ void load_dims(const float* xrow, int L, int gl,
 }
 
 // One block per (row chunk, cell slice), slices of one chunk adjacent.  Rows
-// stream in batches of kBatch.  With one slice every row is added: a group
+// stream in batches of kBatch (one slice) or kSel (several).  With one
+// slice every row is added: a group
 // of G lanes walks a contiguous sub-range of the batch, kUnroll rows (cell
 // index and coordinates) loaded together.  With several slices the batch's
 // cell indices are read first and the rows of this slice are gathered into
 // an LDS list (integer sums make the list order immaterial), then added.
 constexpr int kBatch = 1024;
+constexpr int kSel = 4096;  // several slices: about kSel / nslices rows gathered per batch
 
 // Decision of this iteration from the allocation's partials (the same in every
 // block that calls it); the block with ``lead`` records the next state in
@@ -165,7 +167,7 @@ __device__ __forceinline__ bool acc_decide(const Ctl& ctl, bool lead, int* N) {
 }
 
 // Accumulation of block ``blk`` = (row chunk, cell slice) of the update;
-// slist (kBatch entries) and snsel are the caller's LDS.
+// slist (kSel entries) and snsel are the caller's LDS.
 template <int G, int VW, int DPL>
 __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M, int L,
                                          const int32_t* __restrict__ idx, int N, int cps,
@@ -195,8 +197,9 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
   int32_t* my_cnt = scnt + (g % R) * nk;
   const int64_t r0 = (int64_t)chunk * rows_per_chunk;
   const int64_t r1 = min(M, r0 + rows_per_chunk);
-  for (int64_t b0 = r0; b0 < r1; b0 += kBatch) {
-    const int nb = (int)min((int64_t)kBatch, r1 - b0);
+  const int step = nslices == 1 ? kBatch : kSel;
+  for (int64_t b0 = r0; b0 < r1; b0 += step) {
+    const int nb = (int)min((int64_t)step, r1 - b0);
     if (nslices == 1) {
       constexpr int PER = kBatch / NG;  // rows of one group per batch
       const int64_t gb = b0 + (int64_t)g * PER;
@@ -217,14 +220,14 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
             add_row<G, VW, DPL>(my_acc, my_cnt, nullptr, k[u] - k0, L, gl, s, v[u]);
       }
     } else {
-      int kr[kBatch / kT];
+      int kr[kSel / kT];
 #pragma unroll
-      for (int u = 0; u < kBatch / kT; ++u) {  // loads first, all in flight
+      for (int u = 0; u < kSel / kT; ++u) {  // loads first, all in flight
         const int r = u * kT + t;
         kr[u] = idx[b0 + (r < nb ? r : 0)];
       }
 #pragma unroll
-      for (int u = 0; u < kBatch / kT; ++u) {
+      for (int u = 0; u < kSel / kT; ++u) {
         const int r = u * kT + t;
         const int k = kr[u];
         if (r < nb && k >= k0 && k < k1) slist[atomicAdd(&snsel, 1)] = r * 8192 + (k - k0);

@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kT, 2) void b_assign_kernel(const BInst* __restrict
 __global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ inst, int n_inst,
                                                    const int64_t* __restrict__ pre, Tabs tb) {
   extern __shared__ unsigned long long sacc[];
-  __shared__ int32_t slist[afp::kBatch];
+  __shared__ int32_t slist[afp::kSel];
   __shared__ int32_t snsel;
   const int64_t* acc_pre = pre + (int64_t)kPreAcc * (n_inst + 1);
   if ((int64_t)blockIdx.x >= acc_pre[n_inst]) return;

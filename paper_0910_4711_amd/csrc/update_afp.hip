@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kT) void acc_kernel(
     int cps, int nslices, int64_t rows_per_chunk, const int* __restrict__ shift_p,
     unsigned long long* __restrict__ part, int32_t* __restrict__ pcnt, Ctl ctl) {
   extern __shared__ unsigned long long sacc[];
-  __shared__ int32_t slist[kBatch];
+  __shared__ int32_t slist[kSel];
   __shared__ int32_t snsel;
   if (ctl.st) {
     // the decision (block 0 writes it for the update's last kernel) does not
