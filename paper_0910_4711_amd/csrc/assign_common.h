@@ -138,7 +138,8 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ C, 
     __syncthreads();
   }
   if (t == 0) {
-    const float nrm = (row < n) ? (float)(0.25 * part[0]) : kBig;
+    // at most kBig, so that the BF16 padding stays finite
+    const float nrm = (row < n) ? fminf((float)(0.25 * part[0]), kBig) : kBig;
     E* pad = Cp + (int64_t)row * SC::S + SC::LP;
     if constexpr (SC::EXACT) {
       pad[0] = nrm;
@@ -541,6 +542,44 @@ __device__ __forceinline__ double pair_dist(const float (&xv)[LP / 2], const flo
   return s1;
 }
 
+// The same for two codevectors at once (half-rows ca, cb).
+template <int LP>
+__device__ __forceinline__ void pair_dist2(const float (&xv)[LP / 2], const float (&ca)[LP / 2],
+                                           const float (&cb)[LP / 2], int L, double& da,
+                                           double& db) {
+  double s0 = 0.0, t0 = 0.0;
+#pragma unroll
+  for (int q = 0; q < LP / 2; ++q) {
+    if (q < L) {
+      const double x = (double)xv[q];
+      const double u = x - (double)ca[q], v = x - (double)cb[q];
+      s0 = s0 + u * u;
+      t0 = t0 + v * v;
+    }
+  }
+  const uint64_t b0 = (uint64_t)__double_as_longlong(s0), c0 = (uint64_t)__double_as_longlong(t0);
+  float a_lo, a_hi, b_lo, b_hi, c_lo, c_hi, d_lo, d_hi;
+  pair_values(__uint_as_float((uint32_t)b0), a_lo, a_hi);
+  pair_values(__uint_as_float((uint32_t)(b0 >> 32)), b_lo, b_hi);
+  pair_values(__uint_as_float((uint32_t)c0), c_lo, c_hi);
+  pair_values(__uint_as_float((uint32_t)(c0 >> 32)), d_lo, d_hi);
+  double s1 = __longlong_as_double(
+      (long long)(((uint64_t)__float_as_uint(b_lo) << 32) | __float_as_uint(a_lo)));
+  double t1 = __longlong_as_double(
+      (long long)(((uint64_t)__float_as_uint(d_lo) << 32) | __float_as_uint(c_lo)));
+#pragma unroll
+  for (int q = 0; q < LP / 2; ++q) {
+    if (LP / 2 + q < L) {
+      const double x = (double)xv[q];
+      const double u = x - (double)ca[q], v = x - (double)cb[q];
+      s1 = s1 + u * u;
+      t1 = t1 + v * v;
+    }
+  }
+  da = s1;
+  db = t1;
+}
+
 // Returns the winning distance of the vector this lane finished (0 for the
 // other lanes).  xv: lane (j, h) holds dimensions [h LP/2, (h+1) LP/2) of
 // vector j (FP32); xsq: the vector's squared norm (FP32).  Lane (j, 0) sums
@@ -588,8 +627,8 @@ __device__ __forceinline__ double finish_rows(const Slots& sl, const float* __re
     float ca[LP / 2], cb[LP / 2];
     c_half<SC, VEC>(C, L, nullptr, win, h, ca);
     c_half<SC, VEC>(C, L, nullptr, i2, h, cb);
-    const double da = pair_dist<LP>(xv, ca, L);
-    const double db = pair_dist<LP>(xv, cb, L);
+    double da, db;
+    pair_dist2<LP>(xv, ca, cb, L, da, db);
     d = da;
     if (two && (db < da || (db == da && i2 < win))) {
       d = db;
@@ -716,7 +755,7 @@ __device__ __forceinline__ void stage_from_C(const float* __restrict__ C, int n,
       const double v = (double)(float)sA[r * S + d];
       q += v * v;
     }
-    const float nrm = (r < n) ? (float)(0.25 * q) : kBig;
+    const float nrm = (r < n) ? fminf((float)(0.25 * q), kBig) : kBig;
     E* pad = sA + r * S + LP;
     if constexpr (SC::EXACT) {
       pad[0] = nrm;
@@ -777,13 +816,11 @@ struct Frag<Bf16Screen<LP>> {
   static constexpr int NS = LP / 16;
   bf16x8 an;
   bf16x8 a[NS];
-  // row layout [bf16(-2c) (LP), hi, mid, lo, 1, 1, 1, 0, 0]: half 0 supplies
-  // the norm step, half 1 zeros; dimensions [h LP/2, ...) in steps of 8
+  // row layout [bf16(-2c) (LP), hi, mid, lo, 1, 1, 1, 0, 0]: both halves
+  // load the padding for the norm step (finite: the norm is clamped), which
+  // half 1's zero B operand cancels; dimensions [h LP/2, ...) in steps of 8
   __device__ __forceinline__ void load(const __bf16* ar, int h) {
-    const bf16x8 pad = *reinterpret_cast<const bf16x8*>(ar + LP);
-    const __bf16 zero = (__bf16)0.0f;
-    const bf16x8 zv = {zero, zero, zero, zero, zero, zero, zero, zero};
-    an = h ? zv : pad;
+    an = *reinterpret_cast<const bf16x8*>(ar + LP);
     const __bf16* p = ar + h * (LP / 2);
 #pragma unroll
     for (int s = 0; s < NS; ++s) a[s] = *reinterpret_cast<const bf16x8*>(p + 8 * s);
@@ -934,16 +971,18 @@ __device__ __forceinline__ double process_rows(
     ss += xor_lane<32>(ss);
     xn = h ? (float)ss : 1.0f;
   } else {
+    // |x|^2 of the rounded vector, FP32 (it keeps the keys near the
+    // distances, non-negative, so that equal keys resolve to the lower tile)
+    float sf = 0.0f;
 #pragma unroll
     for (int s = 0; s < LP / 2; ++s) {
       const __bf16 b = (__bf16)xv[s];
       xf[s >> 3][s & 7] = b;
-      const double r = (double)(float)b;
-      ss += r * r;
+      sf = __builtin_fmaf((float)b, (float)b, sf);
     }
-    ss += xor_lane<32>(ss);
+    sf += __uint_as_float(xor_lane<32>(__float_as_uint(sf)));
     __bf16 hi, mid, lo;
-    split3((float)ss, hi, mid, lo);
+    split3(sf, hi, mid, lo);
     const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
     const bf16x8 nv = {one, one, one, hi, mid, lo, zero, zero};
     const bf16x8 zv = {zero, zero, zero, zero, zero, zero, zero, zero};
