@@ -78,13 +78,28 @@ __device__ __forceinline__ void shift_body(const uint32_t* __restrict__ part, in
     const float mx = __uint_as_float(s[0]);
     int e = 0;
     if (mx > 0.0f) frexpf(mx, &e);  // mx < 2^e
-    *shift = (s[0] == 0) ? 0 : (61 - e - b);
+    *shift = (s[0] == 0) ? 0 : (min(51, 62 - b) - e);
   }
 }
 
 
-__device__ __forceinline__ unsigned long long fixed(float v, int s) {
-  return (unsigned long long)llrint(ldexp((double)v, s));
+// round(v * 2^s), nearest with ties to even, as a two's-complement 64-bit
+// integer, for |v * 2^s| < 2^51 (the shift guarantees it for the training
+// data): fma(v, 2^s, 1.5 * 2^52) is exact up to that one rounding, to an
+// integer (the sum lies in [2^52, 2^53), whose spacing is 1; 1.5 * 2^52 is
+// even, so ties go to even as rint's do), and the integer is the sum's bit
+// pattern minus that of 1.5 * 2^52, whose low word is zero.  p2s = 2^s.
+__device__ __forceinline__ unsigned long long fixed(float v, double p2s) {
+  const double y = __builtin_fma((double)v, p2s, 0x1.8p52);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(y);
+  const uint32_t hi = (uint32_t)(b >> 32) - 0x43380000u;  // no borrow: the low word is kept
+  return ((unsigned long long)hi << 32) | (b & 0xffffffffull);
+}
+
+// The same for any magnitude below 2^62 (codevectors outside the data's
+// range, in the gradient).
+__device__ __forceinline__ long long fixed_wide(float v, int s) {
+  return llrint(ldexp((double)v, s));
 }
 
 // Row layout of the accumulation: a row is handled by G lanes; lane gl
@@ -108,15 +123,25 @@ struct VLoad<1> {
 };
 
 template <int G, int VW, int DPL>
-__device__ __forceinline__ void add_row(unsigned long long* sacc, int32_t* scnt, const float* xrow,
-                                        int kk, int L, int gl, int s, const float (&v)[DPL][VW]) {
+__device__ __forceinline__ void add_row(unsigned long long* sacc, int32_t* scnt,
+                                        const float* xrow,
+                                        int kk, int L, int gl, double p2s,
+                                        const float (&v)[DPL][VW]) {
+  unsigned long long* row = sacc + kk * L;
+  if (G * VW * DPL == L) {  // every lane's dimensions exist (a uniform test, once per row)
 #pragma unroll
-  for (int q = 0; q < DPL; ++q)
+    for (int q = 0; q < DPL; ++q)
 #pragma unroll
-    for (int e = 0; e < VW; ++e) {
-      const int d = (gl + q * G) * VW + e;
-      if (d < L) atomicAdd(&sacc[kk * L + d], fixed(v[q][e], s));
-    }
+      for (int e = 0; e < VW; ++e) atomicAdd(&row[(gl + q * G) * VW + e], fixed(v[q][e], p2s));
+  } else {
+#pragma unroll
+    for (int q = 0; q < DPL; ++q)
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const int d = (gl + q * G) * VW + e;
+        if (d < L) atomicAdd(&row[d], fixed(v[q][e], p2s));
+      }
+  }
   if (gl == 0) atomicAdd(&scnt[kk], 1);
 }
 
@@ -142,6 +167,7 @@ __device__ __forceinline__ void load_dims(const float* xrow, int L, int gl,
 // an LDS list (integer sums make the list order immaterial), then added.
 constexpr int kBatch = 1024;
 constexpr int kSel = 4096;  // several slices: about kSel / nslices rows gathered per batch
+constexpr int kUnrollSel = 16;  // gathered rows per group and stage
 
 // Decision of this iteration from the allocation's partials (the same in every
 // block that calls it); the block with ``lead`` records the next state in
@@ -167,8 +193,9 @@ __device__ __forceinline__ bool acc_decide(const Ctl& ctl, bool lead, int* N) {
 }
 
 // Accumulation of block ``blk`` = (row chunk, cell slice) of the update;
-// slist (kSel entries) and snsel are the caller's LDS.
-template <int G, int VW, int DPL>
+// slist (kSel entries when SEL) and snsel are the caller's LDS.  SEL: the
+// block's slice is one of several (nslices > 1).
+template <int G, int VW, int DPL, bool SEL>
 __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M, int L,
                                          const int32_t* __restrict__ idx, int N, int cps,
                                          int nslices, int64_t rows_per_chunk, int s,
@@ -177,6 +204,7 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
                                          unsigned long long* sacc, int32_t* slist,
                                          int32_t& snsel) {
   const int chunk = (int)(blk / nslices), slice = (int)(blk % nslices);
+  const double p2s = ldexp(1.0, s);
   const int k0 = slice * cps, k1 = min(N, k0 + cps), nk = max(0, k1 - k0);
   constexpr int NG = kT / G;  // rows in parallel
   // With a single slice and few cells, R private copies of the table (row
@@ -197,10 +225,9 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
   int32_t* my_cnt = scnt + (g % R) * nk;
   const int64_t r0 = (int64_t)chunk * rows_per_chunk;
   const int64_t r1 = min(M, r0 + rows_per_chunk);
-  const int step = nslices == 1 ? kBatch : kSel;
-  for (int64_t b0 = r0; b0 < r1; b0 += step) {
-    const int nb = (int)min((int64_t)step, r1 - b0);
-    if (nslices == 1) {
+  if constexpr (!SEL) {
+    for (int64_t b0 = r0; b0 < r1; b0 += kBatch) {
+      const int nb = (int)min((int64_t)kBatch, r1 - b0);
       constexpr int PER = kBatch / NG;  // rows of one group per batch
       const int64_t gb = b0 + (int64_t)g * PER;
       for (int i0 = 0; i0 < PER; i0 += kUnroll) {
@@ -217,41 +244,69 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
           if (k[u] >= k0 && k[u] < k1)
-            add_row<G, VW, DPL>(my_acc, my_cnt, nullptr, k[u] - k0, L, gl, s, v[u]);
+            add_row<G, VW, DPL>(my_acc, my_cnt, nullptr, k[u] - k0, L, gl, p2s, v[u]);
       }
-    } else {
-      int kr[kSel / kT];
+    }
+  } else {
+    // Several slices: batches of kSel cell indices; the next batch's indices
+    // are loaded while this batch's rows of the slice are gathered, kUnrollSel
+    // rows per group in flight.
+    constexpr int KR = kSel / kT;
+    int kr[KR];
+    auto load_idx = [&](int64_t b0, int (&dst)[KR]) {
+      const int nb = (int)min((int64_t)kSel, r1 - b0);
 #pragma unroll
-      for (int u = 0; u < kSel / kT; ++u) {  // loads first, all in flight
+      for (int u = 0; u < KR; ++u) {
         const int r = u * kT + t;
-        kr[u] = idx[b0 + (r < nb ? r : 0)];
+        dst[u] = idx[b0 + (r < nb ? r : 0)];
       }
+    };
+    if (r0 < r1) load_idx(r0, kr);
+    for (int64_t b0 = r0; b0 < r1; b0 += kSel) {
+      const int nb = (int)min((int64_t)kSel, r1 - b0);
 #pragma unroll
-      for (int u = 0; u < kSel / kT; ++u) {
+      for (int u = 0; u < KR; ++u) {
         const int r = u * kT + t;
         const int k = kr[u];
         if (r < nb && k >= k0 && k < k1) slist[atomicAdd(&snsel, 1)] = r * 8192 + (k - k0);
       }
+      int kn[KR];
+      const int64_t b1 = b0 + kSel;
+      load_idx(b1 < r1 ? b1 : b0, kn);  // the last batch reads its own indices again
       __syncthreads();
       const int nsel = snsel;
-      for (int e0 = g; e0 < nsel; e0 += NG * kUnroll) {
-        int kk[kUnroll];
-        float v[kUnroll][DPL][VW];
+      // two stages of kUnrollSel rows per group: the next stage's rows load
+      // while this stage's are added
+      auto load_stage = [&](int e0, int (&kk)[kUnrollSel], float (&v)[kUnrollSel][DPL][VW]) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kUnrollSel; ++u) {
           const int e = e0 + u * NG;
           const int packed = (e < nsel) ? slist[e] : -1;
           const int r = packed >= 0 ? packed >> 13 : 0;
           kk[u] = packed >= 0 ? (packed & 8191) : -1;
           load_dims<G, VW, DPL>(X + (b0 + r) * L, L, gl, v[u]);
         }
+      };
+      int kka[kUnrollSel], kkb[kUnrollSel];
+      float va[kUnrollSel][DPL][VW], vb[kUnrollSel][DPL][VW];
+      if (g < nsel) load_stage(g, kka, va);
+      for (int e0 = g; e0 < nsel; e0 += 2 * NG * kUnrollSel) {
+        const int e1 = e0 + NG * kUnrollSel, e2 = e1 + NG * kUnrollSel;
+        if (e1 < nsel) load_stage(e1, kkb, vb);
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-          if (kk[u] >= 0) add_row<G, VW, DPL>(sacc, scnt, nullptr, kk[u], L, gl, s, v[u]);
+        for (int u = 0; u < kUnrollSel; ++u)
+          if (kka[u] >= 0) add_row<G, VW, DPL>(sacc, scnt, nullptr, kka[u], L, gl, p2s, va[u]);
+        if (e1 >= nsel) break;
+        if (e2 < nsel) load_stage(e2, kka, va);
+#pragma unroll
+        for (int u = 0; u < kUnrollSel; ++u)
+          if (kkb[u] >= 0) add_row<G, VW, DPL>(sacc, scnt, nullptr, kkb[u], L, gl, p2s, vb[u]);
       }
       __syncthreads();
       if (t == 0) snsel = 0;
       __syncthreads();
+#pragma unroll
+      for (int u = 0; u < KR; ++u) kr[u] = kn[u];
     }
   }
   __syncthreads();
@@ -363,7 +418,7 @@ __device__ __forceinline__ void fin_body(const unsigned long long* __restrict__ 
         if (MODE == 0) {
           out[e] = (float)(ldexp((double)S, -s) / (double)cnt);
         } else {
-          const long long ck = llrint(ldexp((double)C_old[e], s));
+          const long long ck = fixed_wide(C_old[e], s);
           const long long diff = (long long)((unsigned long long)(cnt * ck) - (unsigned long long)S);
           out[e] = (float)(g2 * ldexp((double)diff, -s));
         }

@@ -201,9 +201,17 @@ __global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ ins
   N = B.st->n;
   const int s = *B.shift;
   const int L = B.L;
-#define LBG_BACC(GG, VV)                                                                    \
-  afp::acc_body<GG, VV, 1>(B.X, B.M, L, B.idx, N, B.cps, B.nslices, B.rows_per_chunk, s, \
-                           B.part, B.pcnt, local, sacc, slist, snsel)
+#define LBG_BACC(GG, VV)                                                                      \
+  do {                                                                                     \
+    if (B.nslices > 1)                                                                     \
+      afp::acc_body<GG, VV, 1, true>(B.X, B.M, L, B.idx, N, B.cps, B.nslices,              \
+                                     B.rows_per_chunk, s, B.part, B.pcnt, local, sacc,     \
+                                     slist, snsel);                                        \
+    else                                                                                   \
+      afp::acc_body<GG, VV, 1, false>(B.X, B.M, L, B.idx, N, B.cps, B.nslices,             \
+                                      B.rows_per_chunk, s, B.part, B.pcnt, local, sacc,    \
+                                      slist, snsel);                                       \
+  } while (0)
   if (B.vec && (L & 3) == 0) {
     const int lanes = L / 4;
     if (lanes <= 1)

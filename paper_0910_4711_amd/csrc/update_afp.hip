@@ -1,16 +1,18 @@
 // Codebook Updation by exact fixed-point accumulation.
 //
-// Every coordinate x is mapped to the integer round(x * 2^s), where the
-// shift s is chosen from the largest |x| of the training set so that a sum of
-// M such integers cannot overflow 62 bits: s = 61 - e - b with |x| < 2^e and
-// M < 2^b.  Cell sums are then formed with 64-bit integer additions, which
-// are exact and associative, so the order in which rows arrive (and the
-// atomics that LDS accumulation uses) cannot change the result: the update
-// is deterministic.  For data whose coordinates are multiples of 2^-s (for
-// instance integer pixels) the sums are the exact sums and the centroid is
-// the exact mean rounded once to FP64 and once to FP32.  Otherwise each
-// coordinate is rounded to a multiple of 2^-s first (relative error below
-// 2^-(61-b) of the largest |x|).
+// Every coordinate x is mapped to the integer round(x * 2^s) (nearest, ties
+// to even), where the shift s is chosen from the largest |x| of the training
+// set: s = min(51, 62 - b) - e with |x| < 2^e and M < 2^b, so that every
+// such integer is below 2^51 in magnitude (three operations convert it, see
+// fixed()) and a sum of M of them cannot overflow 63 bits.  Cell sums are
+// then formed with 64-bit integer additions, which are exact and
+// associative, so the order in which rows arrive (and the atomics that LDS
+// accumulation uses) cannot change the result: the update is deterministic.
+// For data whose coordinates are multiples of 2^-s (for instance integer
+// pixels) the sums are the exact sums and the centroid is the exact mean
+// rounded once to FP64 and once to FP32.  Otherwise each coordinate is
+// rounded to a multiple of 2^-s first (relative error below 2^-(s+e+1) of
+// the largest |x|: 2^-52 for small M, 2^-(63-b) beyond M = 2^11).
 //
 //   absmax    per block: largest |x| (as float bits; max is order-free)
 //   shift     one block: s from the block maxima
@@ -39,13 +41,13 @@ __global__ __launch_bounds__(kT) void shift_kernel(const uint32_t* __restrict__ 
   shift_body(part, nparts, M, shift);
 }
 
-template <int G, int VW, int DPL>
+template <int G, int VW, int DPL, bool SEL>
 __global__ __launch_bounds__(kT) void acc_kernel(
     const float* __restrict__ X, int64_t M, int L, const int32_t* __restrict__ idx, int N,
     int cps, int nslices, int64_t rows_per_chunk, const int* __restrict__ shift_p,
     unsigned long long* __restrict__ part, int32_t* __restrict__ pcnt, Ctl ctl) {
   extern __shared__ unsigned long long sacc[];
-  __shared__ int32_t slist[kSel];
+  __shared__ int32_t slist[SEL ? kSel : 1];
   __shared__ int32_t snsel;
   if (ctl.st) {
     // the decision (block 0 writes it for the update's last kernel) does not
@@ -54,8 +56,8 @@ __global__ __launch_bounds__(kT) void acc_kernel(
     if (blockIdx.x == 0) (void)acc_decide(ctl, true, &N);
     N = ctl.st->n;
   }
-  acc_body<G, VW, DPL>(X, M, L, idx, N, cps, nslices, rows_per_chunk, *shift_p, part, pcnt,
-                       blockIdx.x, sacc, slist, snsel);
+  acc_body<G, VW, DPL, SEL>(X, M, L, idx, N, cps, nslices, rows_per_chunk, *shift_p, part,
+                            pcnt, blockIdx.x, sacc, slist, snsel);
 }
 
 // One block per cell.
@@ -75,8 +77,12 @@ template <int G, int VW, int DPL>
 void launch_acc(dim3 grid, size_t lds, hipStream_t st, const float* X, int64_t M, int L,
                 const int32_t* idx, int N, int cps, int nslices, int64_t rpc, const int* sp,
                 unsigned long long* part, int32_t* pcnt, Ctl ctl) {
-  hipLaunchKernelGGL((acc_kernel<G, VW, DPL>), grid, dim3(kT), lds, st, X, M, L, idx, N, cps,
-                     nslices, rpc, sp, part, pcnt, ctl);
+  if (nslices > 1)
+    hipLaunchKernelGGL((acc_kernel<G, VW, DPL, true>), grid, dim3(kT), lds, st, X, M, L, idx, N,
+                       cps, nslices, rpc, sp, part, pcnt, ctl);
+  else
+    hipLaunchKernelGGL((acc_kernel<G, VW, DPL, false>), grid, dim3(kT), lds, st, X, M, L, idx,
+                       N, cps, nslices, rpc, sp, part, pcnt, ctl);
 }
 
 }  // namespace
