@@ -122,17 +122,20 @@ struct VLoad<1> {
   static __device__ __forceinline__ void get(const float* p, float* v) { v[0] = *p; }
 };
 
+// row += the row's fixed-point coordinates, *cnt += 1.  The caller passes
+// a spare row and count, never read, for a row that is off, so that the
+// adds need no branch.  In a full row (L = G VW DPL) dimension
+// (gl + q G) VW + e is kept at position e G DPL + q G + gl, so that the G
+// lanes of a group add into consecutive words (no LDS bank conflicts among
+// them); otherwise at position d.
 template <int G, int VW, int DPL>
-__device__ __forceinline__ void add_row(unsigned long long* sacc, int32_t* scnt,
-                                        const float* xrow,
-                                        int kk, int L, int gl, double p2s,
-                                        const float (&v)[DPL][VW]) {
-  unsigned long long* row = sacc + kk * L;
-  if (G * VW * DPL == L) {  // every lane's dimensions exist (a uniform test, once per row)
+__device__ __forceinline__ void add_row(unsigned long long* row, int32_t* cnt, int L, int gl,
+                                        double p2s, const float (&v)[DPL][VW]) {
+  if (G * VW * DPL == L) {  // a uniform test, once per row
 #pragma unroll
     for (int q = 0; q < DPL; ++q)
 #pragma unroll
-      for (int e = 0; e < VW; ++e) atomicAdd(&row[(gl + q * G) * VW + e], fixed(v[q][e], p2s));
+      for (int e = 0; e < VW; ++e) atomicAdd(&row[e * G * DPL + q * G + gl], fixed(v[q][e], p2s));
   } else {
 #pragma unroll
     for (int q = 0; q < DPL; ++q)
@@ -142,7 +145,20 @@ __device__ __forceinline__ void add_row(unsigned long long* sacc, int32_t* scnt,
         if (d < L) atomicAdd(&row[d], fixed(v[q][e], p2s));
       }
   }
-  if (gl == 0) atomicAdd(&scnt[kk], 1);
+  if (gl == 0) atomicAdd(cnt, 1);
+}
+
+// LDS position of dimension d in a row (see add_row).
+template <int G, int VW, int DPL>
+__device__ __forceinline__ int acc_pos(int d, int L) {
+  return (G * VW * DPL == L) ? (d % VW) * (G * DPL) + d / VW : d;
+}
+
+// Rows of sums are L + 1 words apart (rows of random cells then start on
+// different LDS banks).  LDS of an accumulation block: cps rows plus the
+// spare row, then cps + 1 counts.
+inline size_t acc_lds_bytes(int cps, int64_t L) {
+  return (size_t)(cps + 1) * (size_t)((L + 1) * 8 + 4);
 }
 
 // Loads are unconditional (no branch, so all rows of a batch are in flight
@@ -167,7 +183,7 @@ __device__ __forceinline__ void load_dims(const float* xrow, int L, int gl,
 // an LDS list (integer sums make the list order immaterial), then added.
 constexpr int kBatch = 1024;
 constexpr int kSel = 4096;  // several slices: about kSel / nslices rows gathered per batch
-constexpr int kUnrollSel = 16;  // gathered rows per group and stage
+constexpr int kUnrollSel = 16;  // gathered coordinates-groups per lane and stage
 
 // Decision of this iteration from the allocation's partials (the same in every
 // block that calls it); the block with ``lead`` records the next state in
@@ -213,8 +229,11 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
   int R = 1;
   if (nslices == 1 && nk > 0)
     while (R < 16 && 2 * R <= NG && 2 * R * nk <= cps) R *= 2;
-  const int TL = nk * L;  // entries of one copy
-  int32_t* scnt = reinterpret_cast<int32_t*>(sacc + (size_t)cps * L);
+  const int LS = L + 1;    // row stride
+  const int TL = nk * LS;  // entries of one copy
+  unsigned long long* spare = sacc + (size_t)cps * LS;  // R * nk <= cps rows are in use
+  int32_t* scnt = reinterpret_cast<int32_t*>(sacc + (size_t)(cps + 1) * LS);
+  int32_t* cspare = scnt + cps;
   const int t = threadIdx.x;
   for (int e = t; e < R * TL; e += kT) sacc[e] = 0ull;
   for (int e = t; e < R * nk; e += kT) scnt[e] = 0;
@@ -242,16 +261,20 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
           load_dims<G, VW, DPL>(X + m * L, L, gl, v[u]);
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-          if (k[u] >= k0 && k[u] < k1)
-            add_row<G, VW, DPL>(my_acc, my_cnt, nullptr, k[u] - k0, L, gl, p2s, v[u]);
+        for (int u = 0; u < kUnroll; ++u) {
+          const bool on = k[u] >= k0 && k[u] < k1;
+          const int kl = k[u] - k0;
+          add_row<G, VW, DPL>(on ? my_acc + __umul24(kl, LS) : spare, on ? my_cnt + kl : cspare,
+                              L, gl, p2s, v[u]);
+        }
       }
     }
   } else {
     // Several slices: batches of kSel cell indices; the next batch's indices
-    // are loaded while this batch's rows of the slice are gathered, kUnrollSel
+    // are loaded while this batch's rows of the slice are gathered, KU
     // rows per group in flight.
     constexpr int KR = kSel / kT;
+    constexpr int KU = kUnrollSel / DPL > 1 ? kUnrollSel / DPL : 1;  // rows per group and stage
     int kr[KR];
     auto load_idx = [&](int64_t b0, int (&dst)[KR]) {
       const int nb = (int)min((int64_t)kSel, r1 - b0);
@@ -275,11 +298,11 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
       load_idx(b1 < r1 ? b1 : b0, kn);  // the last batch reads its own indices again
       __syncthreads();
       const int nsel = snsel;
-      // two stages of kUnrollSel rows per group: the next stage's rows load
+      // two stages of KU rows per group: the next stage's rows load
       // while this stage's are added
-      auto load_stage = [&](int e0, int (&kk)[kUnrollSel], float (&v)[kUnrollSel][DPL][VW]) {
+      auto load_stage = [&](int e0, int (&kk)[KU], float (&v)[KU][DPL][VW]) {
 #pragma unroll
-        for (int u = 0; u < kUnrollSel; ++u) {
+        for (int u = 0; u < KU; ++u) {
           const int e = e0 + u * NG;
           const int packed = (e < nsel) ? slist[e] : -1;
           const int r = packed >= 0 ? packed >> 13 : 0;
@@ -287,20 +310,26 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
           load_dims<G, VW, DPL>(X + (b0 + r) * L, L, gl, v[u]);
         }
       };
-      int kka[kUnrollSel], kkb[kUnrollSel];
-      float va[kUnrollSel][DPL][VW], vb[kUnrollSel][DPL][VW];
+      int kka[KU], kkb[KU];
+      float va[KU][DPL][VW], vb[KU][DPL][VW];
       if (g < nsel) load_stage(g, kka, va);
-      for (int e0 = g; e0 < nsel; e0 += 2 * NG * kUnrollSel) {
-        const int e1 = e0 + NG * kUnrollSel, e2 = e1 + NG * kUnrollSel;
+      for (int e0 = g; e0 < nsel; e0 += 2 * NG * KU) {
+        const int e1 = e0 + NG * KU, e2 = e1 + NG * KU;
         if (e1 < nsel) load_stage(e1, kkb, vb);
 #pragma unroll
-        for (int u = 0; u < kUnrollSel; ++u)
-          if (kka[u] >= 0) add_row<G, VW, DPL>(sacc, scnt, nullptr, kka[u], L, gl, p2s, va[u]);
+        for (int u = 0; u < KU; ++u) {
+          const bool on = kka[u] >= 0;
+          add_row<G, VW, DPL>(on ? sacc + __umul24(kka[u], LS) : spare, on ? scnt + kka[u] : cspare,
+                              L, gl, p2s, va[u]);
+        }
         if (e1 >= nsel) break;
         if (e2 < nsel) load_stage(e2, kka, va);
 #pragma unroll
-        for (int u = 0; u < kUnrollSel; ++u)
-          if (kkb[u] >= 0) add_row<G, VW, DPL>(sacc, scnt, nullptr, kkb[u], L, gl, p2s, vb[u]);
+        for (int u = 0; u < KU; ++u) {
+          const bool on = kkb[u] >= 0;
+          add_row<G, VW, DPL>(on ? sacc + __umul24(kkb[u], LS) : spare, on ? scnt + kkb[u] : cspare,
+                              L, gl, p2s, vb[u]);
+        }
       }
       __syncthreads();
       if (t == 0) snsel = 0;
@@ -311,9 +340,11 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
   }
   __syncthreads();
   unsigned long long* dst = part + ((int64_t)chunk * N + k0) * L;
-  for (int e = t; e < TL; e += kT) {
-    unsigned long long a = sacc[e];
-    for (int r = 1; r < R; ++r) a += sacc[r * TL + e];
+  for (int e = t; e < nk * L; e += kT) {
+    const int k = e / L, d = e - k * L;
+    const int src = k * LS + acc_pos<G, VW, DPL>(d, L);
+    unsigned long long a = sacc[src];
+    for (int r = 1; r < R; ++r) a += sacc[r * TL + src];
     dst[e] = a;
   }
   int32_t* cdst = pcnt + (int64_t)chunk * N + k0;

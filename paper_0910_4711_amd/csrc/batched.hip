@@ -805,7 +805,7 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
       tot[k] += cnt[k];
       hp[(int64_t)k * (n + 1) + i + 1] = tot[k];
     }
-    acc_lds = std::max(acc_lds, (size_t)q.afp.cps * a.L * 8 + (size_t)q.afp.cps * 4);
+    acc_lds = std::max(acc_lds, afp::acc_lds_bytes(q.afp.cps, a.L));
     work += a.M * a.N * a.L;
     sumM += a.M;
     sumN += a.N;

@@ -88,7 +88,7 @@ void launch_acc(dim3 grid, size_t lds, hipStream_t st, const float* X, int64_t M
 }  // namespace
 
 void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w) {
-  w->cps = (int)std::min<int64_t>(std::min<int64_t>(N, 8192), kLdsBytes / (8 * L + 4));
+  w->cps = (int)std::min<int64_t>(std::min<int64_t>(N, 8192), kLdsBytes / (8 * (L + 1) + 4) - 1);
   w->nslices = (int)((N + w->cps - 1) / w->cps);
   // Partials at most half of X's bytes, at least one chunk per 256 rows
   // of work, about 512 blocks in all.
@@ -105,7 +105,7 @@ void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w) {
 }
 
 bool afp_usable(int64_t L, int64_t N) {
-  const int cps = (int)std::min<int64_t>(std::min<int64_t>(N, 8192), kLdsBytes / (8 * L + 4));
+  const int cps = (int)std::min<int64_t>(std::min<int64_t>(N, 8192), kLdsBytes / (8 * (L + 1) + 4) - 1);
   return cps >= 1 && (N + cps - 1) / cps <= 32;
 }
 
@@ -126,9 +126,15 @@ int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const f
   const int lanes = (int)((L + VW - 1) / VW);
   int G = 1;
   while (G < lanes && G < 64) G <<= 1;
+  // several slices, 16-byte rows: four vectors per lane, so that a row's
+  // bookkeeping is shared by sixteen coordinates
+  if (w.nslices > 1 && vec && lanes >= 4 && lanes % 4 == 0) {
+    G = 1;
+    while (4 * G < lanes) G <<= 1;
+  }
   const int DPL = (lanes + G - 1) / G;
   const dim3 grid((unsigned)(w.nchunks * w.nslices));
-  const size_t lds = (size_t)w.cps * L * 8 + (size_t)w.cps * 4;
+  const size_t lds = acc_lds_bytes(w.cps, L);
   const int n = (int)N, Li = (int)L;
 #define LBG_ACC(GG, VV, DD)                                                                     \
   if (G == GG && VW == VV && DPL == DD) {                                                       \
@@ -137,6 +143,7 @@ int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const f
   } else
   LBG_ACC(1, 4, 1) LBG_ACC(2, 4, 1) LBG_ACC(4, 4, 1) LBG_ACC(8, 4, 1) LBG_ACC(16, 4, 1)
   LBG_ACC(32, 4, 1) LBG_ACC(64, 4, 1)
+  LBG_ACC(1, 4, 4) LBG_ACC(2, 4, 4) LBG_ACC(4, 4, 4) LBG_ACC(8, 4, 4) LBG_ACC(16, 4, 4)
   LBG_ACC(1, 1, 1) LBG_ACC(2, 1, 1) LBG_ACC(4, 1, 1) LBG_ACC(8, 1, 1) LBG_ACC(16, 1, 1)
   LBG_ACC(32, 1, 1) LBG_ACC(64, 1, 1) LBG_ACC(64, 1, 2) LBG_ACC(64, 1, 3) LBG_ACC(64, 1, 4) {
     set_error("internal: no accumulation kernel for G=%d VW=%d DPL=%d", G, VW, DPL);
