@@ -217,12 +217,15 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
     }
   }
   // pinned host block: action trace, then the state
-  int32_t* acts = reinterpret_cast<int32_t*>(pinned_block(sizeof(DevState) + kTraceCap * 4));
+  int32_t* acts =
+      reinterpret_cast<int32_t*>(pinned_block(2 * sizeof(DevState) + kTraceCap * 4));
   if (!acts) {
     set_error("could not allocate pinned host memory");
     return LBG_EHIP;
   }
-  DevState* pin = reinterpret_cast<DevState*>(acts + kTraceCap);
+  DevState* pins[2] = {reinterpret_cast<DevState*>(acts + kTraceCap),
+                       reinterpret_cast<DevState*>(acts + kTraceCap) + 1};
+  DevState* pin = pins[0];
   memcpy(pin, &hs, sizeof(hs));
   LBG_TRY_HIP(hipMemcpyAsync(w.st, pin, sizeof(DevState), hipMemcpyHostToDevice, s));
   LBG_TRY_HIP(hipMemsetAsync(w.as.nfb, 0, sizeof(unsigned long long), s));
@@ -301,34 +304,62 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
   double ms[3] = {0.0, 0.0, 0.0};
   int32_t prev_assign = 0;
   int rc = LBG_OK;
-  for (;;) {
+  auto launch_batch = [&]() -> int {
     if (ge) {
       const hipError_t e = hipGraphLaunch(ge->exec, s);
-      if (e != hipSuccess) {
-        rc = hip_fail(e, "hipGraphLaunch");
+      return e == hipSuccess ? LBG_OK : hip_fail(e, "hipGraphLaunch");
+    }
+    return enqueue_batch(b, s, timed ? local_ev : nullptr);
+  };
+  if (!timed) {
+    // The next batch is enqueued before this batch's state is read back (its
+    // kernels return at once when the run has finished in this batch), so
+    // the device does not wait for the host between batches.
+    hipEvent_t read[2] = {nullptr, nullptr};
+    for (auto& e : read)
+      if (rc == LBG_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+        rc = hip_fail(hipGetLastError(), "hipEventCreate");
+    if (rc == LBG_OK) rc = launch_batch();
+    for (int cur = 0; rc == LBG_OK; cur ^= 1) {
+      if (hipMemcpyAsync(pins[cur], w.st, sizeof(DevState), hipMemcpyDeviceToHost, s) !=
+              hipSuccess ||
+          hipEventRecord(read[cur], s) != hipSuccess) {
+        rc = hip_fail(hipGetLastError(), "state readback");
         break;
       }
-    } else {
-      rc = enqueue_batch(b, s, timed ? local_ev : nullptr);
+      rc = launch_batch();
       if (rc < 0) break;
+      if (hipEventSynchronize(read[cur]) != hipSuccess) {
+        rc = hip_fail(hipGetLastError(), "state readback");
+        break;
+      }
+      if (pins[cur]->done) {
+        pin = pins[cur];
+        break;
+      }
     }
+    for (auto& e : read)
+      if (e) (void)hipEventDestroy(e);
+  }
+  // timed: one batch at a time, its events read after it
+  for (; timed && rc == LBG_OK;) {
+    rc = launch_batch();
+    if (rc < 0) break;
     if (hipMemcpyAsync(pin, w.st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(acts, w.Atrace, kTraceCap * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
       rc = hip_fail(hipGetLastError(), "state readback");
       break;
     }
-    if (timed) {
-      hipEvent_t(*ev)[3][2] = ge ? ge->ev : local_ev;
-      for (int i = 0; i < kBatchIters; ++i) {
-        const int a = prev_assign + i;
-        if (a >= pin->n_assign) break;
-        float t = 0.0f;
-        if (hipEventElapsedTime(&t, ev[i][0][0], ev[i][0][1]) == hipSuccess) ms[0] += t;
-        const int act = a < kTraceCap ? acts[a] : kActNone;
-        if (act == kActUpdate && hipEventElapsedTime(&t, ev[i][0][1], ev[i][1][1]) == hipSuccess)
-          ms[1] += t;
-      }
+    hipEvent_t(*ev)[3][2] = ge ? ge->ev : local_ev;
+    for (int i = 0; i < kBatchIters; ++i) {
+      const int a = prev_assign + i;
+      if (a >= pin->n_assign) break;
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, ev[i][0][0], ev[i][0][1]) == hipSuccess) ms[0] += t;
+      const int act = a < kTraceCap ? acts[a] : kActNone;
+      if (act == kActUpdate && hipEventElapsedTime(&t, ev[i][0][1], ev[i][1][1]) == hipSuccess)
+        ms[1] += t;
     }
     prev_assign = pin->n_assign;
     if (pin->done) break;
