@@ -294,6 +294,39 @@ def test_bf16_rescore_close_to_oracle(P, images, M, N):
     np.testing.assert_array_equal(host(mind), dd.astype(np.float32))
 
 
+# other dimensions: rows of exactly 16 floats, padded rows (33 -> 64, 100 ->
+# 128, 8 -> 16), Gaussian-mixture data
+@pytest.mark.parametrize("M,L,N", [(3000, 16, 200), (2500, 33, 64), (1500, 100, 40),
+                                   (2000, 8, 32), (777, 32, 300)])
+def test_bf16_rescore_dimensions(P, M, L, N):
+    X = _gmm(M + L, M, L, max(2, N // 4))
+    C = X[synth.distinct_rows(X, N, 1001)]
+    idx, mind = P.assign(dev(X), dev(C), P.BF16_RESCORE)
+    idx_o, d1, d2 = oracle.assign(X, C.astype(np.float64))
+    h = host(idx)
+    miss = h != idx_o
+    assert miss.mean() < 0.01
+    xx = (X.astype(np.float64) ** 2).sum(1)[miss]
+    assert np.all((d2 - d1)[miss] <= 2 ** -6 * (xx + d1[miss] + 1))
+    dd = ((X.astype(np.float64) - C.astype(np.float64)[h]) ** 2).sum(1)
+    np.testing.assert_array_equal(host(mind), dd.astype(np.float32))
+
+
+def test_train_bf16_one_update_within_tolerance(P):
+    # one Lloyd iteration from the same codebook: the BF16 form's codebook
+    # against the exact one (spec bar: relative 1e-3 per codevector)
+    X = synth.image_training_set((0, 1, 2, 3), 256, 256, 8)  # M = 4096, L = 64
+    C0 = X[synth.distinct_rows(X, 256, 1002)]
+    Cb, _, Db, _ = P.train(dev(X), 256, C_init=dev(C0), fixed_iters=1, precision=P.BF16_RESCORE)
+    Cf, _, Df, _ = P.train(dev(X), 256, C_init=dev(C0), fixed_iters=1)
+    ref = oracle.train(X, 256, C_init=C0.astype(np.float64), fixed_iters=1, store_fp32=True)
+    np.testing.assert_array_equal(host(Cf), ref["C"].astype(np.float32))
+    cb, cf = host(Cb).astype(np.float64), host(Cf).astype(np.float64)
+    rel = np.linalg.norm(cb - cf, axis=1) / np.maximum(np.linalg.norm(cf, axis=1), 1e-30)
+    assert rel.max() <= 1e-3
+    assert abs(Db - Df) <= 1e-3 * Df
+
+
 def test_backward_matches_oracle(P):
     X = _gmm(7, 6000, 16, 20)
     rng = np.random.default_rng(7)
