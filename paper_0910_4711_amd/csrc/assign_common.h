@@ -518,6 +518,30 @@ __device__ __forceinline__ void c_half(const float* __restrict__ C, int L,
 template <int LP>
 __device__ __forceinline__ double pair_dist(const float (&xv)[LP / 2], const float (&cr)[LP / 2],
                                             int L) {
+  if constexpr (LP <= 32) {
+    // the lane's squared differences once; lane (j, 0) adds them as the
+    // first half, lane (j, 1) as the second (same operations, same order)
+    double t[LP / 2];
+#pragma unroll
+    for (int q = 0; q < LP / 2; ++q) {
+      const double u = (double)xv[q] - (double)cr[q];
+      t[q] = u * u;
+    }
+    double a = 0.0;
+#pragma unroll
+    for (int q = 0; q < LP / 2; ++q)
+      if (q < L) a = a + t[q];
+    const uint64_t ab = (uint64_t)__double_as_longlong(a);
+    float la, ha, lb, hb;
+    pair_values(__uint_as_float((uint32_t)ab), la, ha);
+    pair_values(__uint_as_float((uint32_t)(ab >> 32)), lb, hb);
+    double c = __longlong_as_double(
+        (long long)(((uint64_t)__float_as_uint(lb) << 32) | __float_as_uint(la)));
+#pragma unroll
+    for (int q = 0; q < LP / 2; ++q)
+      if (LP / 2 + q < L) c = c + t[q];
+    return c;
+  }
   double s0 = 0.0;
 #pragma unroll
   for (int q = 0; q < LP / 2; ++q) {
