@@ -52,12 +52,6 @@ constexpr float kBig = 3.0e38f;    // squared norm of padding codevectors
 constexpr int kRowsPerTile = 128;  // training vectors per four-wave row tile
 constexpr int kWideLds = 163840;   // LDS of a CU: one eight-wave workgroup
 
-// Row of the 32 x 32 matrix-core result held in accumulator register r of
-// ``lane``: four groups of four rows, the two half-waves interleaved by four.
-__device__ __forceinline__ int out_row(int lane, int r) {
-  return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-}
-
 // ---------------------------------------------------------------- policy --
 // OCC: waves per SIMD the kernel is built for (2 .. 4, by register use); the
 // persistent grid holds 256 * OCC workgroups and each may stage up to
@@ -334,19 +328,6 @@ __device__ __forceinline__ void load_row(const float* __restrict__ p, int L, flo
 
 // Squared distance, FP64, direct form, dimensions in order, one rounding per
 // operation (the library is built without FMA contraction).
-template <int LP>
-__device__ __forceinline__ double d64_regs(const float (&x)[LP], const float (&c)[LP], int L) {
-  double s = 0.0;
-#pragma unroll
-  for (int l = 0; l < LP; ++l) {
-    if (l < L) {
-      const double t = (double)x[l] - (double)c[l];
-      s = s + t * t;
-    }
-  }
-  return s;
-}
-
 __device__ __forceinline__ double d64(const float* x, const float* c, int L) {
   double s = 0.0;
   for (int l = 0; l < L; ++l) {

@@ -82,18 +82,6 @@ struct Tabs {
   int64_t off[kNumPre];       // start of each family in b2i
 };
 
-// Largest i with pre[i] <= x (pre has n + 1 entries, pre[0] = 0).
-__device__ __forceinline__ int find_inst(const int64_t* __restrict__ pre, int n, int64_t x) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (pre[mid] <= x)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
 
 // ------------------------------------------------------------- allocation --
 // Slots [b0, b0 + cnt) of instance B: for each slot b the tiles b, b + G, ...
