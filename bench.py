@@ -138,6 +138,17 @@ def form_batched(args):
     side.synchronize()
     t_b = (time.perf_counter() - t0) / args.steps
     dist = st["total_distances"]
+    # one more run with an event pair around every round's allocation and
+    # update (direct launches): the kernels' own rooflines
+    with torch.cuda.stream(side):
+        res_t, st_t = P.train_batched(Xs, Ns, timing=True)
+    side.synchronize()
+    Ls = [x.shape[1] for x in Xs]
+    Ms = [x.shape[0] for x in Xs]
+    flops = sum(2.0 * L * r[3]["distances"] for L, r in zip(Ls, res_t))
+    upd_bytes = sum(r[3]["n_update"] * M * (4.0 * L + 4.0) for M, L, r in zip(Ms, Ls, res_t))
+    tf = flops / (st_t["ms_assign"] * 1e-3) / 1e12
+    gbs = upd_bytes / (st_t["ms_update"] * 1e-3) / 1e9
     # one lbg_train per instance, same data, same GPU
     ws = None
     for X, N in zip(Xs[:2], Ns[:2]):
@@ -165,6 +176,13 @@ def form_batched(args):
                    "instances": len(inst), "sum_M": int(sum(x.shape[0] for x in Xs)),
                    "grab": st["grab"], "grid": st["grid"], "graph": st["graph"],
                    "rounds": st["rounds"]},
+        "allocation_roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_FP32_MFMA_TFLOPS,
+                                "unit": "TFLOP/s", "frac": tf / PEAK_FP32_MFMA_TFLOPS,
+                                "ms_all_rounds": st_t["ms_assign"]},
+        "update_roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                            "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                            "ms_all_rounds": st_t["ms_update"],
+                            "algorithmic_bytes": upd_bytes},
         "per_instance_launches": {"value": dist / t_s, "ms_total": t_s * 1e3},
         "speedup_vs_per_instance": t_s / t_b,
         "identical_D_to_per_instance": f"{same}/{len(inst)}",

@@ -232,8 +232,8 @@ typedef struct lbg_instance {
   int32_t* idx_out;  /* DEVICE, M: its allocation */
 } lbg_instance;
 
-/* Launch configuration of the batched form.  grab: allocation items (one
- * item = one instance's share of one workgroup of the single-run kernel) a
+/* Launch configuration of the batched form.  grab: allocation slots (one
+ * slot = one instance's share of one workgroup of the single-run kernel) a
  * workgroup takes per queue access; grid: workgroups of the persistent
  * allocation launch.  0 selects them by the autotuner, which times the
  * candidates on the instances' final codebook sizes once per workload
@@ -241,12 +241,14 @@ typedef struct lbg_instance {
  * the result for the process.  graph != 0 (default) replays rounds from a
  * hipGraph (non-NULL streams), else launches them directly;
  * rounds_per_poll: rounds between host checks of the finished count
- * (direct launches). */
+ * (direct launches); timing != 0: direct launches with an event pair around
+ * every round's allocation and update (their sums in lbg_batch_stats). */
 typedef struct lbg_batch_config {
   int32_t grab;
   int32_t grid;
   int32_t graph;
   int32_t rounds_per_poll;
+  int32_t timing;
 } lbg_batch_config;
 
 void lbg_batch_config_default(lbg_batch_config* cfg);
@@ -259,6 +261,7 @@ typedef struct lbg_batch_result {
   int32_t n_assign;       /* allocations performed */
   int32_t n_update;       /* updates performed */
   int64_t fallback_rows;  /* rows searched again exhaustively */
+  int64_t distances;      /* sum over its allocations of M * n */
 } lbg_batch_result;
 
 typedef struct lbg_batch_stats {
@@ -269,6 +272,8 @@ typedef struct lbg_batch_stats {
   int32_t tuned;    /* 1 if this call ran the autotuner */
   int64_t total_distances;  /* sum over instances of sum M * n */
   double ms_tune;   /* time spent timing candidates */
+  double ms_assign; /* with timing: all rounds' allocation launches */
+  double ms_update; /* with timing: all rounds' update launches */
 } lbg_batch_stats;
 
 /* Workspace bytes for lbg_train_batched on these instances (0 on bad

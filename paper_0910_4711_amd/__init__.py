@@ -97,6 +97,7 @@ class BatchConfig(ct.Structure):
         ("grid", ct.c_int32),
         ("graph", ct.c_int32),
         ("rounds_per_poll", ct.c_int32),
+        ("timing", ct.c_int32),
     ]
 
 
@@ -108,6 +109,7 @@ class BatchResult(ct.Structure):
         ("n_assign", ct.c_int32),
         ("n_update", ct.c_int32),
         ("fallback_rows", ct.c_int64),
+        ("distances", ct.c_int64),
     ]
 
 
@@ -120,6 +122,8 @@ class BatchStats(ct.Structure):
         ("tuned", ct.c_int32),
         ("total_distances", ct.c_int64),
         ("ms_tune", ct.c_double),
+        ("ms_assign", ct.c_double),
+        ("ms_update", ct.c_double),
     ]
 
 
@@ -367,11 +371,13 @@ def train(X, N, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta=0.0,
 
 def train_batched(Xs, Ns, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta=0.0,
                   max_iter=1000, fixed_iters=0, grab=0, grid=0, graph=True,
-                  rounds_per_poll=8, workspace=None):
+                  rounds_per_poll=8, workspace=None, timing=False):
     """Independent LBG runs (Algorithm 1 on every instance) advanced together
     by the batched kernels.  Xs: list of [M_i x L_i] float32 device tensors,
     Ns: list of powers of two.  Returns (results, stats): results[i] =
-    (C_i, idx_i, D_i, info_i), each bit-identical to train(Xs[i], Ns[i])."""
+    (C_i, idx_i, D_i, info_i), each bit-identical to train(Xs[i], Ns[i]).
+    timing: direct launches with events around every round's allocation and
+    update (stats ms_assign, ms_update)."""
     if len(Xs) != len(Ns) or len(Xs) == 0:
         raise ValueError("need as many codebook sizes as training sets (at least one)")
     Xs = [_f32_2d(f"Xs[{i}]", X) for i, X in enumerate(Xs)]
@@ -397,6 +403,7 @@ def train_batched(Xs, Ns, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta
     lib.lbg_batch_config_default(ct.byref(cfg))
     cfg.grab, cfg.grid, cfg.graph = int(grab), int(grid), 1 if graph else 0
     cfg.rounds_per_poll = int(rounds_per_poll)
+    cfg.timing = 1 if timing else 0
     nb = lib.lbg_train_batched_workspace(inst, n)
     if nb == 0:
         raise LBGError("lbg_train_batched_workspace: bad instances")
@@ -413,9 +420,11 @@ def train_batched(Xs, Ns, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta
         r = res[i]
         results.append((C, idx, r.D, dict(status=r.status, n_levels=r.n_levels,
                                           n_assign=r.n_assign, n_update=r.n_update,
-                                          fallback_rows=r.fallback_rows)))
+                                          fallback_rows=r.fallback_rows,
+                                          distances=r.distances)))
     stats = dict(status=rc, rounds=st.rounds, grab=st.grab, grid=st.grid, graph=st.graph,
-                 tuned=st.tuned, total_distances=st.total_distances, ms_tune=st.ms_tune)
+                 tuned=st.tuned, total_distances=st.total_distances, ms_tune=st.ms_tune,
+                 ms_assign=st.ms_assign, ms_update=st.ms_update)
     return results, stats
 
 

@@ -210,8 +210,9 @@ __device__ __forceinline__ bool acc_decide(const Ctl& ctl, bool lead, int* N) {
 
 // Accumulation of block ``blk`` = (row chunk, cell slice) of the update;
 // slist (kSel entries when SEL) and snsel are the caller's LDS.  SEL: the
-// block's slice is one of several (nslices > 1).
-template <int G, int VW, int DPL, bool SEL>
+// block's slice is one of several (nslices > 1); US: coordinate groups per
+// lane and stage of its gathers (registers: two stages of US float4s).
+template <int G, int VW, int DPL, bool SEL, int US = kUnrollSel>
 __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M, int L,
                                          const int32_t* __restrict__ idx, int N, int cps,
                                          int nslices, int64_t rows_per_chunk, int s,
@@ -274,7 +275,7 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
     // are loaded while this batch's rows of the slice are gathered, KU
     // rows per group in flight.
     constexpr int KR = kSel / kT;
-    constexpr int KU = kUnrollSel / DPL > 1 ? kUnrollSel / DPL : 1;  // rows per group and stage
+    constexpr int KU = US / DPL > 1 ? US / DPL : 1;  // rows per group and stage
     int kr[KR];
     auto load_idx = [&](int64_t b0, int (&dst)[KR]) {
       const int nb = (int)min((int64_t)kSel, r1 - b0);

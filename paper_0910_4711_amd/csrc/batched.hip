@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ ins
 #define LBG_BACC(GG, VV)                                                                      \
   do {                                                                                     \
     if (B.nslices > 1)                                                                     \
-      afp::acc_body<GG, VV, 1, true>(B.X, B.M, L, B.idx, N, B.cps, B.nslices,              \
+      afp::acc_body<GG, VV, 1, true, 8>(B.X, B.M, L, B.idx, N, B.cps, B.nslices,           \
                                      B.rows_per_chunk, s, B.part, B.pcnt, local, sacc,     \
                                      slist, snsel);                                        \
     else                                                                                   \
@@ -457,18 +457,37 @@ struct Launch {
   int nchunks;
 };
 
-int launch_round(const Launch& l, int grid, hipStream_t s) {
+// ev (nullable): events recorded before the allocation, between it and the
+// update, and after the update.
+int launch_round(const Launch& l, int grid, hipStream_t s, hipEvent_t* ev = nullptr) {
+  if (ev) LBG_TRY_HIP(hipEventRecord(ev[0], s));
   hipLaunchKernelGGL(b_assign_kernel, dim3((unsigned)grid), dim3(kT), kBatchLds, s, l.inst,
                      l.chunks, l.nchunks, l.ctr);
   LBG_TRY_HIP(hipGetLastError());
+  if (ev) LBG_TRY_HIP(hipEventRecord(ev[1], s));
   hipLaunchKernelGGL(b_acc_kernel, dim3((unsigned)l.blocks[kPreAcc]), dim3(kT), l.acc_lds, s,
                      l.inst, l.n, l.pre, l.tb);
   LBG_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(b_fin_kernel, dim3((unsigned)l.blocks[kPreFin]), dim3(kT), 0, s, l.inst,
                      l.n, l.pre, l.tb, l.ctr, l.ctr + 1);
   LBG_TRY_HIP(hipGetLastError());
+  if (ev) LBG_TRY_HIP(hipEventRecord(ev[2], s));
   return LBG_OK;
 }
+
+// Event triples of the rounds between two polls (timed runs).
+struct RoundEvents {
+  std::vector<hipEvent_t> ev;
+  ~RoundEvents() {
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  int make(int rounds) {
+    ev.assign((size_t)rounds * 3, nullptr);
+    for (auto& e : ev) LBG_TRY_HIP(hipEventCreate(&e));
+    return LBG_OK;
+  }
+};
 
 // Autotuner: candidate (grab, grid) pairs timed on the allocation at every
 // instance's final codebook size; the fastest is cached per workload.
@@ -901,7 +920,8 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
   LBG_TRY_HIP(hipGetLastError());
 
   // rounds until every instance has finished
-  const bool use_graph = cfg->graph != 0 && s != nullptr;
+  const bool timing = cfg->timing != 0;
+  const bool use_graph = cfg->graph != 0 && s != nullptr && !timing;
   const int per_poll = use_graph ? kRoundsPerGraph
                                  : (cfg->rounds_per_poll > 0 ? cfg->rounds_per_poll
                                                              : kRoundsPerGraph);
@@ -921,15 +941,26 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
     glk.lock();
     LBG_TRY(get_graph(l, ws, grab, grid, s, &gexec));
   }
+  RoundEvents rev;
+  if (timing) LBG_TRY(rev.make(per_poll));
+  double ms_assign = 0.0, ms_update = 0.0;
   for (;;) {
     if (use_graph) {
       LBG_TRY_HIP(hipGraphLaunch(gexec, s));
     } else {
-      for (int r = 0; r < per_poll; ++r) LBG_TRY(launch_round(l, grid, s));
+      for (int r = 0; r < per_poll; ++r)
+        LBG_TRY(launch_round(l, grid, s, timing ? &rev.ev[(size_t)r * 3] : nullptr));
     }
     rounds += per_poll;
     LBG_TRY_HIP(hipMemcpyAsync(ndone_host, w.ctr + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     LBG_TRY_HIP(hipStreamSynchronize(s));
+    for (int r = 0; timing && r < per_poll; ++r) {
+      float a = 0.0f, u = 0.0f;
+      LBG_TRY_HIP(hipEventElapsedTime(&a, rev.ev[(size_t)r * 3], rev.ev[(size_t)r * 3 + 1]));
+      LBG_TRY_HIP(hipEventElapsedTime(&u, rev.ev[(size_t)r * 3 + 1], rev.ev[(size_t)r * 3 + 2]));
+      ms_assign += a;
+      ms_update += u;
+    }
     if ((int)*ndone_host >= n) break;
     if (rounds > max_rounds + 2 * kRoundsPerGraph) {
       set_error("lbg_train_batched: %d of %d instances unfinished after %d rounds",
@@ -961,6 +992,7 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
       res[i].n_assign = d.n_assign;
       res[i].n_update = d.n_update;
       res[i].fallback_rows = (int64_t)nf[(size_t)i];
+      res[i].distances = d.distances;
     }
   }
   if (stats) {
@@ -971,6 +1003,8 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
     stats->tuned = tuned ? 1 : 0;
     stats->total_distances = dist;
     stats->ms_tune = ms_tune;
+    stats->ms_assign = ms_assign;
+    stats->ms_update = ms_update;
   }
   return status;
 }

@@ -98,6 +98,16 @@ def test_batched_configuration_does_not_change_results(P, grab, grid, graph):
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[2] == b[2]
 
 
+def test_batched_timing_keeps_results(P):
+    data = _data(CASES[:4])
+    ref, _ = P.train_batched([dev(X) for X, _ in data], [N for _, N in data])
+    got, st = P.train_batched([dev(X) for X, _ in data], [N for _, N in data], timing=True)
+    assert st["graph"] == 0 and st["ms_assign"] > 0 and st["ms_update"] > 0
+    for a, b in zip(ref, got):
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[2] == b[2]
+        assert b[3]["distances"] > 0
+
+
 def test_batched_matches_oracle_on_images(P):
     img = synth.blocks(synth.image(0, 512, 512), 4).astype(np.float32)
     sets = [(img[:4096], 64), (img[4096:6144], 16), (img[8192:20480], 128)]
