@@ -212,7 +212,7 @@ __device__ __forceinline__ bool acc_decide(const Ctl& ctl, bool lead, int* N) {
 // slist (kSel entries when SEL) and snsel are the caller's LDS.  SEL: the
 // block's slice is one of several (nslices > 1); US: coordinate groups per
 // lane and stage of its gathers (registers: two stages of US float4s).
-template <int G, int VW, int DPL, bool SEL, int US = kUnrollSel>
+template <int G, int VW, int DPL, bool SEL, int US = kUnrollSel, int NT = kT>
 __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M, int L,
                                          const int32_t* __restrict__ idx, int N, int cps,
                                          int nslices, int64_t rows_per_chunk, int s,
@@ -223,7 +223,7 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
   const int chunk = (int)(blk / nslices), slice = (int)(blk % nslices);
   const double p2s = ldexp(1.0, s);
   const int k0 = slice * cps, k1 = min(N, k0 + cps), nk = max(0, k1 - k0);
-  constexpr int NG = kT / G;  // rows in parallel
+  constexpr int NG = NT / G;  // rows in parallel
   // With a single slice and few cells, R private copies of the table (row
   // group g adds into copy g % R) keep rows of one cell from meeting in the
   // same LDS atomic; the copies are added (integers) at the end.
@@ -236,8 +236,8 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
   int32_t* scnt = reinterpret_cast<int32_t*>(sacc + (size_t)(cps + 1) * LS);
   int32_t* cspare = scnt + cps;
   const int t = threadIdx.x;
-  for (int e = t; e < R * TL; e += kT) sacc[e] = 0ull;
-  for (int e = t; e < R * nk; e += kT) scnt[e] = 0;
+  for (int e = t; e < R * TL; e += NT) sacc[e] = 0ull;
+  for (int e = t; e < R * nk; e += NT) scnt[e] = 0;
   if (t == 0) snsel = 0;
   __syncthreads();
   const int g = t / G, gl = t % G;
@@ -246,23 +246,26 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
   const int64_t r0 = (int64_t)chunk * rows_per_chunk;
   const int64_t r1 = min(M, r0 + rows_per_chunk);
   if constexpr (!SEL) {
+    // rows b0 + g + NG i of the batch go to group g: a wave's groups load
+    // consecutive rows
+    constexpr int PER = kBatch / NG;  // rows of one group per batch
+    constexpr int KU1 = PER < kUnroll ? PER : kUnroll;
     for (int64_t b0 = r0; b0 < r1; b0 += kBatch) {
       const int nb = (int)min((int64_t)kBatch, r1 - b0);
-      constexpr int PER = kBatch / NG;  // rows of one group per batch
-      const int64_t gb = b0 + (int64_t)g * PER;
-      for (int i0 = 0; i0 < PER; i0 += kUnroll) {
-        int k[kUnroll];
-        float v[kUnroll][DPL][VW];
+      for (int i0 = 0; i0 < PER; i0 += KU1) {
+        int k[KU1];
+        float v[KU1][DPL][VW];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const bool on = (i0 + u < PER) && (g * PER + i0 + u < nb);
-          const int64_t m = on ? gb + i0 + u : b0;  // b0: a row of this batch
+        for (int u = 0; u < KU1; ++u) {
+          const int r = g + NG * (i0 + u);
+          const bool on = r < nb;
+          const int64_t m = b0 + (on ? r : 0);  // b0: a row of this batch
           const int kv = idx[m];
           k[u] = on ? kv : -1;
           load_dims<G, VW, DPL>(X + m * L, L, gl, v[u]);
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < KU1; ++u) {
           const bool on = k[u] >= k0 && k[u] < k1;
           const int kl = k[u] - k0;
           add_row<G, VW, DPL>(on ? my_acc + __umul24(kl, LS) : spare, on ? my_cnt + kl : cspare,
@@ -274,14 +277,14 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
     // Several slices: batches of kSel cell indices; the next batch's indices
     // are loaded while this batch's rows of the slice are gathered, KU
     // rows per group in flight.
-    constexpr int KR = kSel / kT;
+    constexpr int KR = kSel / NT;
     constexpr int KU = US / DPL > 1 ? US / DPL : 1;  // rows per group and stage
     int kr[KR];
     auto load_idx = [&](int64_t b0, int (&dst)[KR]) {
       const int nb = (int)min((int64_t)kSel, r1 - b0);
 #pragma unroll
       for (int u = 0; u < KR; ++u) {
-        const int r = u * kT + t;
+        const int r = u * NT + t;
         dst[u] = idx[b0 + (r < nb ? r : 0)];
       }
     };
@@ -290,7 +293,7 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
       const int nb = (int)min((int64_t)kSel, r1 - b0);
 #pragma unroll
       for (int u = 0; u < KR; ++u) {
-        const int r = u * kT + t;
+        const int r = u * NT + t;
         const int k = kr[u];
         if (r < nb && k >= k0 && k < k1) slist[atomicAdd(&snsel, 1)] = r * 8192 + (k - k0);
       }
@@ -341,7 +344,7 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
   }
   __syncthreads();
   unsigned long long* dst = part + ((int64_t)chunk * N + k0) * L;
-  for (int e = t; e < nk * L; e += kT) {
+  for (int e = t; e < nk * L; e += NT) {
     const int k = e / L, d = e - k * L;
     const int src = k * LS + acc_pos<G, VW, DPL>(d, L);
     unsigned long long a = sacc[src];
@@ -349,7 +352,7 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
     dst[e] = a;
   }
   int32_t* cdst = pcnt + (int64_t)chunk * N + k0;
-  for (int e = t; e < nk; e += kT) {
+  for (int e = t; e < nk; e += NT) {
     int32_t c = scnt[e];
     for (int r = 1; r < R; ++r) c += scnt[r * nk + e];
     cdst[e] = c;

@@ -41,8 +41,11 @@ __global__ __launch_bounds__(kT) void shift_kernel(const uint32_t* __restrict__ 
   shift_body(part, nparts, M, shift);
 }
 
+// One workgroup per (row chunk, cell slice): 1024 threads with a single
+// slice (one workgroup per CU keeps 16 waves busy on the chunk), 256 with
+// several (the gathers' registers allow no more).
 template <int G, int VW, int DPL, bool SEL>
-__global__ __launch_bounds__(kT) void acc_kernel(
+__global__ __launch_bounds__(SEL ? kT : 1024) void acc_kernel(
     const float* __restrict__ X, int64_t M, int L, const int32_t* __restrict__ idx, int N,
     int cps, int nslices, int64_t rows_per_chunk, const int* __restrict__ shift_p,
     unsigned long long* __restrict__ part, int32_t* __restrict__ pcnt, Ctl ctl) {
@@ -56,8 +59,9 @@ __global__ __launch_bounds__(kT) void acc_kernel(
     if (blockIdx.x == 0) (void)acc_decide(ctl, true, &N);
     N = ctl.st->n;
   }
-  acc_body<G, VW, DPL, SEL>(X, M, L, idx, N, cps, nslices, rows_per_chunk, *shift_p, part,
-                            pcnt, blockIdx.x, sacc, slist, snsel);
+  acc_body<G, VW, DPL, SEL, kUnrollSel, SEL ? kT : 1024>(X, M, L, idx, N, cps, nslices,
+                                                         rows_per_chunk, *shift_p, part, pcnt,
+                                                         blockIdx.x, sacc, slist, snsel);
 }
 
 // One block per cell.
@@ -81,7 +85,7 @@ void launch_acc(dim3 grid, size_t lds, hipStream_t st, const float* X, int64_t M
     hipLaunchKernelGGL((acc_kernel<G, VW, DPL, true>), grid, dim3(kT), lds, st, X, M, L, idx, N,
                        cps, nslices, rpc, sp, part, pcnt, ctl);
   else
-    hipLaunchKernelGGL((acc_kernel<G, VW, DPL, false>), grid, dim3(kT), lds, st, X, M, L, idx,
+    hipLaunchKernelGGL((acc_kernel<G, VW, DPL, false>), grid, dim3(1024), lds, st, X, M, L, idx,
                        N, cps, nslices, rpc, sp, part, pcnt, ctl);
 }
 
