@@ -211,11 +211,14 @@ __device__ __forceinline__ bool acc_decide(const Ctl& ctl, bool lead, int* N) {
 // Accumulation of block ``blk`` = (row chunk, cell slice) of the update;
 // slist (kSel entries when SEL) and snsel are the caller's LDS.  SEL: the
 // block's slice is one of several (nslices > 1); US: coordinate groups per
-// lane and stage of its gathers (registers: two stages of US float4s).
+// lane and stage of its gathers (registers: two stages of US float4s).  N:
+// cells of this update; ns: cells per chunk in the partials' layout (the
+// planned codebook size, so that the finishing kernel can address them
+// before it knows N).
 template <int G, int VW, int DPL, bool SEL, int US = kUnrollSel, int NT = kT>
 __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M, int L,
-                                         const int32_t* __restrict__ idx, int N, int cps,
-                                         int nslices, int64_t rows_per_chunk, int s,
+                                         const int32_t* __restrict__ idx, int N, int ns,
+                                         int cps, int nslices, int64_t rows_per_chunk, int s,
                                          unsigned long long* __restrict__ part,
                                          int32_t* __restrict__ pcnt, int64_t blk,
                                          unsigned long long* sacc, int32_t* slist,
@@ -343,7 +346,7 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
     }
   }
   __syncthreads();
-  unsigned long long* dst = part + ((int64_t)chunk * N + k0) * L;
+  unsigned long long* dst = part + ((int64_t)chunk * ns + k0) * L;
   for (int e = t; e < nk * L; e += NT) {
     const int k = e / L, d = e - k * L;
     const int src = k * LS + acc_pos<G, VW, DPL>(d, L);
@@ -351,7 +354,7 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
     for (int r = 1; r < R; ++r) a += sacc[r * TL + src];
     dst[e] = a;
   }
-  int32_t* cdst = pcnt + (int64_t)chunk * N + k0;
+  int32_t* cdst = pcnt + (int64_t)chunk * ns + k0;
   for (int e = t; e < nk; e += NT) {
     int32_t c = scnt[e];
     for (int r = 1; r < R; ++r) c += scnt[r * nk + e];
@@ -359,82 +362,104 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
   }
 }
 
-// One block per cell: thread (q, d) adds the partials of chunks q, q+Q, ...
-// (integers, so the order is immaterial), then the Q lane sums.
 // Under device control: acts on the pending state for cell ``k`` (a split
 // of codevector k, or nothing); the block with ``lead`` commits the state.
 // Returns true when cell k is to be updated, with N, C_old and out set.
-// ``ndone`` (nullable) counts runs that finish with this commit.
+// ``ndone`` (nullable) counts runs that finish with this commit.  The fields
+// it needs are loaded together (pend is valid whenever st is not done).
 __device__ __forceinline__ bool fin_state(const Ctl& ctl, const CbPair& cbp, int64_t k, bool lead,
                                           int L, int* N, const float** C_old, float** out,
                                           unsigned* ndone = nullptr) {
-  if (ctl.st->done) return false;
   const DevState* st = ctl.pend;
+  const int done = ctl.st->done;
+  const int action = st->action, n_src = st->n_src, src = st->src, dst = st->dst;
+  if (done) return false;
   if (lead && threadIdx.x == 0) {
     *ctl.st = *st;
     if (ndone && st->done) atomicAdd(ndone, 1u);
   }
-  if (st->action == kActSplit) {
+  if (action == kActSplit) {
     // Codebook Splitting of codevector k (the split kernel's arithmetic):
     // children 2k ("+") and 2k+1 ("-"), formed in FP64, rounded once.
-    if (k >= st->n_src) return false;
-    const float* Cs = cbp.c[st->src];
-    float* Cd = cbp.c[st->dst];
+    if (k >= n_src) return false;
+    const float* Cs = cbp.c[src];
+    float* Cd = cbp.c[dst];
     for (int d = threadIdx.x; d < L; d += kT)
       misc::split_pair(Cs[k * L + d], st->split_mode, st->eps, st->delta, &Cd[(2 * k) * L + d],
                        &Cd[(2 * k + 1) * L + d]);
     return false;
   }
-  if (st->action != kActUpdate) return false;
-  *N = st->n_src;
-  *C_old = cbp.c[st->src];
-  *out = cbp.c[st->dst];
+  if (action != kActUpdate) return false;
+  *N = n_src;
+  *C_old = cbp.c[src];
+  *out = cbp.c[dst];
   return k < *N;
 }
 
-// Centroid (MODE 0) or gradient (MODE 1) of cell k from the chunk partials.
-template <int MODE>
+// Centroid (MODE 0) or gradient (MODE 1) of cell k from the chunk partials
+// (ns cells per chunk).  The first partials and the counts are loaded
+// before ``gate(&C_old, &out)`` runs, so that its reads of the run's state
+// overlap them; gate returns false (the same in every thread) when cell k
+// is not to be updated.  Thread (q, d) adds the partials of chunks q, q+Q,
+// ... (integers, so the order is immaterial), then the Q lane sums.
+template <int MODE, class Gate>
 __device__ __forceinline__ void fin_body(const unsigned long long* __restrict__ part,
-                                         const int32_t* __restrict__ pcnt, int nchunks, int N,
-                                         int L, int s, const float* __restrict__ C_old,
-                                         float* __restrict__ out, int32_t* __restrict__ counts,
-                                         double g2, int k) {
+                                         const int32_t* __restrict__ pcnt, int nchunks, int ns,
+                                         int L, int s, int32_t* __restrict__ counts, double g2,
+                                         int k, Gate&& gate) {
+  constexpr int U = 16;  // partials in flight per thread
+  constexpr int UC = 8;  // counts in flight per thread
   __shared__ unsigned long long red[kT];
   __shared__ long long scount;
   const int t = threadIdx.x;
   int G2 = 1;
   while (G2 < L && G2 < kT) G2 <<= 1;
   const int Q = kT / G2;
-  // the count and the first dimension block's partials are loaded together
-  long long c = 0;
-  if (t < 64) {
-    int ch = t;
-    for (; ch + 3 * 64 < nchunks; ch += 4 * 64) {  // four loads in flight
-      const int c0 = pcnt[(int64_t)ch * N + k], c1 = pcnt[(int64_t)(ch + 64) * N + k];
-      const int c2 = pcnt[(int64_t)(ch + 128) * N + k], c3 = pcnt[(int64_t)(ch + 192) * N + k];
-      c += (long long)c0 + c1 + c2 + c3;
+  const int q = t / G2;
+  auto load_u = [&](int d, int chs, unsigned long long (&v)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ch = chs + q + Q * u;
+      v[u] = (d < L && ch < nchunks) ? part[((int64_t)ch * ns + k) * L + d] : 0ull;
     }
-    for (; ch < nchunks; ch += 64) c += pcnt[(int64_t)ch * N + k];
+  };
+  auto load_c = [&](int chs, int (&v)[UC]) {
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int ch = chs + t + 64 * u;
+      v[u] = ch < nchunks ? pcnt[(int64_t)ch * ns + k] : 0;
+    }
+  };
+  int cv[UC];
+  if (t < 64) load_c(0, cv);
+  unsigned long long a[U];
+  load_u(t % G2, 0, a);
+  const float* C_old = nullptr;
+  float* out = nullptr;
+  if (!gate(&C_old, &out)) return;
+  if (t < 64) {
+    long long c = 0;
+    for (int chs = 64 * UC;; chs += 64 * UC) {
+#pragma unroll
+      for (int u = 0; u < UC; ++u) c += cv[u];
+      if (chs >= nchunks) break;
+      load_c(chs, cv);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+    if (t == 0) scount = c;
   }
   for (int d0 = 0; d0 < L; d0 += G2) {
-    const int q = t / G2, d = d0 + t % G2;
-    unsigned long long a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (d < L) {
-      int ch = q;
-      for (; ch + 7 * Q < nchunks; ch += 8 * Q) {
+    const int d = d0 + t % G2;
+    if (d0 > 0) load_u(d, 0, a);
+    unsigned long long acc = 0;
+    for (int chs = Q * U;; chs += Q * U) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] += part[((int64_t)(ch + u * Q) * N + k) * L + d];
-      }
-      for (; ch < nchunks; ch += Q) a[0] += part[((int64_t)ch * N + k) * L + d];
+      for (int u = 0; u < U; ++u) acc += a[u];
+      if (chs >= nchunks) break;
+      load_u(d, chs, a);
     }
-    if (d0 == 0) {
-      if (t < 64) {
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
-        if (t == 0) scount = c;
-      }
-    }
-    red[t] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    red[t] = acc;
     __syncthreads();
     const long long cnt = scount;
     if (d0 == 0 && counts && t == 0) counts[k] = (int32_t)cnt;

@@ -192,11 +192,11 @@ __global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ ins
 #define LBG_BACC(GG, VV)                                                                      \
   do {                                                                                     \
     if (B.nslices > 1)                                                                     \
-      afp::acc_body<GG, VV, 1, true, 8>(B.X, B.M, L, B.idx, N, B.cps, B.nslices,           \
+      afp::acc_body<GG, VV, 1, true, 8>(B.X, B.M, L, B.idx, N, B.N, B.cps, B.nslices,           \
                                      B.rows_per_chunk, s, B.part, B.pcnt, local, sacc,     \
                                      slist, snsel);                                        \
     else                                                                                   \
-      afp::acc_body<GG, VV, 1, false>(B.X, B.M, L, B.idx, N, B.cps, B.nslices,             \
+      afp::acc_body<GG, VV, 1, false>(B.X, B.M, L, B.idx, N, B.N, B.cps, B.nslices,             \
                                       B.rows_per_chunk, s, B.part, B.pcnt, local, sacc,    \
                                       slist, snsel);                                       \
   } while (0)
@@ -246,10 +246,10 @@ __global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ ins
   const Ctl ctl{B.st, B.pend, B.dpart, (B.M + 31) / 32, B.Dtrace, B.Atrace};
   const CbPair cbp{{B.Cb[0], B.Cb[1]}};
   int N = B.N;
-  const float* c_old = nullptr;
-  float* dst = nullptr;
-  if (!afp::fin_state(ctl, cbp, k, k == 0, B.L, &N, &c_old, &dst, ndone)) return;
-  afp::fin_body<0>(B.part, B.pcnt, B.nchunks, N, B.L, *B.shift, c_old, dst, nullptr, 0.0, k);
+  afp::fin_body<0>(B.part, B.pcnt, B.nchunks, B.N, B.L, *B.shift, nullptr, 0.0, k,
+                   [&](const float** c_old, float** dst) {
+                     return afp::fin_state(ctl, cbp, k, k == 0, B.L, &N, c_old, dst, ndone);
+                   });
 }
 
 // ------------------------------------------------------------- set-up, end --

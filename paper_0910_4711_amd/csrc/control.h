@@ -84,13 +84,25 @@ __device__ inline void apply_step(const DevState* in, DevState* out, double D, S
 // Block-wide D = sum(parts) / M in a fixed order: thread t adds parts t,
 // t+256, ..., then a fixed tree.  Every block that calls it gets the same
 // value.  ``red`` is 256 doubles of LDS; blockDim.x must be at least 256
-// (threads beyond the first 256 only take part in the barriers).
+// (threads beyond the first 256 only take part in the barriers).  A thread
+// issues 32 loads before its first addition (up to 8192 partials in one
+// memory round trip); positions past the end read as +0, which leaves the
+// non-negative sum unchanged.
 __device__ inline double block_distortion(const double* __restrict__ parts, int64_t nparts,
                                           int64_t M, double* red) {
+  constexpr int U = 32;
   double acc = 0.0;
   if (threadIdx.x < 256) {
-#pragma unroll 8
-    for (int64_t p = threadIdx.x; p < nparts; p += 256) acc += parts[p];
+    for (int64_t b = threadIdx.x; b < nparts; b += 256 * U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t p = b + 256 * u;
+        v[u] = p < nparts ? parts[p] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc += v[u];
+    }
     red[threadIdx.x] = acc;
   }
   __syncthreads();

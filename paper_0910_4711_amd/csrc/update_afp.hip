@@ -52,6 +52,7 @@ __global__ __launch_bounds__(SEL ? kT : 1024) void acc_kernel(
   extern __shared__ unsigned long long sacc[];
   __shared__ int32_t slist[SEL ? kSel : 1];
   __shared__ int32_t snsel;
+  const int ns = N;  // cells per chunk in the partials (the planned size)
   if (ctl.st) {
     // the decision (block 0 writes it for the update's last kernel) does not
     // change what is accumulated, so the other blocks do not wait for it
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(SEL ? kT : 1024) void acc_kernel(
     if (blockIdx.x == 0) (void)acc_decide(ctl, true, &N);
     N = ctl.st->n;
   }
-  acc_body<G, VW, DPL, SEL, kUnrollSel, SEL ? kT : 1024>(X, M, L, idx, N, cps, nslices,
+  acc_body<G, VW, DPL, SEL, kUnrollSel, SEL ? kT : 1024>(X, M, L, idx, N, ns, cps, nslices,
                                                          rows_per_chunk, *shift_p, part, pcnt,
                                                          blockIdx.x, sacc, slist, snsel);
 }
@@ -71,10 +72,13 @@ __global__ __launch_bounds__(kT) void fin_kernel(
     int N, int L, const int* __restrict__ shift_p, const float* __restrict__ C_old,
     float* __restrict__ out, int32_t* __restrict__ counts, double g2, Ctl ctl, CbPair cbp) {
   const int k = blockIdx.x;
-  const float* c_old = C_old;
-  float* dst = out;
-  if (ctl.st && !fin_state(ctl, cbp, k, k == 0, L, &N, &c_old, &dst)) return;
-  fin_body<MODE>(part, pcnt, nchunks, N, L, *shift_p, c_old, dst, counts, g2, k);
+  const int s = *shift_p;
+  fin_body<MODE>(part, pcnt, nchunks, N, L, s, counts, g2, k,
+                 [&](const float** c_old, float** dst) {
+                   *c_old = C_old;
+                   *dst = out;
+                   return !ctl.st || fin_state(ctl, cbp, k, k == 0, L, &N, c_old, dst);
+                 });
 }
 
 template <int G, int VW, int DPL>
