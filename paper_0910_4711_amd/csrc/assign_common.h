@@ -198,16 +198,27 @@ __device__ __forceinline__ void pair_values(int v, int& lo, int& hi) {
   hi = __float_as_int(b);
 }
 
-// Value held by lane l ^ OFF (OFF a power of two below 64), without a
-// lane-address register: ds_swizzle (xor mode within 32 lanes) or, across
-// the two halves, v_permlane32_swap.
+// Partner of lane l at distance OFF (a power of two below 64) in a pairwise
+// reduction over the wave, by VALU instructions only (no LDS round trip):
+//   OFF 1, 2:   DPP quad permutation, exactly lane l ^ OFF;
+//   OFF 4:      DPP row_half_mirror, lane l ^ 7 within eight lanes; this is
+//               the value of lane l ^ 4 when every aligned group of four
+//               lanes holds one value (as after the steps 1 and 2 of a
+//               reduction);
+//   OFF 8:      DPP row_ror:8, exactly lane l ^ 8 within a row of 16;
+//   OFF 16, 32: v_permlane16_swap / v_permlane32_swap, exactly lane l ^ OFF.
 template <int OFF>
 __device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
   if constexpr (OFF == 32) {
     const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
     return (threadIdx.x & 32) ? r[0] : r[1];
+  } else if constexpr (OFF == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (threadIdx.x & 16) ? r[0] : r[1];
   } else {
-    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (OFF << 10) | 0x1f);
+    constexpr int ctrl = OFF == 1 ? 0xb1 : OFF == 2 ? 0x4e : OFF == 4 ? 0x141 : 0x128;
+    static_assert(OFF == 1 || OFF == 2 || OFF == 4 || OFF == 8, "lane distance");
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, ctrl, 0xf, 0xf, false);
   }
 }
 
@@ -223,7 +234,9 @@ __device__ __forceinline__ int xor_lane(int v) {
   return (int)xor_lane<OFF>((uint32_t)v);
 }
 
-// Smallest distance over the wave, lowest index on equal distances.
+// Smallest distance over the wave, lowest index on equal distances (a total
+// order, so the order of the steps does not matter); steps of increasing
+// distance, as xor_lane<4> requires.
 template <int OFF>
 __device__ __forceinline__ void argmin_step(double& best, int& bi) {
   const double ob = xor_lane<OFF>(best);
@@ -234,14 +247,15 @@ __device__ __forceinline__ void argmin_step(double& best, int& bi) {
   }
 }
 
-// Sum over the wave by a fixed butterfly (the same result in every lane).
+// Sum over the wave by a fixed pairwise tree, partners at distances 1, 2,
+// 4, ..., 32 (the same result in every lane).
 __device__ __forceinline__ double wave_sum(double v) {
-  v += xor_lane<32>(v);
-  v += xor_lane<16>(v);
-  v += xor_lane<8>(v);
-  v += xor_lane<4>(v);
-  v += xor_lane<2>(v);
   v += xor_lane<1>(v);
+  v += xor_lane<2>(v);
+  v += xor_lane<4>(v);
+  v += xor_lane<8>(v);
+  v += xor_lane<16>(v);
+  v += xor_lane<32>(v);
   return v;
 }
 
@@ -430,12 +444,12 @@ __device__ __forceinline__ void search_row(const float* __restrict__ xrow, int L
       bi = k;
     }
   }
-  argmin_step<32>(best, bi);
-  argmin_step<16>(best, bi);
-  argmin_step<8>(best, bi);
-  argmin_step<4>(best, bi);
-  argmin_step<2>(best, bi);
   argmin_step<1>(best, bi);
+  argmin_step<2>(best, bi);
+  argmin_step<4>(best, bi);
+  argmin_step<8>(best, bi);
+  argmin_step<16>(best, bi);
+  argmin_step<32>(best, bi);
   *best_d = best;
   *best_i = bi;
 }

@@ -99,8 +99,9 @@ void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w) {
   w->cps = (int)std::min<int64_t>(std::min<int64_t>(N, 8192), kLdsBytes / (8 * (L + 1) + 4) - 1);
   w->nslices = (int)((N + w->cps - 1) / w->cps);
   // Partials at most half of X's bytes, at least one chunk per 256 rows
-  // of work, about 512 blocks in all.
-  int64_t nch = std::max<int64_t>(1, 512 / w->nslices);
+  // of work; one 1024-thread block per CU with a single slice (one wave of
+  // blocks), about 512 blocks in all with several.
+  int64_t nch = w->nslices == 1 ? 256 : std::max<int64_t>(1, 512 / w->nslices);
   nch = std::min<int64_t>(nch, std::max<int64_t>(1, M / (4 * N)));
   nch = std::min<int64_t>(nch, std::max<int64_t>(1, (M + 255) / 256));
   w->nchunks = (int)nch;
