@@ -321,6 +321,74 @@ __device__ __forceinline__ Cand best_of(const Slots& sl, uint32_t lowmask, float
   return c;
 }
 
+// The two smallest keys of the vector (codevectors i1, i2) and a lower bound
+// k3 on the key of every other codevector, for the second acceptance test
+// of the FP32 screen.  A lane tracks the two smallest keys of each of its
+// slots, and a key it does not track is at least its slot's second; so
+// when the lane's two best lie in different slots r1, r2, every other key
+// of the lane is at least min(second of r1, second of r2, third smallest
+// first), and when both lie in slot r1, at least min(second smallest first,
+// second of r1).  The pair (j, 0), (j, 1) then merges its two sorted
+// triples.  Both lanes of the pair obtain the same result.
+struct Cand3 {
+  float k3;
+  int i1, i2;
+};
+
+__device__ __forceinline__ Cand3 best3_of(const Slots& sl, uint32_t lowmask, float ninf, int h) {
+  float m1 = INFINITY, m2 = INFINITY, m3 = INFINITY;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const float x = sl.mn[r];
+    m3 = __builtin_amdgcn_fmed3f(m2, m3, x);
+    m2 = __builtin_amdgcn_fmed3f(m1, m2, x);
+    m1 = __builtin_amdgcn_fmed3f(m1, x, ninf);
+  }
+  int r1 = 0;
+#pragma unroll
+  for (int r = 15; r >= 0; --r) r1 = sl.mn[r] == m1 ? r : r1;
+  int r2 = r1 == 0 ? 1 : 0;
+  float s2 = INFINITY, t2 = INFINITY;
+#pragma unroll
+  for (int r = 15; r >= 0; --r) {
+    const bool e = sl.mn[r] == m2 && r != r1;
+    r2 = e ? r : r2;
+    s2 = r == r1 ? sl.mn2[r] : s2;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) t2 = r == r2 ? sl.mn2[r] : t2;
+  const int row1 = 8 * (r1 >> 2) + 4 * h + (r1 & 3);
+  const int row2 = 8 * (r2 >> 2) + 4 * h + (r2 & 3);
+  const bool same = s2 <= m2;  // the lane's second best is slot r1's second
+  const float a1 = m1, a2 = same ? s2 : m2;
+  const float a3 = same ? s2 : fminf(fminf(s2, t2), m3);
+  const int ai1 = (int)((__float_as_uint(m1) & lowmask) << 5) + row1;
+  const int ai2 = same ? (int)((__float_as_uint(s2) & lowmask) << 5) + row1
+                       : (int)((__float_as_uint(m2) & lowmask) << 5) + row2;
+  float x1, y1, x2, y2, x3, y3;
+  int xi1, yi1, xi2, yi2;
+  pair_values(a1, x1, y1);
+  pair_values(a2, x2, y2);
+  pair_values(a3, x3, y3);
+  pair_values(ai1, xi1, yi1);
+  pair_values(ai2, xi2, yi2);
+  // merge (x1 <= x2 <= x3...) and (y1 <= y2 <= y3...)
+  const bool xw = x1 < y1 || (x1 == y1 && xi1 < yi1);
+  Cand3 c;
+  if (xw) {
+    c.i1 = xi1;
+    const bool x2w = x2 < y1 || (x2 == y1 && xi2 < yi1);
+    c.i2 = x2w ? xi2 : yi1;
+    c.k3 = x2w ? fminf(x3, y1) : fminf(x2, y2);
+  } else {
+    c.i1 = yi1;
+    const bool y2w = y2 < x1 || (y2 == x1 && yi2 < xi1);
+    c.i2 = y2w ? yi2 : xi1;
+    c.k3 = y2w ? fminf(y3, x1) : fminf(y2, x2);
+  }
+  return c;
+}
+
 // Row of L floats into registers (LP slots, zero beyond L), loads issued
 // together.
 template <int LP, bool VEC>
@@ -371,17 +439,27 @@ __device__ __forceinline__ double d64(const float* x, const float* c, int L) {
 // lane l scores codevectors l, l+64, ... in increasing order (strict <), then
 // the wave takes the smallest distance, lowest index on equal distances.
 // Codevectors come from the LDS-resident screen copy (-2c, exact) when the
-// whole codebook is staged, otherwise from C with vector loads.
+// whole codebook is staged, otherwise from C with vector loads.  With LP <=
+// 32 the row is taken from the registers of the pair that holds it (xv of
+// lanes jr and jr + 32, read into every lane) rather than from memory;
+// beyond that it is streamed from xrow with the codevectors.
 template <class SC, bool VEC>
 __device__ __forceinline__ void search_row(const float* __restrict__ xrow, int L,
                                            const float* __restrict__ C, int n,
-                                           const float* resident, int lane, double* best_d,
-                                           int* best_i) {
+                                           const float* resident, int lane,
+                                           const float (&xv)[SC::LP / 2], int jr,
+                                           double* best_d, int* best_i) {
   constexpr int LP = SC::LP;
   constexpr int W = LP < 16 ? LP : 16;
   constexpr bool XREG = LP <= 32;  // the row in registers; else streamed with c
   float xr[XREG ? LP : 1];
-  if constexpr (XREG) load_row<LP, VEC>(xrow, L, xr);
+  if constexpr (XREG) {
+#pragma unroll
+    for (int s = 0; s < LP / 2; ++s) {
+      xr[s] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv[s]), jr));
+      xr[LP / 2 + s] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv[s]), jr + 32));
+    }
+  }
   double best = INFINITY;
   int bi = 0x7fffffff;
   for (int k = lane; k < n; k += 64) {
@@ -656,6 +734,34 @@ __device__ __forceinline__ double finish_rows(const Slots& sl, const float* __re
   }
   if constexpr (SC::EXACT) {
     unsigned long long fl = __ballot(flag);
+    if (fl) {
+      // Second test for the rows that failed: the best two candidates
+      // rescored in FP64 (the closer taken, the lower index on equal
+      // distances), every other codevector bounded below by k3 through the
+      // same inequality.  This settles a near tie of two codevectors, such
+      // as the children of one split, without a search.
+      const Cand3 t3 = best3_of(sl, lowmask, ninf, h);
+      const bool ok = (unsigned)t3.i1 < (unsigned)n && (unsigned)t3.i2 < (unsigned)n &&
+                      t3.i1 != t3.i2;
+      float ca[LP / 2], cb[LP / 2];
+      c_half<SC, VEC>(C, L, reinterpret_cast<const float*>(resident), ok ? t3.i1 : 0, h, ca);
+      c_half<SC, VEC>(C, L, reinterpret_cast<const float*>(resident), ok ? t3.i2 : 0, h, cb);
+      double da, db;
+      pair_dist2<LP>(xv, ca, cb, L, da, db);
+      if (flag && ok) {
+        const bool second = db < da || (db == da && t3.i2 < t3.i1);
+        const double dw = second ? db : da;
+        const float rf = 2.0f * __builtin_sqrtf(xsq) + __builtin_sqrtf((float)dw);
+        const double E = (double)(bd.cE * rf * rf) + 1e-30;
+        const double lim = (double)t3.k3 * bd.invks - E;
+        if (dw * bd.dslack < lim) {
+          flag = false;
+          d = dw;
+          win = second ? t3.i2 : t3.i1;
+        }
+      }
+      fl = __ballot(flag);
+    }
     if (nfb && lane == 0 && fl) atomicAdd(nfb, (unsigned long long)__popcll(fl));
     while (fl) {
       const int src = __ffsll((long long)fl) - 1;
@@ -664,7 +770,8 @@ __device__ __forceinline__ double finish_rows(const Slots& sl, const float* __re
       double best;
       int bi;
       search_row<SC, VEC>(X + mf * (int64_t)L, L, C, n,
-                          reinterpret_cast<const float*>(resident), lane, &best, &bi);
+                          reinterpret_cast<const float*>(resident), lane, xv, src & 31, &best,
+                          &bi);
       if (lane == src) {
         d = best;
         win = bi;
