@@ -1138,6 +1138,85 @@ __device__ __forceinline__ double process_rows(
                               resident ? sA : nullptr, xk, xsq, w.bd, w.ninf);
 }
 
+// Direct allocation for small codebooks (FP32 screen, n <= kDirectN, LP <=
+// 32): one training vector per lane, FP64 distances to the n codevectors
+// (staged in LDS as FP64), dimensions in order, the first smallest taken.
+// That is what the exhaustive search computes and what the certified screen
+// returns, so indices and distances are the same; the partial of each 32
+// vectors is the butterfly of wave_sum over lanes that hold the distances
+// (its last step adds zeros there), so the partials are the same too.  At
+// such n this takes fewer instructions per vector than the screen and its
+// finishing work.  Each wave takes 64 consecutive vectors at a time and
+// loads the next 64 while it searches.
+constexpr int kDirectN = 8;
+
+template <class SC, bool VEC, int W>
+__device__ __forceinline__ void direct_rows(const float* __restrict__ X, int64_t M, int L,
+                                            const float* __restrict__ C, int n,
+                                            int32_t* __restrict__ idx, float* __restrict__ mind,
+                                            double* __restrict__ dpart, double* sC) {
+  constexpr int LP = SC::LP;
+  constexpr int NT = 64 * W;
+  for (int e = threadIdx.x; e < n * LP; e += NT) {
+    const int k = e / LP, l = e - k * LP;
+    sC[e] = l < L ? (double)C[(int64_t)k * L + l] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t ngroups = (M + 63) >> 6;
+  const int64_t step = (int64_t)gridDim.x * W;
+  float xr[LP];
+  auto load = [&](int64_t gg) {
+    const int64_t m = gg * 64 + lane;
+    if (gg < ngroups && m < M) {
+      load_row<LP, VEC>(X + m * (int64_t)L, L, xr);
+    } else {
+#pragma unroll
+      for (int s = 0; s < LP; ++s) xr[s] = 0.0f;
+    }
+  };
+  int64_t g = (int64_t)blockIdx.x * W + wave;
+  load(g);
+  for (; g < ngroups; g += step) {
+    const int64_t m = g * 64 + lane;
+    double xd[LP];
+#pragma unroll
+    for (int s = 0; s < LP; ++s) xd[s] = (double)xr[s];
+    load(g + step);
+    double best = INFINITY;
+    int bi = 0x7fffffff;
+#pragma unroll 2
+    for (int k = 0; k < n; ++k) {
+      const double* c = sC + k * LP;
+      double dk = 0.0;
+#pragma unroll
+      for (int l = 0; l < LP; ++l) {
+        if (l < L) {
+          const double t = xd[l] - c[l];
+          dk = dk + t * t;
+        }
+      }
+      if (dk < best) {
+        best = dk;
+        bi = k;
+      }
+    }
+    const bool live = m < M;
+    if (live) {
+      idx[m] = bi;
+      if (mind) mind[m] = (float)best;
+    }
+    double v = live ? best : 0.0;
+    v += xor_lane<1>(v);
+    v += xor_lane<2>(v);
+    v += xor_lane<4>(v);
+    v += xor_lane<8>(v);
+    v += xor_lane<16>(v);
+    if (dpart && (lane & 31) == 0 && live) dpart[m >> 5] = v;
+  }
+}
+
 // W waves per workgroup: 4 (OCC workgroups per CU), or 8 with one workgroup
 // per CU holding a codebook of up to kWideLds bytes resident.
 template <class SC, bool VEC, int W>
@@ -1160,6 +1239,13 @@ __global__ __launch_bounds__(64 * W, W == 4 ? SC::OCC : 1) void assign_kernel(
   typedef typename SC::elem E;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   E* sA = reinterpret_cast<E*>(smem);
+  if constexpr (SC::EXACT && LP <= 32) {
+    // the LDS holds at least 32 screen rows, more than n <= kDirectN FP64 rows
+    if (n <= kDirectN) {
+      direct_rows<SC, VEC, W>(X, M, L, C, n, idx, mind, dpart, reinterpret_cast<double*>(smem));
+      return;
+    }
+  }
 
   constexpr int NT = 64 * W;
   constexpr int RT = 32 * W;  // training vectors per row tile

@@ -69,6 +69,15 @@ ASSIGN_CASES = [
     (800, 100, 20, "gmm"),
     (600, 128, 129, "gmm"),
     (300, 200, 9, "gmm"),
+    # small codebooks take the direct FP64 search (several 64-vector groups
+    # per wave, ragged ends), and just above it the screen again
+    (70001, 16, 2, "gmm"),
+    (16383, 16, 2, "img"),
+    (4097, 16, 8, "img"),
+    (3001, 8, 4, "gmm"),
+    (2049, 32, 8, "gmm"),
+    (999, 17, 3, "gmm"),
+    (1000, 16, 9, "img"),
     # codebooks resident only in one eight-wave workgroup's LDS, and larger
     # ones staged chunk by chunk
     (5000, 16, 700, "img"),
