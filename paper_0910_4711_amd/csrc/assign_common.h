@@ -60,22 +60,46 @@ template <int LP_>
 struct Fp32Screen {
   static constexpr int LP = LP_;
   static constexpr int S = LP + 4;   // row stride, elements
+  static constexpr int PAD = LP;     // first element of the norm padding
   static constexpr int ESZ = 4;      // bytes per element
   static constexpr int NS = LP / 2;  // data K-steps per tile (half per lane half)
   static constexpr int OCC = LP <= 16 ? 3 : 2;
   static constexpr bool EXACT = true;
+  static constexpr bool SPLIT = false;
   static constexpr bool PF = LP <= 32;  // registers for the next tile's vectors
   typedef float elem;
+};
+
+// FP32-accurate screen from BF16 parts (exact result): -2c and x are each
+// split exactly into hi + mid + lo (BF16, eight significant bits each, RNE),
+// and v_mfma_f32_32x32x16_bf16 sums the six products hi.hi, hi.mid, mid.hi,
+// hi.lo, lo.hi, mid.mid (the three dropped ones are below 2^-24 |x||c|)
+// with the norm parts in FP32.  Row layout: hi, mid, lo (LP each), then the
+// norm padding [hi, mid, lo, 1, 1, 1, 0, 0] of |c|^2.
+template <int LP_>
+struct Bf16x3Screen {
+  static constexpr int LP = LP_;
+  static constexpr int S = 3 * LP + 8;
+  static constexpr int PAD = 3 * LP;
+  static constexpr int ESZ = 2;
+  static constexpr int NS = LP / 16;  // K-blocks of 16 dimensions per part
+  static constexpr int OCC = LP <= 16 ? 3 : 2;
+  static constexpr bool EXACT = true;
+  static constexpr bool SPLIT = true;
+  static constexpr bool PF = LP <= 32;
+  typedef __bf16 elem;
 };
 
 template <int LP_>
 struct Bf16Screen {
   static constexpr int LP = LP_;
   static constexpr int S = LP + 8;
+  static constexpr int PAD = LP;
   static constexpr int ESZ = 2;
   static constexpr int NS = LP / 16;
   static constexpr int OCC = LP <= 16 ? 4 : (LP <= 32 ? 3 : 2);
   static constexpr bool EXACT = false;
+  static constexpr bool SPLIT = false;
   static constexpr bool PF = LP <= 64;
   typedef __bf16 elem;
 };
@@ -95,11 +119,65 @@ inline int chunk_rows(int n_pad) {
   return n_pad <= cap ? n_pad : cap;
 }
 
+// v = hi + mid + lo exactly (for v within the normal BF16 range): each
+// residual is exact in FP32 and the last has at most eight significant bits.
 __device__ __forceinline__ void split3(float v, __bf16& hi, __bf16& mid, __bf16& lo) {
   hi = (__bf16)v;
   const float r = v - (float)hi;
   mid = (__bf16)r;
   lo = (__bf16)(r - (float)mid);
+}
+
+// The FP32 value of three parts (exact: (hi + mid) + lo needs no rounding).
+__device__ __forceinline__ float join3(__bf16 hi, __bf16 mid, __bf16 lo) {
+  return ((float)hi + (float)mid) + (float)lo;
+}
+
+// Norm padding of a screen row (|c|^2 already clamped to kBig).
+template <class SC>
+__device__ __forceinline__ void write_pad(typename SC::elem* pad, float nrm) {
+  if constexpr (SC::ESZ == 4) {
+    pad[0] = nrm;
+    pad[1] = 1.0f;
+    pad[2] = 0.0f;
+    pad[3] = 0.0f;
+  } else {
+    __bf16 hi, mid, lo;
+    split3(nrm, hi, mid, lo);
+    const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
+    pad[0] = hi;
+    pad[1] = mid;
+    pad[2] = lo;
+    pad[3] = one;
+    pad[4] = one;
+    pad[5] = one;
+    pad[6] = zero;
+    pad[7] = zero;
+  }
+}
+
+// Element d of a screen row: -2c stored (exact), split into parts when SPLIT.
+template <class SC>
+__device__ __forceinline__ void put_elem(typename SC::elem* row, int d, float c) {
+  const float v = -2.0f * c;
+  if constexpr (SC::SPLIT) {
+    __bf16 hi, mid, lo;
+    split3(v, hi, mid, lo);
+    row[d] = hi;
+    row[SC::LP + d] = mid;
+    row[2 * SC::LP + d] = lo;
+  } else {
+    row[d] = (typename SC::elem)v;
+  }
+}
+
+// The value the screen uses for element d (-2c, or its BF16 rounding).
+template <class SC>
+__device__ __forceinline__ float get_elem(const typename SC::elem* row, int d) {
+  if constexpr (SC::SPLIT)
+    return join3(row[d], row[SC::LP + d], row[2 * SC::LP + d]);
+  else
+    return (float)row[d];
 }
 
 // Codebook in the screen's row layout; one block per row.
@@ -115,14 +193,13 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ C, 
     C = cbp.c[st->cb];
     if (row >= ((n + 31) & ~31)) return;
   }
-  typedef typename SC::elem E;
   __shared__ double part[256];
   double q = 0.0;
+  typename SC::elem* out = Cp + (int64_t)row * SC::S;
   for (int d = t; d < SC::LP; d += 256) {
     const float v = (row < n && d < L) ? C[(int64_t)row * L + d] : 0.0f;
-    const E e = (E)(-2.0f * v);
-    Cp[(int64_t)row * SC::S + d] = e;
-    const double r = (double)(float)e;  // -2 * (rounded value)
+    put_elem<SC>(out, d, v);
+    const double r = (double)get_elem<SC>(out, d);  // -2 * (value the screen uses)
     q += r * r;
   }
   part[t] = q;
@@ -134,25 +211,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ C, 
   if (t == 0) {
     // at most kBig, so that the BF16 padding stays finite
     const float nrm = (row < n) ? fminf((float)(0.25 * part[0]), kBig) : kBig;
-    E* pad = Cp + (int64_t)row * SC::S + SC::LP;
-    if constexpr (SC::EXACT) {
-      pad[0] = nrm;
-      pad[1] = 1.0f;
-      pad[2] = 0.0f;
-      pad[3] = 0.0f;
-    } else {
-      __bf16 hi, mid, lo;
-      split3(nrm, hi, mid, lo);
-      const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
-      pad[0] = hi;
-      pad[1] = mid;
-      pad[2] = lo;
-      pad[3] = one;
-      pad[4] = one;
-      pad[5] = one;
-      pad[6] = zero;
-      pad[7] = zero;
-    }
+    write_pad<SC>(out + SC::PAD, nrm);
   }
 }
 
@@ -532,17 +591,45 @@ __device__ __forceinline__ void search_row(const float* __restrict__ xrow, int L
   *best_i = bi;
 }
 
-// Constants of the acceptance test of the FP32 screen.
+// Constants of the acceptance test of the exact screens.  E bounds the
+// screen's error for a codevector c with |c| <= |x| + sqrt(d(w)) as
+// cE rf^2 + eabs (1 + rf) + 1e-30, rf = 2 |x| + sqrt(d(w)) >= |x| + |c|:
+//   FP32 screen: cE = 2 gamma_{L+4} (1 + 2^-24);
+//   split screen: an FP32 sum of exact products and norm parts (absolute
+//     sum at most (1 + 2^-5) (|x| + |c|)^2), each addition taken with a
+//     relative error of 2u whatever the order and rounding inside the matrix
+//     core, gamma'_k = 2 k u / (1 - 2 k u).  The chain adds the five small
+//     products per dimension first, from zero: its n1 = 80 NS additions
+//     act on sums of at most 2^-7.9 (|x| + |c|)^2 of them; then the L
+//     products hi.hi and the six norm parts, n2 = L + 6 additions, act on
+//     the whole (|error| <= gamma'_n2 (1 + gamma'_n1) sum|terms| +
+//     gamma'_n1 sum|small terms|).  The dropped products and the norms'
+//     rounding to FP32 add below 2^-22 (|x| + |c|)^2; parts, products or
+//     sums below the normal range add at most T 2^-124 (1 + |x| + |c|),
+//     T = 6 (L + 1).
+// cE is raised by 2^-12 for its own FP32 evaluation.
 struct Bound {
-  float cE;      // 2 gamma_{L+4} (1 + 2^-24) (1 + 2^-12)
+  float cE;
+  double eabs;
   double invks;  // (1 - 2^-48) / (1 + 2^(tile_bits - 23))
   double dslack; // 1 + 4 (L + 2) 2^-53
 };
 
+template <class SC>
 __device__ __forceinline__ Bound bound_of(int L, int tile_bits) {
   Bound b;
-  const double k = (double)(L + 4) * 0x1p-24;
-  b.cE = (float)(2.0 * (k / (1.0 - k)) * (1.0 + 0x1p-24) * (1.0 + 0x1p-12));
+  if constexpr (SC::SPLIT) {
+    const double u2 = 0x1p-23;  // 2u
+    const double n1 = 80.0 * SC::NS, n2 = (double)L + 6.0;
+    const double g1 = n1 * u2 / (1.0 - n1 * u2), g2 = n2 * u2 / (1.0 - n2 * u2);
+    b.cE = (float)((g2 * (1.0 + g1) * (1.0 + 0x1p-5) + g1 * 0x1.2p-8 + 0x1p-22) *
+                   (1.0 + 0x1p-12));
+    b.eabs = 6.0 * (double)(L + 1) * 0x1p-124;
+  } else {
+    const double k = (double)(L + 4) * 0x1p-24;
+    b.cE = (float)(2.0 * (k / (1.0 - k)) * (1.0 + 0x1p-24) * (1.0 + 0x1p-12));
+    b.eabs = 0.0;
+  }
   b.invks = (1.0 - 0x1p-48) / (1.0 + ldexp(1.0, tile_bits - 23));
   b.dslack = 1.0 + 4.0 * (double)(L + 2) * 0x1p-53;
   return b;
@@ -553,11 +640,22 @@ __device__ __forceinline__ Bound bound_of(int L, int tile_bits) {
 // (-2c, exact: times -1/2) or from C.
 template <class SC, bool VEC>
 __device__ __forceinline__ void c_half(const float* __restrict__ C, int L,
-                                       const float* resident, int w, int h,
+                                       const typename SC::elem* resident, int w, int h,
                                        float (&cr)[SC::LP / 2]) {
   constexpr int H = SC::LP / 2;
-  if (resident) {
-    const float* r = resident + (int64_t)w * SC::S + h * H;
+  if (resident && SC::SPLIT) {
+    // -2c from its three parts (exact), times -1/2 (exact)
+    const __bf16* r = reinterpret_cast<const __bf16*>(resident) + (int64_t)w * SC::S + h * H;
+#pragma unroll
+    for (int q = 0; q < H; q += 8) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(r + q);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(r + SC::LP + q);
+      const bf16x8 c = *reinterpret_cast<const bf16x8*>(r + 2 * SC::LP + q);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) cr[q + e] = -0.5f * join3(a[e], b[e], c[e]);
+    }
+  } else if (resident) {
+    const float* r = reinterpret_cast<const float*>(resident) + (int64_t)w * SC::S + h * H;
 #pragma unroll
     for (int q = 0; q < H; q += 4) {
       const float4 v = *reinterpret_cast<const float4*>(r + q);
@@ -707,11 +805,11 @@ __device__ __forceinline__ double finish_rows(const Slots& sl, const float* __re
   if (bad) win = 0;
   if constexpr (SC::EXACT) {
     float cr[LP / 2];
-    c_half<SC, VEC>(C, L, reinterpret_cast<const float*>(resident), win, h, cr);
+    c_half<SC, VEC>(C, L, resident, win, h, cr);
     d = pair_dist<LP>(xv, cr, L);
     if (live) {
       const float rf = 2.0f * __builtin_sqrtf(xsq) + __builtin_sqrtf((float)d);
-      const double E = (double)(bd.cE * rf * rf) + 1e-30;
+      const double E = (double)(bd.cE * rf * rf) + bd.eabs * (1.0 + (double)rf) + 1e-30;
       const double lim = (double)t.k2 * bd.invks - E;
       flag = bad || !(d * bd.dslack < lim);
     }
@@ -744,15 +842,15 @@ __device__ __forceinline__ double finish_rows(const Slots& sl, const float* __re
       const bool ok = (unsigned)t3.i1 < (unsigned)n && (unsigned)t3.i2 < (unsigned)n &&
                       t3.i1 != t3.i2;
       float ca[LP / 2], cb[LP / 2];
-      c_half<SC, VEC>(C, L, reinterpret_cast<const float*>(resident), ok ? t3.i1 : 0, h, ca);
-      c_half<SC, VEC>(C, L, reinterpret_cast<const float*>(resident), ok ? t3.i2 : 0, h, cb);
+      c_half<SC, VEC>(C, L, resident, ok ? t3.i1 : 0, h, ca);
+      c_half<SC, VEC>(C, L, resident, ok ? t3.i2 : 0, h, cb);
       double da, db;
       pair_dist2<LP>(xv, ca, cb, L, da, db);
       if (flag && ok) {
         const bool second = db < da || (db == da && t3.i2 < t3.i1);
         const double dw = second ? db : da;
         const float rf = 2.0f * __builtin_sqrtf(xsq) + __builtin_sqrtf((float)dw);
-        const double E = (double)(bd.cE * rf * rf) + 1e-30;
+        const double E = (double)(bd.cE * rf * rf) + bd.eabs * (1.0 + (double)rf) + 1e-30;
         const double lim = (double)t3.k3 * bd.invks - E;
         if (dw * bd.dslack < lim) {
           flag = false;
@@ -769,9 +867,10 @@ __device__ __forceinline__ double finish_rows(const Slots& sl, const float* __re
       const int64_t mf = row0 + (src & 31);
       double best;
       int bi;
+      // (the split layout is not read back here: codevectors come from C)
       search_row<SC, VEC>(X + mf * (int64_t)L, L, C, n,
-                          reinterpret_cast<const float*>(resident), lane, xv, src & 31, &best,
-                          &bi);
+                          SC::SPLIT ? nullptr : reinterpret_cast<const float*>(resident), lane,
+                          xv, src & 31, &best, &bi);
       if (lane == src) {
         d = best;
         win = bi;
@@ -858,11 +957,12 @@ __device__ __forceinline__ void stage_from_C(const float* __restrict__ C, int n,
       for (int u = 0; u < 4; ++u) {
         const int e = base + u * NT + threadIdx.x;
         if (e < nv) {
-          E* dst = sA + (e / Q) * S + (e % Q) * 4;
-          dst[0] = (E)(-2.0f * v[u].x);
-          dst[1] = (E)(-2.0f * v[u].y);
-          dst[2] = (E)(-2.0f * v[u].z);
-          dst[3] = (E)(-2.0f * v[u].w);
+          E* row = sA + (e / Q) * S;
+          const int d = (e % Q) * 4;
+          put_elem<SC>(row, d, v[u].x);
+          put_elem<SC>(row, d + 1, v[u].y);
+          put_elem<SC>(row, d + 2, v[u].z);
+          put_elem<SC>(row, d + 3, v[u].w);
         }
       }
     }
@@ -870,7 +970,7 @@ __device__ __forceinline__ void stage_from_C(const float* __restrict__ C, int n,
     for (int e = threadIdx.x; e < n_pad * LP; e += NT) {
       const int r = e / LP, d = e % LP;
       const float v = (r < n && d < L) ? C[(int64_t)r * L + d] : 0.0f;
-      sA[r * S + d] = (E)(-2.0f * v);
+      put_elem<SC>(sA + r * S, d, v);
     }
   }
   __syncthreads();
@@ -878,29 +978,11 @@ __device__ __forceinline__ void stage_from_C(const float* __restrict__ C, int n,
     double q = 0.0;
 #pragma unroll 8
     for (int d = 0; d < LP; ++d) {
-      const double v = (double)(float)sA[r * S + d];
+      const double v = (double)get_elem<SC>(sA + r * S, d);
       q += v * v;
     }
     const float nrm = (r < n) ? fminf((float)(0.25 * q), kBig) : kBig;
-    E* pad = sA + r * S + LP;
-    if constexpr (SC::EXACT) {
-      pad[0] = nrm;
-      pad[1] = 1.0f;
-      pad[2] = 0.0f;
-      pad[3] = 0.0f;
-    } else {
-      __bf16 hi, mid, lo;
-      split3(nrm, hi, mid, lo);
-      const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
-      pad[0] = hi;
-      pad[1] = mid;
-      pad[2] = lo;
-      pad[3] = one;
-      pad[4] = one;
-      pad[5] = one;
-      pad[6] = zero;
-      pad[7] = zero;
-    }
+    write_pad<SC>(sA + r * S + SC::PAD, nrm);
   }
   __syncthreads();
 }
@@ -957,6 +1039,49 @@ struct Frag<Bf16Screen<LP>> {
 #pragma unroll
     for (int s = 0; s < NS; ++s)
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], xf[s], acc, 0, 0, 0);
+  }
+};
+
+// B operand of the split screen: lane (j, h) holds the parts of dimensions
+// [h LP/2, (h+1) LP/2) of vector j, eight per K-block.
+template <int NS>
+struct XSplit {
+  bf16x8 h[NS], m[NS], l[NS];
+};
+
+template <int LP>
+struct Frag<Bf16x3Screen<LP>> {
+  static constexpr int NS = LP / 16;
+  bf16x8 an;
+  bf16x8 hi[NS], mid[NS], lo[NS];
+  // the same K mapping per part as the BF16 screen (dimensions [h LP/2, ...)
+  // in steps of 8); both halves load the norm padding, which half 1's zero
+  // B operand cancels
+  __device__ __forceinline__ void load(const __bf16* ar, int h) {
+    an = *reinterpret_cast<const bf16x8*>(ar + 3 * LP);
+    const __bf16* p = ar + h * (LP / 2);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      hi[s] = *reinterpret_cast<const bf16x8*>(p + 8 * s);
+      mid[s] = *reinterpret_cast<const bf16x8*>(p + LP + 8 * s);
+      lo[s] = *reinterpret_cast<const bf16x8*>(p + 2 * LP + 8 * s);
+    }
+  }
+  // small products first, then hi.hi, then the norms
+  __device__ __forceinline__ void mma(const XSplit<NS>& x, const bf16x8& xn, f16v& acc) const {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(mid[0], x.m[0], f16v{}, 0, 0, 0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (s > 0) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(mid[s], x.m[s], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[s], x.h[s], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], x.l[s], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(mid[s], x.h[s], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], x.m[s], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], x.h[s], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an, xn, acc, 0, 0, 0);
   }
 };
 
@@ -1047,6 +1172,7 @@ struct WaveCtx {
   Bound bd;
 };
 
+template <class SC>
 __device__ __forceinline__ WaveCtx wave_ctx(int L, int tile_bits) {
   WaveCtx w;
   const int lane = threadIdx.x & 63;
@@ -1059,7 +1185,7 @@ __device__ __forceinline__ WaveCtx wave_ctx(int L, int tile_bits) {
   asm volatile("v_mov_b32 %0, %1" : "=v"(ninf) : "v"(ninf));
   w.vmask = vmask;
   w.ninf = ninf;
-  w.bd = bound_of(L, tile_bits);
+  w.bd = bound_of<SC>(L, tile_bits);
   return w;
 }
 
@@ -1084,11 +1210,30 @@ __device__ __forceinline__ double process_rows(
   // B operand: lane (j, h) keeps dims [h*LP/2, (h+1)*LP/2) of vector j and
   // the norm step's [1, |x|^2] (FP32) or [1, 1, 1, hi, mid, lo, 0, 0] /
   // zeros (BF16).
-  typedef typename std::conditional<SC::EXACT, float, bf16x8>::type BF;
-  BF xf[NS];
+  typedef typename std::conditional<SC::ESZ == 4, float, bf16x8>::type BF;
+  typedef typename std::conditional<SC::SPLIT, XSplit<NS>, BF[NS]>::type XF;
+  XF xf;
   BF xn;
   double ss = 0.0;
-  if constexpr (SC::EXACT) {
+  if constexpr (SC::SPLIT) {
+    // |x|^2 in FP64 from the FP32 vector, rounded once, split like |c|^2
+#pragma unroll
+    for (int s = 0; s < LP / 2; ++s) {
+      __bf16 a, b, c;
+      split3(xv[s], a, b, c);
+      xf.h[s >> 3][s & 7] = a;
+      xf.m[s >> 3][s & 7] = b;
+      xf.l[s >> 3][s & 7] = c;
+      ss += (double)xv[s] * (double)xv[s];
+    }
+    ss += xor_lane<32>(ss);
+    __bf16 hi, mid, lo;
+    split3(fminf((float)ss, kBig), hi, mid, lo);
+    const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
+    const bf16x8 nv = {one, one, one, hi, mid, lo, zero, zero};
+    const bf16x8 zv = {zero, zero, zero, zero, zero, zero, zero, zero};
+    xn = h ? zv : nv;
+  } else if constexpr (SC::EXACT) {
 #pragma unroll
     for (int s = 0; s < LP / 2; ++s) {
       xf[s] = xv[s];
@@ -1253,7 +1398,7 @@ __global__ __launch_bounds__(64 * W, W == 4 ? SC::OCC : 1) void assign_kernel(
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (SGPR)
   const int64_t ntiles_rows = (M + RT - 1) / RT;
   const bool resident = CR >= n_pad;
-  const WaveCtx w = wave_ctx(L, tile_bits);
+  const WaveCtx w = wave_ctx<SC>(L, tile_bits);
 
   float xv[LP / 2];
   int64_t rt = blockIdx.x;

@@ -108,7 +108,7 @@ __device__ __forceinline__ void alloc_chunk(const BInst& B, const DevState* st, 
   }
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const WaveCtx w = wave_ctx(L, tile_bits_of(n));
+  const WaveCtx w = wave_ctx<SC>(L, tile_bits_of(n));
   const int G = B.G;
   const int64_t nt = B.ntiles;
   float xv[LP / 2];
