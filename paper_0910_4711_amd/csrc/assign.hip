@@ -45,7 +45,7 @@ size_t prep_size(int64_t N, int precision) {
     constexpr int LB = LP < 16 ? 16 : LP;
     return (size_t)n_pad * Bf16Screen<LB>::S * 2;
   }
-  if (LP == 16) return (size_t)n_pad * Bf16x3Screen<16>::S * 2;
+  if (LP >= 16 && LP <= 64) return (size_t)n_pad * Bf16x3Screen<LP < 16 ? 16 : LP>::S * 2;
   return (size_t)n_pad * Fp32Screen<LP>::S * 4;
 }
 
@@ -109,8 +109,8 @@ int launch_assign(const float* X, int64_t M, int64_t L, const float* C, int64_t 
   switch (LP) {
     case 8: return launch_screen<Fp32Screen<8>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s, ctl, cbp);
     case 16: return launch_screen<Bf16x3Screen<16>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s, ctl, cbp);
-    case 32: return launch_screen<Fp32Screen<32>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s, ctl, cbp);
-    case 64: return launch_screen<Fp32Screen<64>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s, ctl, cbp);
+    case 32: return launch_screen<Bf16x3Screen<32>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s, ctl, cbp);
+    case 64: return launch_screen<Bf16x3Screen<64>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s, ctl, cbp);
     default: return launch_screen<Fp32Screen<128>>(X, M, Li, C, n, idx, mind, dpart, nfb, prep, s, ctl, cbp);
   }
 }
