@@ -504,7 +504,11 @@ def main():
             "traffic": traffic["bytes"] if traffic else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                             "copy-calibrated)",
-            "kernel": "allocation: assign_kernel<Fp32Screen<16>, vector loads>",
+            "kernel": "allocation: assign_kernel<Bf16x3Screen<16>, vector loads>",
+            "peak_basis": "FP32 MFMA peak for the 2L FP32 flops per distance the allocation "
+                          "must resolve; the kernel screens with BF16 hi/mid/lo parts "
+                          "(7 v_mfma_f32_32x32x16_bf16 per 32x32 tile at L = 16) and "
+                          "searches codebooks of n <= 8 directly in FP64",
             "launches": ev["assigns"],
             "event_steps": ev["steps"],
             "avg_launch_us": ev["ms_assign"] / ev["assigns"] * 1e3,
