@@ -1094,7 +1094,7 @@ __device__ __forceinline__ void screen_tiles(const typename SC::elem* ar, int nt
                                              int h, const XF& xf, const XN& xn, Slots& sl,
                                              uint32_t vmask, float ninf) {
   constexpr int TS = 32 * SC::S;  // elements per tile
-  constexpr bool DB = SC::LP <= 32;
+  constexpr bool DB = SC::LP <= 32 && !SC::SPLIT;
   if constexpr (SC::LP >= 128) {  // long K: the products dominate, no pipelining
     for (int t = 0; t < nt; ++t) {
       Frag<SC> f;
