@@ -264,7 +264,13 @@ def form_precision(args):
                      "assign_ms_total": ms_a, "update_ms_total": st["ms_update"],
                      "wall_ms": wall * 1e3, "assigns": st["total_assigns"],
                      "roofline": {"bound": "mfma", "achieved": tf, "peak": peak,
-                                  "unit": "TFLOP/s", "frac": tf / peak},
+                                  "unit": "TFLOP/s", "frac": tf / peak,
+                                  "peak_basis": ("FP32 MFMA peak for the 2L FP32 flops per "
+                                                 "distance; the exact kernel screens with BF16 "
+                                                 "hi/mid/lo parts (25 v_mfma_f32_32x32x16_bf16 "
+                                                 "per 32x32 tile at L = 64), so frac can exceed 1"
+                                                 if prec == P.FP32 else
+                                                 "BF16 MFMA peak, 2L flops per distance")},
                      "update_GBs": (st["total_updates"] * M * (4 * L + 4)
                                     / (st["ms_update"] * 1e-3) / 1e9
                                     if st["ms_update"] > 0 else None),
