@@ -188,23 +188,38 @@ constexpr int kUnrollSel = 16;  // gathered coordinates-groups per lane and stag
 // Decision of this iteration from the allocation's partials (the same in every
 // block that calls it); the block with ``lead`` records the next state in
 // ctl.pend.  Returns true when this iteration updates; *N receives the
-// codebook size.
+// codebook size.  The run state is read into LDS (a word per thread) beside
+// the partials' loads, stepped there by thread 0, and the pending state is
+// written back a word per thread, so the decision takes one memory round
+// trip.
 __device__ __forceinline__ bool acc_decide(const Ctl& ctl, bool lead, int* N) {
+  constexpr int NW = (int)(sizeof(DevState) / 4);
+  static_assert(sizeof(DevState) % 4 == 0 && NW <= kT, "state words");
   __shared__ double red[kT];
+  __shared__ DevState sst, spend;
   __shared__ int s_act;
-  const DevState* st = ctl.st;
-  if (st->done) return false;
-  const double D = block_distortion(ctl.dpart, ctl.nparts, st->M, red);
-  if (threadIdx.x == 0) {
-    const Step r = step_of(st, D);
-    s_act = r.action;
-    if (lead) {
-      *ctl.pend = *st;
-      apply_step(st, ctl.pend, D, r, ctl.Dtrace, ctl.Atrace);
+  const int t = threadIdx.x;
+  uint32_t word = 0;
+  if (t < NW) word = reinterpret_cast<const uint32_t*>(ctl.st)[t];
+  const double S = block_sum0(ctl.dpart, ctl.nparts, red);
+  if (t < NW) {
+    reinterpret_cast<uint32_t*>(&sst)[t] = word;
+    reinterpret_cast<uint32_t*>(&spend)[t] = word;  // the next state starts as a copy
+  }
+  __syncthreads();
+  if (t == 0) {
+    s_act = kActNone;
+    if (!sst.done) {
+      const double D = S / (double)sst.M;
+      const Step r = step_of(&sst, D);
+      s_act = r.action;
+      if (lead) apply_step(&sst, &spend, D, r, ctl.Dtrace, ctl.Atrace);
     }
   }
   __syncthreads();
-  *N = st->n;
+  if (lead && !sst.done && t < NW)
+    reinterpret_cast<uint32_t*>(ctl.pend)[t] = reinterpret_cast<const uint32_t*>(&spend)[t];
+  *N = sst.n;
   return s_act == kActUpdate;
 }
 

@@ -81,15 +81,44 @@ __device__ inline void apply_step(const DevState* in, DevState* out, double D, S
   }
 }
 
-// Block-wide D = sum(parts) / M in a fixed order: thread t adds parts t,
-// t+256, ..., then a fixed tree.  Every block that calls it gets the same
-// value.  ``red`` is 256 doubles of LDS; blockDim.x must be at least 256
-// (threads beyond the first 256 only take part in the barriers).  A thread
-// issues 32 loads before its first addition (up to 8192 partials in one
-// memory round trip); positions past the end read as +0, which leaves the
-// non-negative sum unchanged.
-__device__ inline double block_distortion(const double* __restrict__ parts, int64_t nparts,
-                                          int64_t M, double* red) {
+// Value of lane l ^ OFF (exactly), by VALU lane operations except for OFF 4.
+template <int OFF>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+  if constexpr (OFF == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (threadIdx.x & 32) ? r[0] : r[1];
+  } else if constexpr (OFF == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (threadIdx.x & 16) ? r[0] : r[1];
+  } else if constexpr (OFF == 8) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x128, 0xf, 0xf, false);  // row_ror:8
+  } else if constexpr (OFF == 4) {
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (4 << 10) | 0x1f);
+  } else {
+    static_assert(OFF == 1 || OFF == 2, "lane distance");
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, OFF == 1 ? 0xb1 : 0x4e, 0xf,
+                                                 0xf, false);  // quad_perm
+  }
+}
+
+template <int OFF>
+__device__ __forceinline__ double lane_xor(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint64_t lo = lane_xor<OFF>((uint32_t)b), hi = lane_xor<OFF>((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
+// Block-wide sum(parts) in a fixed order, valid in thread 0: thread t < 256
+// adds parts t, t+256, ... in order, then the tree red[t] += red[t + off]
+// for off = 128, 64, ..., 1.  Wave 0 forms the levels 128 and 64 from LDS
+// (lane l: (red[l] + red[l+128]) + (red[l+64] + red[l+192])) and the rest
+// from its registers (lane l < off adds lane l + off = l ^ off), so there is
+// one barrier.  ``red`` is 256 doubles of LDS; blockDim.x must be at least 256.
+// A thread issues 32 loads before its first addition (up to 8192 partials
+// in one memory round trip); positions past the end read as +0, which
+// leaves the non-negative sum unchanged.
+__device__ inline double block_sum0(const double* __restrict__ parts, int64_t nparts,
+                                    double* red) {
   constexpr int U = 32;
   double acc = 0.0;
   if (threadIdx.x < 256) {
@@ -106,13 +135,19 @@ __device__ inline double block_distortion(const double* __restrict__ parts, int6
     red[threadIdx.x] = acc;
   }
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
+  double v = 0.0;
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    v = (red[l] + red[l + 128]) + (red[l + 64] + red[l + 192]);
+    v = v + lane_xor<32>(v);
+    v = v + lane_xor<16>(v);
+    v = v + lane_xor<8>(v);
+    v = v + lane_xor<4>(v);
+    v = v + lane_xor<2>(v);
+    v = v + lane_xor<1>(v);
   }
-  const double D = red[0] / (double)M;
-  __syncthreads();
-  return D;
+  __syncthreads();  // red may be reused
+  return v;
 }
 
 // Decide step by one block (the standalone kernel): the state is updated in
@@ -120,8 +155,9 @@ __device__ inline double block_distortion(const double* __restrict__ parts, int6
 __device__ inline void decide_block(const double* __restrict__ parts, int64_t nparts,
                                     DevState* st, double* __restrict__ Dtrace,
                                     int32_t* __restrict__ Atrace, double* red) {
-  const double D = block_distortion(parts, nparts, st->M, red);
+  const double S = block_sum0(parts, nparts, red);
   if (threadIdx.x != 0) return;
+  const double D = S / (double)st->M;
   const Step r = step_of(st, D);
   apply_step(st, st, D, r, Dtrace, Atrace);
 }
