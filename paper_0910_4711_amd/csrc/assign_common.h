@@ -330,8 +330,16 @@ struct Cand {
   int i1, i2;
 };
 
+// The lane's own reduction, kept for the second acceptance test: its two
+// smallest first keys m1 <= m2, the slot r1 of m1 and that slot's second s2.
+struct LaneBest {
+  float m1, m2, s2;
+  int r1;
+};
+
 template <bool SECOND>
-__device__ __forceinline__ Cand best_of(const Slots& sl, uint32_t lowmask, float ninf, int h) {
+__device__ __forceinline__ Cand best_of(const Slots& sl, uint32_t lowmask, float ninf, int h,
+                                        LaneBest* lb = nullptr) {
   float m1 = INFINITY, m2 = INFINITY;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -346,6 +354,7 @@ __device__ __forceinline__ Cand best_of(const Slots& sl, uint32_t lowmask, float
     s2 = e ? sl.mn2[r] : s2;
     r1 = e ? r : r1;
   }
+  if (lb) *lb = LaneBest{m1, m2, s2, r1};
   const int row1 = 8 * (r1 >> 2) + 4 * h + (r1 & 3);
   const float k2l = __builtin_amdgcn_fmed3f(m2, s2, ninf);
   const int i1l = (int)((__float_as_uint(m1) & lowmask) << 5) + row1;
@@ -394,28 +403,22 @@ struct Cand3 {
   int i1, i2;
 };
 
-__device__ __forceinline__ Cand3 best3_of(const Slots& sl, uint32_t lowmask, float ninf, int h) {
-  float m1 = INFINITY, m2 = INFINITY, m3 = INFINITY;
+__device__ __forceinline__ Cand3 best3_of(const Slots& sl, uint32_t lowmask, int h,
+                                          const LaneBest& lb) {
+  // m1, m2, r1 and s2 come from the first test's reduction; r2 is the lowest
+  // other slot whose first key is m2, t2 its second, m3 the smallest first
+  // key of the other slots (the third smallest of the lane)
+  const float m1 = lb.m1, m2 = lb.m2, s2 = lb.s2;
+  const int r1 = lb.r1;
+  int r2 = r1 == 0 ? 1 : 0;
+#pragma unroll
+  for (int r = 15; r >= 0; --r) r2 = (sl.mn[r] == m2 && r != r1) ? r : r2;
+  float t2 = INFINITY, m3 = INFINITY;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const float x = sl.mn[r];
-    m3 = __builtin_amdgcn_fmed3f(m2, m3, x);
-    m2 = __builtin_amdgcn_fmed3f(m1, m2, x);
-    m1 = __builtin_amdgcn_fmed3f(m1, x, ninf);
+    t2 = r == r2 ? sl.mn2[r] : t2;
+    m3 = (r != r1 && r != r2) ? fminf(m3, sl.mn[r]) : m3;
   }
-  int r1 = 0;
-#pragma unroll
-  for (int r = 15; r >= 0; --r) r1 = sl.mn[r] == m1 ? r : r1;
-  int r2 = r1 == 0 ? 1 : 0;
-  float s2 = INFINITY, t2 = INFINITY;
-#pragma unroll
-  for (int r = 15; r >= 0; --r) {
-    const bool e = sl.mn[r] == m2 && r != r1;
-    r2 = e ? r : r2;
-    s2 = r == r1 ? sl.mn2[r] : s2;
-  }
-#pragma unroll
-  for (int r = 0; r < 16; ++r) t2 = r == r2 ? sl.mn2[r] : t2;
   const int row1 = 8 * (r1 >> 2) + 4 * h + (r1 & 3);
   const int row2 = 8 * (r2 >> 2) + 4 * h + (r2 & 3);
   const bool same = s2 <= m2;  // the lane's second best is slot r1's second
@@ -795,7 +798,8 @@ __device__ __forceinline__ double finish_rows(const Slots& sl, const float* __re
   const int j = lane & 31;
   const uint32_t lowmask = (1u << tile_bits) - 1u;
 
-  const Cand t = best_of<!SC::EXACT>(sl, lowmask, ninf, h);
+  LaneBest lb;
+  const Cand t = best_of<!SC::EXACT>(sl, lowmask, ninf, h, SC::EXACT ? &lb : nullptr);
   const int64_t m = row0 + j;
   const bool live = h == 1 && m < M;
   bool flag = false;
@@ -837,16 +841,16 @@ __device__ __forceinline__ double finish_rows(const Slots& sl, const float* __re
       // rescored in FP64 (the closer taken, the lower index on equal
       // distances), every other codevector bounded below by k3 through the
       // same inequality.  This settles a near tie of two codevectors, such
-      // as the children of one split, without a search.
-      const Cand3 t3 = best3_of(sl, lowmask, ninf, h);
-      const bool ok = (unsigned)t3.i1 < (unsigned)n && (unsigned)t3.i2 < (unsigned)n &&
-                      t3.i1 != t3.i2;
-      float ca[LP / 2], cb[LP / 2];
-      c_half<SC, VEC>(C, L, resident, ok ? t3.i1 : 0, h, ca);
+      // as the children of one split, without a search.  The best candidate
+      // is the first test's (the same keys and rule), so its distance d is
+      // reused.
+      const Cand3 t3 = best3_of(sl, lowmask, h, lb);
+      const bool ok = t3.i1 == win && !bad && (unsigned)t3.i2 < (unsigned)n && t3.i2 != win;
+      float cb[LP / 2];
       c_half<SC, VEC>(C, L, resident, ok ? t3.i2 : 0, h, cb);
-      double da, db;
-      pair_dist2<LP>(xv, ca, cb, L, da, db);
+      const double db = pair_dist<LP>(xv, cb, L);
       if (flag && ok) {
+        const double da = d;
         const bool second = db < da || (db == da && t3.i2 < t3.i1);
         const double dw = second ? db : da;
         const float rf = 2.0f * __builtin_sqrtf(xsq) + __builtin_sqrtf((float)dw);
