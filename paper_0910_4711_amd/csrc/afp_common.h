@@ -385,13 +385,20 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
 __device__ __forceinline__ bool fin_state(const Ctl& ctl, const CbPair& cbp, int64_t k, bool lead,
                                           int L, int* N, const float** C_old, float** out,
                                           unsigned* ndone = nullptr) {
+  constexpr int NW = (int)(sizeof(DevState) / 4);
+  static_assert(sizeof(DevState) % 4 == 0 && NW <= kT, "state words");
   const DevState* st = ctl.pend;
+  const int t = threadIdx.x;
+  // the commit copies the pending state a word per thread; its loads are
+  // issued with the others
+  uint32_t word = 0;
+  if (lead && t < NW) word = reinterpret_cast<const uint32_t*>(st)[t];
   const int done = ctl.st->done;
   const int action = st->action, n_src = st->n_src, src = st->src, dst = st->dst;
   if (done) return false;
-  if (lead && threadIdx.x == 0) {
-    *ctl.st = *st;
-    if (ndone && st->done) atomicAdd(ndone, 1u);
+  if (lead) {
+    if (t < NW) reinterpret_cast<uint32_t*>(ctl.st)[t] = word;
+    if (ndone && t == 0 && st->done) atomicAdd(ndone, 1u);
   }
   if (action == kActSplit) {
     // Codebook Splitting of codevector k (the split kernel's arithmetic):
