@@ -15,6 +15,10 @@ namespace lbg {
 namespace {
 
 constexpr int kBatchIters = 8;
+// Iterations per batch once the final level has begun (untimed direct
+// launches): a run ends during it, and a shorter batch leaves fewer no-op
+// launches queued behind the last iteration.
+constexpr int kTailIters = 2;
 // Timing events only order the stream on the device: no system-scope fence.
 constexpr unsigned kEventFlags = hipEventDisableSystemFence;
 
@@ -90,9 +94,10 @@ inline hipEvent_t event_after(hipEvent_t (*ev)[3][2], int i, int piece) {
   return piece == 0 ? ev[i][0][1] : ev[i][1][1];
 }
 
-// kBatchIters iterations launched directly.
-int enqueue_batch(const Batch& b, hipStream_t s, hipEvent_t (*ev)[3][2]) {
-  for (int i = 0; i < kBatchIters; ++i)
+// ``iters`` (at most kBatchIters) iterations launched directly.
+int enqueue_batch(const Batch& b, hipStream_t s, hipEvent_t (*ev)[3][2],
+                  int iters = kBatchIters) {
+  for (int i = 0; i < iters; ++i)
     for (int piece = 0; piece < kPieces; ++piece) {
       if (ev && event_before(ev, i, piece))
         LBG_TRY_HIP(hipEventRecord(event_before(ev, i, piece), s));
@@ -304,12 +309,13 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
   double ms[3] = {0.0, 0.0, 0.0};
   int32_t prev_assign = 0;
   int rc = LBG_OK;
+  int iters = kBatchIters;  // of the next untimed direct batch
   auto launch_batch = [&]() -> int {
     if (ge) {
       const hipError_t e = hipGraphLaunch(ge->exec, s);
       return e == hipSuccess ? LBG_OK : hip_fail(e, "hipGraphLaunch");
     }
-    return enqueue_batch(b, s, timed ? local_ev : nullptr);
+    return timed ? enqueue_batch(b, s, local_ev) : enqueue_batch(b, s, nullptr, iters);
   };
   if (!timed) {
     // The next batch is enqueued before this batch's state is read back (its
@@ -337,6 +343,7 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
         pin = pins[cur];
         break;
       }
+      if (pins[cur]->n >= N) iters = kTailIters;
     }
     for (auto& e : read)
       if (e) (void)hipEventDestroy(e);
