@@ -157,12 +157,20 @@ int launch_update(const float* X, int64_t M, int64_t L, const int32_t* idx,
 
 // ----------------------------------------------------------------- misc --
 struct CentroidWs {
-  double* part;  // [nwg][L]
+  double* part;    // [nwg][L]
+  uint32_t* amax;  // [nwg] block maxima of |x| (set-up of a training run)
   int64_t nwg;
 };
 void plan_centroid(Carver& c, int64_t M, int64_t L, CentroidWs* ws);
 int launch_centroid(const float* X, int64_t M, int64_t L, float* c0,
                     const CentroidWs& ws, hipStream_t s);
+// Set-up of a training run from the centroid (two launches): c0, its split
+// into C2 (two codevectors), the fixed-point shift of X, the initial device
+// state and the cleared fallback counter.  The same values as
+// launch_centroid, launch_split, launch_afp_shift and the state copy.
+int launch_setup(const float* X, int64_t M, int64_t L, float* c0, float* C2, int mode,
+                 double eps, double delta, const CentroidWs& ws, int* shift,
+                 const DevState& init, DevState* st, unsigned long long* nfb, hipStream_t s);
 
 int launch_split(const float* C, int64_t n, int64_t L, int mode, double eps,
                  double delta, float* C2, hipStream_t s, const DevState* st = nullptr,

@@ -3,6 +3,7 @@
 // of per-workgroup partial sums and the gradient with respect to X.
 #include <algorithm>
 
+#include "afp_common.h"
 #include "control.h"
 #include "lbg_internal.h"
 #include "misc_common.h"
@@ -118,6 +119,80 @@ int launch_split(const float* C, int64_t n, int64_t L, int mode, double eps,
   return LBG_OK;
 }
 
+// Set-up of a training run in two launches.  setup_pass_kernel: the column
+// sums of colsum_kernel (same blocks, same order) and, from the same loads,
+// each block's largest finite |x| (as absmax_kernel forms it; a maximum does
+// not depend on the order).
+__global__ __launch_bounds__(kThreads) void setup_pass_kernel(const float* __restrict__ X,
+                                                              int64_t M, int L,
+                                                              int64_t rows_per_block,
+                                                              double* __restrict__ part,
+                                                              uint32_t* __restrict__ amax) {
+  __shared__ double s[kThreads];
+  __shared__ uint32_t sm[kThreads];
+  const int R = kThreads / L;
+  const int t = threadIdx.x;
+  const int q = t / L, d = t % L;
+  const int64_t blk = blockIdx.x;
+  const int64_t r0 = blk * rows_per_block;
+  const int64_t r1 = min(M, r0 + rows_per_block);
+  double acc = 0.0;
+  uint32_t m = 0;
+  if (q < R)
+    for (int64_t r = r0 + q; r < r1; r += R) {
+      const float v = X[r * L + d];
+      acc += (double)v;
+      const uint32_t b = __float_as_uint(v) & 0x7fffffffu;
+      m = (b > m && b < 0x7f800000u) ? b : m;  // ignore Inf / NaN
+    }
+  s[t] = acc;
+  sm[t] = m;
+  __syncthreads();
+  if (t < L) {
+    double v = 0.0;
+    for (int qi = 0; qi < R; ++qi) v += s[qi * L + t];
+    part[blk * L + t] = v;
+  }
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if (t < off) sm[t] = max(sm[t], sm[t + off]);
+    __syncthreads();
+  }
+  if (t == 0) amax[blk] = sm[0];
+}
+
+// setup_final_kernel, one block per dimension d: c0[d] as colsum_final_kernel
+// forms it, its split into C2 (children 0 "+" and 1 "-", as split_kernel),
+// and in block 0 the fixed-point shift (as shift_kernel), the initial run
+// state and the cleared fallback counter.
+__global__ __launch_bounds__(kThreads) void setup_final_kernel(
+    const double* __restrict__ part, int64_t nparts, int L, int64_t M, float* __restrict__ c0,
+    float* __restrict__ C2, int mode, double eps, double delta,
+    const uint32_t* __restrict__ amax, int namax, int* __restrict__ shift, DevState init,
+    DevState* __restrict__ st, unsigned long long* __restrict__ nfb) {
+  const int d = blockIdx.x;
+  __shared__ double s[kThreads];
+  double acc = 0.0;
+  for (int64_t p = threadIdx.x; p < nparts; p += kThreads) acc += part[p * L + d];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float c = (float)(s[0] / (double)M);
+    c0[d] = c;
+    misc::split_pair(c, mode, eps, delta, &C2[d], &C2[L + d]);
+  }
+  if (d == 0) {
+    afp::shift_body(amax, namax, M, shift);
+    if (threadIdx.x == 0) {
+      *st = init;
+      *nfb = 0ull;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void decide_kernel(const double* __restrict__ parts,
                                                           int64_t nparts, DevState* st,
                                                           double* __restrict__ Dtrace,
@@ -138,6 +213,21 @@ int launch_decide(const double* dpart, int64_t nparts, DevState* st, double* Dtr
 void plan_centroid(Carver& c, int64_t M, int64_t L, CentroidWs* ws) {
   ws->nwg = std::min<int64_t>(1024, std::max<int64_t>(1, (M + 255) / 256));
   ws->part = c.take<double>((size_t)(ws->nwg * L));
+  ws->amax = c.take<uint32_t>((size_t)ws->nwg);
+}
+
+int launch_setup(const float* X, int64_t M, int64_t L, float* c0, float* C2, int mode,
+                 double eps, double delta, const CentroidWs& ws, int* shift,
+                 const DevState& init, DevState* st, unsigned long long* nfb, hipStream_t s) {
+  const int64_t rpb = (M + ws.nwg - 1) / ws.nwg;
+  hipLaunchKernelGGL(setup_pass_kernel, dim3((unsigned)ws.nwg), dim3(kThreads), 0, s, X, M,
+                     (int)L, rpb, ws.part, ws.amax);
+  LBG_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(setup_final_kernel, dim3((unsigned)L), dim3(kThreads), 0, s, ws.part,
+                     ws.nwg, (int)L, M, c0, C2, mode, eps, delta, ws.amax, (int)ws.nwg, shift,
+                     init, st, nfb);
+  LBG_TRY_HIP(hipGetLastError());
+  return LBG_OK;
 }
 
 int launch_centroid(const float* X, int64_t M, int64_t L, float* c0,

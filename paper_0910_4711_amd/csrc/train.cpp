@@ -202,24 +202,23 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
   for (int i = 0; i < hs.n_forced; ++i) hs.forced[i] = p->forced_iters[i];
 
   CbPair cbp{{w.Cb[0], w.Cb[1]}};
-  if (p->C_init) {
+  // the common start (centroid, split, shift, state) in two launches
+  const bool fused_setup = !p->C_init && N >= 2;
+  if (fused_setup) {
+    hs.cb = 1;
+    hs.n = 2;
+  } else if (p->C_init) {
     LBG_TRY_HIP(hipMemcpyAsync(w.Cb[0], p->C_init, (size_t)(p->N_init * L) * sizeof(float),
                                hipMemcpyDeviceToDevice, s));
     hs.cb = 0;
     hs.n = (int32_t)p->N_init;
   } else {
+    // N = 1: the centroid is the one-level codebook: one allocation, no update
     LBG_TRY(launch_centroid(X, M, L, w.Cb[0], w.ce, s));
-    if (N == 1) {
-      // the centroid is the one-level codebook: one allocation, no update
-      hs.cb = 0;
-      hs.n = 1;
-      hs.n_forced = 1;
-      hs.forced[0] = 0;
-    } else {
-      LBG_TRY(launch_split(w.Cb[0], 1, L, p->split_mode, p->eps_split, p->delta, w.Cb[1], s));
-      hs.cb = 1;
-      hs.n = 2;
-    }
+    hs.cb = 0;
+    hs.n = 1;
+    hs.n_forced = 1;
+    hs.forced[0] = 0;
   }
   // pinned host block: action trace, then the state
   int32_t* acts =
@@ -232,9 +231,14 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
                        reinterpret_cast<DevState*>(acts + kTraceCap) + 1};
   DevState* pin = pins[0];
   memcpy(pin, &hs, sizeof(hs));
-  LBG_TRY_HIP(hipMemcpyAsync(w.st, pin, sizeof(DevState), hipMemcpyHostToDevice, s));
-  LBG_TRY_HIP(hipMemsetAsync(w.as.nfb, 0, sizeof(unsigned long long), s));
-  LBG_TRY(launch_afp_shift(X, M, L, w.up.afp, s));
+  if (fused_setup) {
+    LBG_TRY(launch_setup(X, M, L, w.Cb[0], w.Cb[1], p->split_mode, p->eps_split, p->delta, w.ce,
+                         w.up.afp.shift, hs, w.st, w.as.nfb, s));
+  } else {
+    LBG_TRY_HIP(hipMemcpyAsync(w.st, pin, sizeof(DevState), hipMemcpyHostToDevice, s));
+    LBG_TRY_HIP(hipMemsetAsync(w.as.nfb, 0, sizeof(unsigned long long), s));
+    LBG_TRY(launch_afp_shift(X, M, L, w.up.afp, s));
+  }
 
   const bool timed = p->timing != 0 && st != nullptr;
   Batch b{X, M, L, N, p->precision, p->split_mode, p->eps_split, p->delta, idx_out, &w,
