@@ -98,12 +98,16 @@ int lbg_centroid(const float* X, int64_t M, int64_t L, float* c0, void* ws,
  *   idx[m] = min { k : d(x_m, c_k) = min_j d(x_m, c_j) }.
  * mind[m] (nullable) receives d(x_m, c_idx[m]) rounded to FP32.
  *
- * precision == LBG_FP32: distances are screened on FP32 matrix cores in the
- * expanded form |x|^2 - 2 x.c + |c|^2; the best candidate is rescored in
- * FP64 in the direct form sum_l (x_l - c_l)^2 and accepted only when a
- * rigorous error bound proves no other codevector can be as close;
- * otherwise the row is searched again exhaustively in FP64.  The result
- * equals the FP64 direct-form argmin exactly.
+ * precision == LBG_FP32: distances are screened on matrix cores in the
+ * expanded form |x|^2 - 2 x.c + |c|^2 with FP32 accuracy (from exact
+ * three-part BF16 splits of x and -2c for 8 < L <= 64, in FP32 otherwise);
+ * the best candidate is rescored in FP64 in the direct form
+ * sum_l (x_l - c_l)^2 and accepted only when a rigorous error bound proves
+ * no other codevector can be as close; failing that, the two best are
+ * rescored and the closer one accepted under the same bound against all
+ * others; otherwise the row is searched again exhaustively in FP64.
+ * Codebooks of at most 8 codevectors (L <= 32) are searched directly in
+ * FP64.  The result equals the FP64 direct-form argmin exactly.
  * precision == LBG_BF16_RESCORE: the screen runs in BF16 with FP32
  * accumulation; the two best candidates are rescored in FP64 and the
  * closer one (lowest index on ties) is taken.  Approximate: a row whose

@@ -1,33 +1,36 @@
-// Cell Allocation on gfx950 matrix cores: the kernel shared by the FP32
-// screen (exact result) and the BF16 screen (precision form).
+// Cell Allocation on gfx950 matrix cores: the kernel shared by the exact
+// screens (FP32-accurate: split BF16 parts, or FP32) and the BF16 screen
+// (precision form).
 //
 //   * The codebook is staged into LDS in the screen's row layout: -2c (exact
-//     scaling), zero-padded to LP dimensions, with the squared norm in the
-//     row's padding; rows are padded to a multiple of 32 with a huge norm so
-//     that padding never wins.  A codebook that fits is staged once per
-//     workgroup (resident); otherwise a prepared copy is staged chunk by chunk
-//     for every row tile.
-//   * One workgroup = 4 waves; a wave owns a tile of 32 training vectors, a
-//     workgroup a row tile of 128.  Workgroups loop over row tiles; the grid
-//     is sized so that 2 to 4 waves share each SIMD (by register use), which
-//     lets one wave's candidate work overlap another's matrix-core work.
-//   * Screen: v_mfma_f32_32x32x2_f32 (FP32) or v_mfma_f32_32x32x16_bf16 (BF16)
-//     computes |c|^2 + |x|^2 - 2 x.c for a 32 (codevectors) x 32 (vectors)
-//     tile; a first K-step with A = [|c|^2, 1], B = [1, |x|^2] adds both norms,
-//     so the accumulator starts at zero.  Codevectors are the A operand, so
-//     each lane holds 16 distances of ONE vector; the two lanes (j, 0) and
-//     (j, 1) hold the 32 codevectors of a tile for vector j between them.
+//     scaling; three BF16 parts for the split screen), zero-padded to LP
+//     dimensions, with the squared norm in the row's padding; rows are
+//     padded to a multiple of 32 with a huge norm so that padding never
+//     wins.  A codebook that fits is staged once per workgroup (resident);
+//     otherwise a prepared copy is staged chunk by chunk for every row tile.
+//   * One workgroup = 4 waves (8 for a codebook resident only in a whole
+//     CU's LDS); a wave owns a tile of 32 training vectors.  Workgroups loop
+//     over row tiles; the grid is sized so that 2 to 4 waves share each SIMD
+//     (by register use).
+//   * Screen: MFMAs compute |c|^2 + |x|^2 - 2 x.c for a 32 (codevectors) x
+//     32 (vectors) tile, the norms entering through one K-step.  Codevectors
+//     are the A operand, so each lane holds 16 distances of ONE vector; the
+//     two lanes (j, 0) and (j, 1) hold the 32 codevectors of a tile for
+//     vector j between them.
 //   * Each lane keeps the two smallest keys of every accumulator slot; a key
 //     is the screened distance with its low mantissa bits replaced by the tile
 //     number (3 VALU ops per distance: and-or, med3 as min, med3).  The tile
 //     loop is software-pipelined: the products of tile t+1 are issued before
 //     the key updates of tile t.
-//   * FP32: the best candidate is rescored in FP64, direct form, dimension
-//     order (lane (j, 0) sums the first half of the dimensions, lane (j, 1)
-//     continues); a rigorous bound on the screen's rounding decides whether it
-//     is provably the unique nearest codevector, otherwise the wave searches
-//     the row again exhaustively in FP64.  BF16: the two best candidates are
-//     rescored in FP64 and the closer taken (lowest index on ties).
+//   * Exact screens: the best candidate is rescored in FP64, direct form,
+//     dimension order (lane (j, 0) sums the first half of the dimensions,
+//     lane (j, 1) continues); a rigorous bound on the screen's rounding
+//     decides whether it is provably the unique nearest codevector; failing
+//     that, the two best are rescored and the closer one is tested the same
+//     way against a bound on all others; otherwise the wave searches the row
+//     again exhaustively in FP64.  Codebooks of at most kDirectN codevectors
+//     are searched directly in FP64 instead.  BF16: the two best candidates
+//     are rescored in FP64 and the closer taken (lowest index on ties).
 #pragma once
 
 #include <float.h>
