@@ -126,6 +126,41 @@ def test_assign_ties_lowest_index(P):
     assert host(idx)[0] == 3 and host(idx)[1] == 3 and host(idx)[3] == 12
 
 
+@pytest.mark.parametrize("L,eps", [(16, 1e-3), (16, 1e-5), (16, 1e-7), (32, 1e-6), (64, 1e-6)])
+def test_assign_split_siblings_exact(P, L, eps):
+    # codebooks of split pairs c(1 + eps), c(1 - eps) (children 2i, 2i + 1),
+    # the near ties the second acceptance test and the exhaustive search
+    # settle; vectors drawn around the parents and exactly at some of them
+    rng = np.random.default_rng(int(1e6 * eps) + L)
+    par = rng.uniform(0, 255, size=(40, L))
+    C = np.empty((80, L), np.float32)
+    C[0::2] = (par * (1 + eps)).astype(np.float32)
+    C[1::2] = (par * (1 - eps)).astype(np.float32)
+    X = (par[rng.integers(0, 40, size=6000)] + rng.normal(0, 4.0, size=(6000, L))).astype(np.float32)
+    X[:40] = par.astype(np.float32)
+    idx_o, d1, _ = oracle.assign(X, C.astype(np.float64))
+    idx, mind = P.assign(dev(X), dev(C), P.FP32)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(idx), idx_o)
+    np.testing.assert_array_equal(host(mind), d1.astype(np.float32))
+
+
+@pytest.mark.parametrize("L,n", [(8, 100), (16, 300), (32, 96), (64, 64)])
+def test_assign_large_offset_exact(P, L, n):
+    # a common offset of 1e4 with a spread of a few units: |x|^2 dwarfs the
+    # distances, so the screen's error bound is large relative to the gaps
+    # and many rows need the second test or the search
+    rng = np.random.default_rng(L + n)
+    base = 1e4 + rng.normal(0, 1.0, size=L)
+    C = (base + rng.normal(0, 3.0, size=(n, L))).astype(np.float32)
+    X = (base + rng.normal(0, 3.0, size=(5000, L))).astype(np.float32)
+    idx_o, d1, _ = oracle.assign(X, C.astype(np.float64))
+    idx, mind = P.assign(dev(X), dev(C), P.FP32)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(idx), idx_o)
+    np.testing.assert_array_equal(host(mind), d1.astype(np.float32))
+
+
 def test_assign_all_equal_and_zero(P):
     X = np.full((513, 16), 255.0, np.float32)
     X[100:200] = 0.0
