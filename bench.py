@@ -375,6 +375,80 @@ def form_differentiation(args):
     print(json.dumps(out), flush=True)
 
 
+def _image_worker(args):
+    import synth
+    seed, W, H = args
+    return synth.image(seed, W, H)
+
+
+def form_codec(args):
+    """Codec form: the encoder/decoder half of VQ with the benchmark
+    workload's codebook (LBG on the 16 training pictures, 4 x 4 blocks, N =
+    256), applied to 64 other synthetic 512 x 512 pictures (seeds
+    1000..1063, M = 1,048,576 blocks): pictures -> block vectors
+    (lbg_image_blocks), encoder (nearest codevector, lbg_encode), decoder
+    straight into pictures (lbg_decode_image); PSNR from the distortion and
+    the rate log2(N)/L."""
+    import concurrent.futures as cf
+    import torch
+    import paper_0910_4711_amd as P
+    cfg, Xtrain = workload()
+    N, b, W, H = cfg["N"], cfg["b"], cfg["W"], cfg["H"]
+    L = b * b
+    seeds = list(range(1000, 1064))
+    with cf.ProcessPoolExecutor(max_workers=16) as ex:
+        pics = np.stack(list(ex.map(_image_worker, [(s_, W, H) for s_ in seeds])))
+    nimg = len(seeds)
+    M = nimg * (H // b) * (W // b)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        C, _, _, _ = P.train(torch.from_numpy(Xtrain).to(dev), N)
+        img = torch.from_numpy(pics.astype(np.float32)).to(dev)
+        X = P.image_blocks(img, b)
+        idx = P.encode(X, C)
+        rec = P.decode_image(idx, C, nimg, H, W, b)
+        D = P.distortion(X, C, idx)
+    stream.synchronize()
+    psnr = P.psnr(D, L)
+    ms_blocks = _events_ms(lambda: P.image_blocks(img, b), stream, args.steps)
+    ms_enc = _events_ms(lambda: P.encode(X, C), stream, args.steps)
+    ms_dec = _events_ms(lambda: P.decode_image(idx, C, nimg, H, W, b), stream, args.steps)
+
+    def pipeline():
+        x = P.image_blocks(img, b)
+        return P.decode_image(P.encode(x, C), C, nimg, H, W, b)
+
+    ms_all = _events_ms(pipeline, stream, args.steps)
+    pixels = nimg * H * W
+    dec_bytes = M * 4 + M * L * 4 + N * L * 4  # indices, pictures written, codebook once
+    blk_bytes = 2 * M * L * 4                  # pictures read, vectors written
+    dec_gbs = dec_bytes / (ms_dec * 1e-3) / 1e9
+    blk_gbs = blk_bytes / (ms_blocks * 1e-3) / 1e9
+    enc_tf = 2.0 * L * M * N / (ms_enc * 1e-3) / 1e12
+    out = {"metric": "codec form: picture pixels coded and decoded/s",
+           "value": pixels / (ms_all * 1e-3), "unit": "pixels/s", "n_gpus": 1,
+           "steps": args.steps, "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"code{nimg}x{H}x{W}_b{b}_M{M}_L{L}_N{N}",
+                      "codebook": cfg["name"], "pictures": nimg, "M": M, "L": L, "N": N},
+           "psnr_db": psnr, "rate_bits_per_sample": P.rate(N, L), "D": float(D.item()),
+           "ms": {"image_blocks": ms_blocks, "encode": ms_enc, "decode_image": ms_dec,
+                  "pipeline": ms_all},
+           "decode_roofline": {"bound": "hbm", "achieved": dec_gbs, "peak": PEAK_HBM_GBS,
+                               "unit": "GB/s", "frac": dec_gbs / PEAK_HBM_GBS,
+                               "algorithmic_bytes": dec_bytes,
+                               "kernel": "block_rows_kernel<1, 128, 0> (decoder)"},
+           "image_blocks_roofline": {"bound": "hbm", "achieved": blk_gbs,
+                                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                     "frac": blk_gbs / PEAK_HBM_GBS,
+                                     "algorithmic_bytes": blk_bytes,
+                                     "kernel": "block_rows_kernel<1, 128, 1> (pictures to blocks)"},
+           "encode": {"distances_per_s": M * N / (ms_enc * 1e-3), "tflops": enc_tf,
+                      "frac_fp32_mfma": enc_tf / PEAK_FP32_MFMA_TFLOPS}}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(X, N, images):
     """The FP64 oracle, as it stands, on the first ``images`` pictures' rows
     with all host cores; distances/s of the full LBG run."""
@@ -405,7 +479,7 @@ def main():
                     help="timed steps that record HIP events around every kernel")
     ap.add_argument("--copy-calibration", type=int, metavar="MIB", default=0,
                     help="only run a plain device copy of MIB MiB (counter calibration)")
-    ap.add_argument("--form", choices=["batched", "precision", "differentiation"],
+    ap.add_argument("--form", choices=["batched", "precision", "differentiation", "codec"],
                     default=None, help="benchmark one of the forms instead of the main workload")
     ap.add_argument("--images", type=int, default=0,
                     help="images of --form precision (default: all 256)")
@@ -419,7 +493,7 @@ def main():
         if args.gpus != 1:
             sys.exit("bench.py: the forms run on one GPU")
         {"batched": form_batched, "precision": form_precision,
-         "differentiation": form_differentiation}[args.form](args)
+         "differentiation": form_differentiation, "codec": form_codec}[args.form](args)
         return
     if args.gpus != 1:
         print(f"bench.py: this benchmark runs on exactly one GPU; --gpus {args.gpus} "

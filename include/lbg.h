@@ -157,6 +157,60 @@ int lbg_distortion_backward(const float* X, int64_t M, int64_t L,
                             double g, float* gX, float* gC, void* ws,
                             size_t ws_bytes, void* stream);
 
+/*
+ * Encoder and decoder of the trained quantizer (Introduction: a vector is
+ * coded by the index of its nearest codevector, which the decoder maps back;
+ * log2(N) bits per vector, log2(N)/L bits per sample).
+ *
+ * lbg_encode: idx[m] = index of the codevector of C (N x L) nearest to row m
+ * of X (M x L), lowest index on ties: lbg_assign with LBG_FP32 and no
+ * distances.  ws: lbg_workspace_size(LBG_OP_ASSIGN, M, L, N, LBG_FP32) bytes.
+ */
+int lbg_encode(const float* X, int64_t M, int64_t L, const float* C, int64_t N,
+               int32_t* idx, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * lbg_decode: Y[m] = C[idx[m]] for the M indices idx, Y M x L (device,
+ * caller-owned, may not overlap C).  An index outside [0, N) gives a row of
+ * quiet NaNs, so that a corrupt code stays visible.  No workspace.
+ */
+int lbg_decode(const int32_t* idx, int64_t M, const float* C, int64_t N,
+               int64_t L, float* Y, void* stream);
+
+/*
+ * Pictures cut into b x b blocks (the training vectors of an image coder,
+ * L = b * b): nimg pictures of H rows by W columns, row-major, picture after
+ * picture (img: nimg x H x W floats); H and W multiples of b.  Vector v =
+ * (p * (H / b) + by) * (W / b) + bx holds block (by, bx) of picture p, its
+ * pixels row-major: dimension dy * b + dx is pixel (by b + dy, bx b + dx).
+ *
+ * lbg_image_blocks: img -> X (nimg (H/b)(W/b) x b*b).
+ * lbg_decode_image: the decoder written straight into pictures: pixel
+ *   (p, y, x) of img is dimension (y mod b) b + (x mod b) of codevector
+ *   idx[v] of C (N x b*b), v the block that holds the pixel; an index outside
+ *   [0, N) gives NaN pixels.  Equals lbg_decode followed by the inverse of
+ *   lbg_image_blocks, in one pass.
+ * Limits: 1 <= b, b * b <= LBG_MAX_L; H, W <= 2^31 - 1; nimg (H/b)(W/b) <=
+ * LBG_MAX_M.  Output and input must not overlap.  No workspace.
+ */
+int lbg_image_blocks(const float* img, int64_t nimg, int64_t H, int64_t W,
+                     int64_t b, float* X, void* stream);
+int lbg_decode_image(const int32_t* idx, const float* C, int64_t N,
+                     int64_t nimg, int64_t H, int64_t W, int64_t b,
+                     float* img, void* stream);
+
+/*
+ * Host-only figures of merit (no GPU work; *out is a HOST double).
+ * lbg_rate: log2(N) / L bits per sample (Introduction).  N >= 1, L >= 1.
+ * lbg_psnr: peak signal-to-noise ratio of a reconstruction whose average
+ *   distortion (lbg_distortion: mean over vectors of the squared error) is
+ *   D: the mean squared error per sample is D / L, and
+ *   PSNR = 10 log10(peak^2 / (D / L)) dB; +infinity when D == 0.  D >= 0,
+ *   L >= 1, peak > 0 (255 for 8-bit pictures).
+ */
+int lbg_rate(int64_t N, int64_t L, double* out);
+int lbg_psnr(double D, int64_t L, double peak, double* out);
+
 /* Parameters of lbg_train.  lbg_params_default() fills the defaults. */
 typedef struct lbg_params {
   double thr;        /* relative distortion-change threshold (1e-3), >= 0 */

@@ -25,6 +25,7 @@ __all__ = [
     "FP32", "BF16_RESCORE", "SPLIT_MULT", "SPLIT_ADD", "LBGError",
     "library_path", "load", "centroid", "split", "assign", "update",
     "distortion", "distortion_backward", "train", "Distortion",
+    "encode", "decode", "image_blocks", "decode_image", "rate", "psnr",
 ]
 
 FP32 = 0
@@ -150,6 +151,12 @@ def load():
             "lbg_update": [vp, i64, i64, vp, vp, i64, vp, vp, vp, sz, vp],
             "lbg_distortion": [vp, i64, i64, vp, i64, vp, vp, vp, sz, vp],
             "lbg_distortion_backward": [vp, i64, i64, vp, i64, vp, dbl, vp, vp, vp, sz, vp],
+            "lbg_encode": [vp, i64, i64, vp, i64, vp, vp, sz, vp],
+            "lbg_decode": [vp, i64, vp, i64, i64, vp, vp],
+            "lbg_image_blocks": [vp, i64, i64, i64, i64, vp, vp],
+            "lbg_decode_image": [vp, vp, i64, i64, i64, i64, i64, vp, vp],
+            "lbg_rate": [i64, i64, ct.POINTER(ct.c_double)],
+            "lbg_psnr": [dbl, i64, dbl, ct.POINTER(ct.c_double)],
             "lbg_train": [vp, i64, i64, i64, ct.POINTER(Params), vp, vp,
                           ct.POINTER(ct.c_double), ct.POINTER(Stats), vp, sz, vp],
             "lbg_train_batched": [ct.POINTER(Instance), i32, ct.POINTER(Params),
@@ -295,6 +302,91 @@ def distortion(X, C, idx):
     _check(load().lbg_distortion(_ptr(X), M, L, _ptr(C), N, _ptr(idx), _ptr(D), _ptr(ws),
                                  nb, _stream(X.device)), "lbg_distortion")
     return D
+
+
+def encode(X, C):
+    """Encoder: index of the nearest codevector of every row of X (int32 [M])."""
+    X, C = _f32_2d("X", X), _f32_2d("C", C)
+    M, L = X.shape
+    N = C.shape[0]
+    if C.shape[1] != L:
+        raise ValueError("X and C differ in dimension")
+    if C.device != X.device:
+        raise ValueError("X and C are on different devices")
+    idx = torch.empty(M, dtype=torch.int32, device=X.device)
+    ws, nb = _ws(OP_ASSIGN, M, L, N, FP32, X.device)
+    _check(load().lbg_encode(_ptr(X), M, L, _ptr(C), N, _ptr(idx), _ptr(ws), nb,
+                             _stream(X.device)), "lbg_encode")
+    return idx
+
+
+def decode(idx, C):
+    """Decoder: Y [M x L] with Y[m] = C[idx[m]] (NaN rows for indices outside
+    [0, N))."""
+    C = _f32_2d("C", C)
+    N, L = C.shape
+    if not isinstance(idx, torch.Tensor) or idx.dim() != 1:
+        raise TypeError("idx must be a 1-D int32 tensor")
+    M = idx.numel()
+    idx = _i32_1d("idx", idx, M)
+    Y = torch.empty((M, L), dtype=torch.float32, device=C.device)
+    _check(load().lbg_decode(_ptr(idx), M, _ptr(C), N, L, _ptr(Y), _stream(C.device)),
+           "lbg_decode")
+    return Y
+
+
+def _pictures(name, t):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.dim() != 3:
+        raise TypeError(f"{name} must be a 3-D float32 tensor (pictures x rows x columns)")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous GPU tensor")
+    return t
+
+
+def image_blocks(img, b):
+    """Training vectors of pictures img (nimg x H x W): b x b blocks in raster
+    order, pixels row-major inside a block ([nimg (H/b)(W/b)] x b*b)."""
+    img = _pictures("img", img)
+    nimg, H, W = img.shape
+    if b < 1 or H % b or W % b:
+        raise ValueError("picture size must be a multiple of b")
+    X = torch.empty((nimg * (H // b) * (W // b), b * b), dtype=torch.float32, device=img.device)
+    _check(load().lbg_image_blocks(_ptr(img), nimg, H, W, b, _ptr(X), _stream(img.device)),
+           "lbg_image_blocks")
+    return X
+
+
+def decode_image(idx, C, nimg, H, W, b):
+    """Decoder into pictures: block v of the output (the layout of
+    image_blocks) is codevector idx[v] as b x b pixels."""
+    C = _f32_2d("C", C)
+    N, L = C.shape
+    if L != b * b:
+        raise ValueError("codevectors must have b * b dimensions")
+    if b < 1 or H % b or W % b:
+        raise ValueError("picture size must be a multiple of b")
+    idx = _i32_1d("idx", idx, nimg * (H // b) * (W // b))
+    img = torch.empty((nimg, H, W), dtype=torch.float32, device=C.device)
+    _check(load().lbg_decode_image(_ptr(idx), _ptr(C), N, nimg, H, W, b, _ptr(img),
+                                   _stream(C.device)), "lbg_decode_image")
+    return img
+
+
+def rate(N, L):
+    """Bits per sample, log2(N) / L."""
+    out = ct.c_double()
+    _check(load().lbg_rate(int(N), int(L), ct.byref(out)), "lbg_rate")
+    return out.value
+
+
+def psnr(D, L, peak=255.0):
+    """PSNR in dB of a reconstruction with average distortion D (a float or
+    a 0-d tensor, as from distortion()) over L-dimensional vectors."""
+    if isinstance(D, torch.Tensor):
+        D = float(D.item())
+    out = ct.c_double()
+    _check(load().lbg_psnr(float(D), int(L), float(peak), ct.byref(out)), "lbg_psnr")
+    return out.value
 
 
 def distortion_backward(X, C, idx, g=1.0, need_x=True, need_c=True):

@@ -586,4 +586,110 @@ int lbg_train(const float* X, int64_t M, int64_t L, int64_t N, const lbg_params*
   return status;
 }
 
+int lbg_encode(const float* X, int64_t M, int64_t L, const float* C, int64_t N, int32_t* idx,
+               void* ws, size_t ws_bytes, void* stream) {
+  return lbg_assign(X, M, L, C, N, idx, nullptr, LBG_FP32, ws, ws_bytes, stream);
+}
+
+int lbg_decode(const int32_t* idx, int64_t M, const float* C, int64_t N, int64_t L, float* Y,
+               void* stream) {
+  clear_error();
+  LBG_TRY(check_dims(M, L, N));
+  LBG_TRY(need(idx, "idx"));
+  LBG_TRY(need(C, "C"));
+  LBG_TRY(need(Y, "Y"));
+  const char* a = reinterpret_cast<const char*>(C);
+  const char* b = reinterpret_cast<const char*>(Y);
+  if (b < a + N * L * 4 && a < b + M * L * 4) {
+    set_error("Y overlaps C");
+    return LBG_EINVAL;
+  }
+  return launch_decode(idx, M, C, N, L, Y, (hipStream_t)stream);
+}
+
+namespace {
+
+int check_pictures(int64_t nimg, int64_t H, int64_t W, int64_t b) {
+  if (b < 1 || b * b > LBG_MAX_L) {
+    set_error("block side b = %lld outside [1, %d]", (long long)b, (int)sqrt((double)LBG_MAX_L));
+    return LBG_EINVAL;
+  }
+  if (nimg < 1 || H < 1 || W < 1 || H > INT32_MAX || W > INT32_MAX || nimg > INT32_MAX) {
+    set_error("bad picture size %lld x %lld x %lld", (long long)nimg, (long long)H,
+              (long long)W);
+    return LBG_EINVAL;
+  }
+  if (H % b || W % b) {
+    set_error("picture size %lld x %lld is not a multiple of b = %lld", (long long)H,
+              (long long)W, (long long)b);
+    return LBG_EINVAL;
+  }
+  if ((H / b) * (W / b) > LBG_MAX_M / nimg) {
+    set_error("more than %lld blocks", (long long)LBG_MAX_M);
+    return LBG_EINVAL;
+  }
+  return LBG_OK;
+}
+
+bool overlap(const void* p, int64_t pbytes, const void* q, int64_t qbytes) {
+  const char* a = reinterpret_cast<const char*>(p);
+  const char* b = reinterpret_cast<const char*>(q);
+  return b < a + pbytes && a < b + qbytes;
+}
+
+}  // namespace
+
+int lbg_image_blocks(const float* img, int64_t nimg, int64_t H, int64_t W, int64_t b, float* X,
+                     void* stream) {
+  clear_error();
+  LBG_TRY(check_pictures(nimg, H, W, b));
+  LBG_TRY(need(img, "img"));
+  LBG_TRY(need(X, "X"));
+  const int64_t bytes = nimg * H * W * 4;
+  if (overlap(img, bytes, X, bytes)) {
+    set_error("X overlaps img");
+    return LBG_EINVAL;
+  }
+  return launch_image(1, nullptr, nullptr, 0, nimg, H, W, b, img, X, (hipStream_t)stream);
+}
+
+int lbg_decode_image(const int32_t* idx, const float* C, int64_t N, int64_t nimg, int64_t H,
+                     int64_t W, int64_t b, float* img, void* stream) {
+  clear_error();
+  LBG_TRY(check_pictures(nimg, H, W, b));
+  if (N < 1 || N > LBG_MAX_N) {
+    set_error("N = %lld outside [1, %d]", (long long)N, LBG_MAX_N);
+    return LBG_EINVAL;
+  }
+  LBG_TRY(need(idx, "idx"));
+  LBG_TRY(need(C, "C"));
+  LBG_TRY(need(img, "img"));
+  if (overlap(C, N * b * b * 4, img, nimg * H * W * 4)) {
+    set_error("img overlaps C");
+    return LBG_EINVAL;
+  }
+  return launch_image(0, idx, C, N, nimg, H, W, b, nullptr, img, (hipStream_t)stream);
+}
+
+int lbg_rate(int64_t N, int64_t L, double* out) {
+  clear_error();
+  if (N < 1 || L < 1 || !out) {
+    set_error("lbg_rate needs N >= 1, L >= 1 and an output");
+    return LBG_EINVAL;
+  }
+  *out = log2((double)N) / (double)L;
+  return LBG_OK;
+}
+
+int lbg_psnr(double D, int64_t L, double peak, double* out) {
+  clear_error();
+  if (!(D >= 0.0) || !isfinite(D) || L < 1 || !(peak > 0.0) || !isfinite(peak) || !out) {
+    set_error("lbg_psnr needs a finite D >= 0, L >= 1, a finite peak > 0 and an output");
+    return LBG_EINVAL;
+  }
+  *out = D == 0.0 ? HUGE_VAL : 10.0 * log10(peak * peak * (double)L / D);
+  return LBG_OK;
+}
+
+
 }  // extern "C"

@@ -192,6 +192,14 @@ int launch_grad_x(const float* X, int64_t M, int64_t L, const float* C,
                   int64_t N, const int32_t* idx, double g2, float* gX,
                   hipStream_t s);
 
+// ---------------------------------------------------------------- codec --
+int launch_decode(const int32_t* idx, int64_t M, const float* C, int64_t N, int64_t L, float* Y,
+                  hipStream_t s);
+// dir 0: indices -> pictures; dir 1: pictures -> block vectors.
+int launch_image(int dir, const int32_t* idx, const float* C, int64_t N, int64_t nimg,
+                 int64_t H, int64_t W, int64_t b, const float* img_in, float* out,
+                 hipStream_t s);
+
 // ------------------------------------------------------------- training --
 constexpr int kTraceCap = 32768;  // allocations recorded on the device
 
