@@ -144,6 +144,21 @@ int lbg_distortion(const float* X, int64_t M, int64_t L, const float* C,
                    size_t ws_bytes, void* stream);
 
 /*
+ * Cell Allocation and its average distortion in one pass over X (the
+ * allocation followed by IntegrateDistortions of Algorithm 1): idx and mind
+ * as lbg_assign; D (one DEVICE double) = (1/M) sum_m d(x_m, c_idx[m]), the
+ * FP64 direct-form distance of each row's winner (summed over the dimensions
+ * in order), added in FP64 in an order fixed by M and L alone (partials of
+ * consecutive rows by a fixed pairwise tree, then the partials by a fixed
+ * strided sum and tree).  Same per-row values as lbg_distortion on the
+ * returned allocation.  ws: lbg_workspace_size(LBG_OP_ASSIGN, M, L, N,
+ * precision) bytes.
+ */
+int lbg_assign_distortion(const float* X, int64_t M, int64_t L, const float* C,
+                          int64_t N, int32_t* idx, float* mind, int precision,
+                          double* D, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Gradient of D(C, X) = (1/M) sum_m min_k d(x_m, c_k) at the allocation idx,
  * scaled by g (the upstream gradient of a scalar loss):
  *   gX[m] = g * 2/M * (x_m - c_idx[m])

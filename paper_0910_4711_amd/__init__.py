@@ -25,7 +25,7 @@ __all__ = [
     "FP32", "BF16_RESCORE", "SPLIT_MULT", "SPLIT_ADD", "LBGError",
     "library_path", "load", "centroid", "split", "assign", "update",
     "distortion", "distortion_backward", "train", "Distortion",
-    "encode", "decode", "image_blocks", "decode_image", "rate", "psnr",
+    "encode", "decode", "image_blocks", "decode_image", "rate", "psnr", "assign_distortion",
 ]
 
 FP32 = 0
@@ -152,6 +152,7 @@ def load():
             "lbg_distortion": [vp, i64, i64, vp, i64, vp, vp, vp, sz, vp],
             "lbg_distortion_backward": [vp, i64, i64, vp, i64, vp, dbl, vp, vp, vp, sz, vp],
             "lbg_encode": [vp, i64, i64, vp, i64, vp, vp, sz, vp],
+            "lbg_assign_distortion": [vp, i64, i64, vp, i64, vp, vp, i32, vp, vp, sz, vp],
             "lbg_decode": [vp, i64, vp, i64, i64, vp, vp],
             "lbg_image_blocks": [vp, i64, i64, i64, i64, vp, vp],
             "lbg_decode_image": [vp, vp, i64, i64, i64, i64, i64, vp, vp],
@@ -272,6 +273,26 @@ def assign(X, C, precision=FP32, with_mind=True):
                              _prec(precision), _ptr(ws), nb, _stream(X.device)),
            "lbg_assign")
     return idx, mind
+
+
+def assign_distortion(X, C, precision=FP32, with_mind=False):
+    """Cell Allocation and its average distortion in one pass:
+    (idx int32 [M], mind float32 [M] or None, D 0-d float64 GPU tensor)."""
+    X, C = _f32_2d("X", X), _f32_2d("C", C)
+    M, L = X.shape
+    N = C.shape[0]
+    if C.shape[1] != L:
+        raise ValueError("X and C differ in dimension")
+    if C.device != X.device:
+        raise ValueError("X and C are on different devices")
+    idx = torch.empty(M, dtype=torch.int32, device=X.device)
+    mind = torch.empty(M, dtype=torch.float32, device=X.device) if with_mind else None
+    D = torch.empty((), dtype=torch.float64, device=X.device)
+    ws, nb = _ws(OP_ASSIGN, M, L, N, _prec(precision), X.device)
+    _check(load().lbg_assign_distortion(_ptr(X), M, L, _ptr(C), N, _ptr(idx), _ptr(mind),
+                                        _prec(precision), _ptr(D), _ptr(ws), nb,
+                                        _stream(X.device)), "lbg_assign_distortion")
+    return idx, mind, D
 
 
 def update(X, idx, C_old, out=None):
@@ -527,8 +548,7 @@ class Distortion(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, X, C):
-        idx, _ = assign(X, C, FP32, with_mind=False)
-        D = distortion(X, C, idx)
+        idx, _, D = assign_distortion(X, C, FP32)
         ctx.save_for_backward(X, C, idx)
         return D
 

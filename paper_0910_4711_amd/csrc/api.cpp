@@ -327,6 +327,29 @@ int lbg_assign(const float* X, int64_t M, int64_t L, const float* C, int64_t N,
                        (hipStream_t)stream);
 }
 
+int lbg_assign_distortion(const float* X, int64_t M, int64_t L, const float* C, int64_t N,
+                          int32_t* idx, float* mind, int precision, double* D, void* ws,
+                          size_t ws_bytes, void* stream) {
+  clear_error();
+  LBG_TRY(check_dims(M, L, N));
+  LBG_TRY(check_precision(precision));
+  LBG_TRY(need(X, "X"));
+  LBG_TRY(need(C, "C"));
+  LBG_TRY(need(idx, "idx"));
+  LBG_TRY(need(D, "D"));
+  if (mind && !aligned4(mind)) {
+    set_error("mind is not 4-byte aligned");
+    return LBG_EINVAL;
+  }
+  Carver c{reinterpret_cast<char*>(ws), 0};
+  AssignWs w;
+  plan_assign(c, M, L, N, precision, &w);
+  LBG_TRY(check_ws(ws, ws_bytes, c.size()));
+  hipStream_t s = (hipStream_t)stream;
+  LBG_TRY(launch_assign(X, M, L, C, N, idx, mind, precision, w.dpart, nullptr, w.prep, s));
+  return launch_reduce_parts(w.dpart, assign_num_parts(M, L, N, precision), (double)M, D, s);
+}
+
 int lbg_update(const float* X, int64_t M, int64_t L, const int32_t* idx,
                const float* C_old, int64_t N, float* C_new, int32_t* counts,
                void* ws, size_t ws_bytes, void* stream) {

@@ -48,14 +48,25 @@ __global__ __launch_bounds__(kThreads) void colsum_final_kernel(
   misc::colsum_final_body(part, nparts, L, M, c0, blockIdx.x);
 }
 
-// Fixed-order sum of FP64 partials: thread t adds parts t, t+256, ...; the
-// 256 results are added by a fixed tree.
+// Fixed-order sum of FP64 partials: thread t adds parts t, t+256, ... in
+// that order (loads issued kRB at a time, additions in sequence); the 256
+// results are added by a fixed tree.
+constexpr int kRB = 32;
+
 __global__ __launch_bounds__(kThreads) void reduce_parts_kernel(
     const double* __restrict__ parts, int64_t nparts, double denom,
     double* __restrict__ out) {
   __shared__ double s[kThreads];
   double acc = 0.0;
-  for (int64_t p = threadIdx.x; p < nparts; p += kThreads) acc += parts[p];
+  int64_t p = threadIdx.x;
+  for (; p + (int64_t)(kRB - 1) * kThreads < nparts; p += (int64_t)kRB * kThreads) {
+    double v[kRB];
+#pragma unroll
+    for (int b = 0; b < kRB; ++b) v[b] = parts[p + (int64_t)b * kThreads];
+#pragma unroll
+    for (int b = 0; b < kRB; ++b) acc += v[b];
+  }
+  for (; p < nparts; p += kThreads) acc += parts[p];
   s[threadIdx.x] = acc;
   __syncthreads();
   for (int off = kThreads / 2; off > 0; off >>= 1) {
@@ -66,46 +77,122 @@ __global__ __launch_bounds__(kThreads) void reduce_parts_kernel(
 }
 
 // Distance of every row to its allocated codevector (FP64 direct form, in
-// dimension order), block partial sums in a fixed tree.
+// dimension order), block partial sums in a fixed tree.  The workgroup's 256
+// rows pass through LDS kDC dimensions at a time, copied with consecutive
+// threads on consecutive words so that the loads of X coalesce; thread t then
+// adds row t's dimensions in order.  V4: L % kDC == 0 and X, C 16-byte
+// aligned (16-byte loads).
+constexpr int kDC = 16;
+
+template <bool V4>
 __global__ __launch_bounds__(kThreads) void rowdist_kernel(
     const float* __restrict__ X, int64_t M, int L, const float* __restrict__ C,
     int n, const int32_t* __restrict__ idx, double* __restrict__ part) {
+  __shared__ float sx[kThreads * (kDC + 1)];
   __shared__ double s[kThreads];
-  const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int t = threadIdx.x;
+  const int64_t m0 = (int64_t)blockIdx.x * kThreads;
+  const int rows = (int)min<int64_t>(kThreads, M - m0);
+  const int k = t < rows ? idx[m0 + t] : -1;
+  const bool ok = t < rows && (unsigned)k < (unsigned)n;
+  const float* c = C + (int64_t)(ok ? k : 0) * L;
+  const float* xb = X + m0 * L;
   double d = 0.0;
-  if (m < M) {
-    const int k = idx[m];
-    if ((unsigned)k < (unsigned)n) {
-      const float* x = X + m * L;
-      const float* c = C + (int64_t)k * L;
-      for (int l = 0; l < L; ++l) {
-        const double t = (double)x[l] - (double)c[l];
-        d = d + t * t;
+  for (int c0 = 0; c0 < L; c0 += kDC) {
+    const int w = min(kDC, L - c0);
+    __syncthreads();  // the previous chunk has been read
+    if constexpr (V4) {
+      for (int e = t; e < rows * (kDC / 4); e += kThreads) {
+        const int r = e / (kDC / 4), q = e % (kDC / 4);
+        const float4 v = *reinterpret_cast<const float4*>(xb + (int64_t)r * L + c0 + 4 * q);
+        float* dst = sx + r * (kDC + 1) + 4 * q;
+        dst[0] = v.x;
+        dst[1] = v.y;
+        dst[2] = v.z;
+        dst[3] = v.w;
+      }
+    } else {
+      for (int e = t; e < rows * kDC; e += kThreads) {
+        const int r = e / kDC, j = e % kDC;
+        if (j < w) sx[r * (kDC + 1) + j] = xb[(int64_t)r * L + c0 + j];
+      }
+    }
+    __syncthreads();
+    if (ok) {
+      const float* xr = sx + t * (kDC + 1);
+      if constexpr (V4) {
+#pragma unroll
+        for (int q = 0; q < kDC / 4; ++q) {
+          const float4 cv = *reinterpret_cast<const float4*>(c + c0 + 4 * q);
+          const double u0 = (double)xr[4 * q] - (double)cv.x;
+          d = d + u0 * u0;
+          const double u1 = (double)xr[4 * q + 1] - (double)cv.y;
+          d = d + u1 * u1;
+          const double u2 = (double)xr[4 * q + 2] - (double)cv.z;
+          d = d + u2 * u2;
+          const double u3 = (double)xr[4 * q + 3] - (double)cv.w;
+          d = d + u3 * u3;
+        }
+      } else {
+        for (int j = 0; j < w; ++j) {
+          const double u = (double)xr[j] - (double)c[c0 + j];
+          d = d + u * u;
+        }
       }
     }
   }
-  s[threadIdx.x] = d;
+  s[t] = d;
   __syncthreads();
   for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    if (t < off) s[t] += s[t + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+  if (t == 0) part[blockIdx.x] = s[0];
 }
 
+// dD/dX: G lanes per row (a power of two, at least the row's words; VEC:
+// words are float4), kThreads / G rows per pass, kGU rows per thread in
+// flight.  Rows with an index outside [0, n) get zeros.
+constexpr int kGU = 4;
+
+template <int G, bool VEC>
 __global__ __launch_bounds__(kThreads) void grad_x_kernel(
     const float* __restrict__ X, int64_t M, int L, const float* __restrict__ C,
     int n, const int32_t* __restrict__ idx, double g2, float* __restrict__ gX) {
-  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (e >= M * L) return;
-  const int64_t m = e / L;
-  const int d = (int)(e % L);
-  const int k = idx[m];
-  if ((unsigned)k >= (unsigned)n) {
-    gX[e] = 0.0f;
-    return;
+  constexpr int RB = kThreads / G;
+  const int q = threadIdx.x % G, r = threadIdx.x / G;
+  const int W = VEC ? L / 4 : L;  // words per row
+  if (q >= W) return;             // (no barrier below)
+  const int64_t step = (int64_t)gridDim.x * RB * kGU;
+  for (int64_t base = (int64_t)blockIdx.x * RB * kGU; base < M; base += step) {
+    int k[kGU];
+#pragma unroll
+    for (int u = 0; u < kGU; ++u) {
+      const int64_t m = base + u * RB + r;
+      k[u] = m < M ? idx[m] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kGU; ++u) {
+      const int64_t m = base + u * RB + r;
+      if (m >= M) continue;
+      const bool ok = (unsigned)k[u] < (unsigned)n;
+      const int64_t crow = (int64_t)(ok ? k[u] : 0) * W;
+      if constexpr (VEC) {
+        const float4 x = reinterpret_cast<const float4*>(X)[m * W + q];
+        const float4 c = reinterpret_cast<const float4*>(C)[crow + q];
+        float4 o;
+        o.x = ok ? (float)(g2 * ((double)x.x - (double)c.x)) : 0.0f;
+        o.y = ok ? (float)(g2 * ((double)x.y - (double)c.y)) : 0.0f;
+        o.z = ok ? (float)(g2 * ((double)x.z - (double)c.z)) : 0.0f;
+        o.w = ok ? (float)(g2 * ((double)x.w - (double)c.w)) : 0.0f;
+        reinterpret_cast<float4*>(gX)[m * W + q] = o;
+      } else {
+        const float x = X[m * W + q];
+        const float c = C[crow + q];
+        gX[m * W + q] = ok ? (float)(g2 * ((double)x - (double)c)) : 0.0f;
+      }
+    }
   }
-  gX[e] = (float)(g2 * ((double)X[e] - (double)C[(int64_t)k * L + d]));
 }
 
 }  // namespace
@@ -258,8 +345,14 @@ void plan_distortion(Carver& c, int64_t M, DistWs* ws) {
 int launch_distortion(const float* X, int64_t M, int64_t L, const float* C,
                       int64_t N, const int32_t* idx, double* D,
                       const DistWs& ws, hipStream_t s) {
-  hipLaunchKernelGGL(rowdist_kernel, dim3((unsigned)ws.nparts), dim3(kThreads), 0, s, X,
-                     M, (int)L, C, (int)N, idx, ws.part);
+  const bool v4 = (L % kDC == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
+                  ((reinterpret_cast<uintptr_t>(C) & 15) == 0);
+  if (v4)
+    hipLaunchKernelGGL(rowdist_kernel<true>, dim3((unsigned)ws.nparts), dim3(kThreads), 0, s,
+                       X, M, (int)L, C, (int)N, idx, ws.part);
+  else
+    hipLaunchKernelGGL(rowdist_kernel<false>, dim3((unsigned)ws.nparts), dim3(kThreads), 0, s,
+                       X, M, (int)L, C, (int)N, idx, ws.part);
   LBG_TRY_HIP(hipGetLastError());
   return launch_reduce_parts(ws.part, ws.nparts, (double)M, D, s);
 }
@@ -267,9 +360,29 @@ int launch_distortion(const float* X, int64_t M, int64_t L, const float* C,
 int launch_grad_x(const float* X, int64_t M, int64_t L, const float* C,
                   int64_t N, const int32_t* idx, double g2, float* gX,
                   hipStream_t s) {
-  const int64_t grid = (M * L + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(grad_x_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, X, M,
-                     (int)L, C, (int)N, idx, g2, gX);
+  const bool vec = (L % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(C) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(gX) & 15) == 0);
+  const int words = (int)(vec ? L / 4 : L);
+  int G = 1;
+  while (G < words && G < kThreads) G <<= 1;
+  const int64_t per_block = (int64_t)(kThreads / G) * kGU;
+  const unsigned grid =
+      (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (M + per_block - 1) / per_block));
+  const int l = (int)L, n = (int)N;
+#define LBG_GX(GG, VV)                                                                       \
+  if (G == GG && vec == VV) {                                                                \
+    hipLaunchKernelGGL((grad_x_kernel<GG, VV>), dim3(grid), dim3(kThreads), 0, s, X, M, l, C, \
+                       n, idx, g2, gX);                                                      \
+  } else
+  LBG_GX(1, true) LBG_GX(2, true) LBG_GX(4, true) LBG_GX(8, true) LBG_GX(16, true)
+  LBG_GX(32, true) LBG_GX(64, true)
+  LBG_GX(1, false) LBG_GX(2, false) LBG_GX(4, false) LBG_GX(8, false) LBG_GX(16, false)
+  LBG_GX(32, false) LBG_GX(64, false) LBG_GX(128, false) LBG_GX(256, false) {
+    set_error("internal: no gradient kernel for %d lanes per row", G);
+    return LBG_EINVAL;
+  }
+#undef LBG_GX
   LBG_TRY_HIP(hipGetLastError());
   return LBG_OK;
 }

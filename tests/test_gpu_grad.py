@@ -116,3 +116,38 @@ def test_grad_c_is_cell_sum_closed_form(case):
     np.add.at(ref, idx, C[idx] - X)
     ref *= 2.0 / M
     np.testing.assert_allclose(case["gC"], ref, rtol=2 ** -20, atol=1e-12)
+
+
+@pytest.mark.parametrize("M,L,n", [(1, 1, 1), (999, 3, 5), (4097, 16, 64), (3001, 17, 9),
+                                   (2049, 64, 300), (513, 200, 7), (70001, 16, 256)])
+def test_grad_x_exact_layouts(P, M, L, n):
+    # dD/dX = (2g/M)(x - c_idx) in FP64, rounded once: bit-identical to the
+    # oracle's closed form rounded to FP32, on the 16-byte path (L % 4 == 0)
+    # and the scalar path (other L, misaligned X); rows whose index is out of
+    # range get zeros and leave the other rows unchanged
+    X = (synth.gmm(M + 5, M, L, 7)).astype(np.float32)
+    rng = np.random.default_rng(M * 3 + L)
+    C = rng.normal(100.0, 30.0, size=(n, L)).astype(np.float32)
+    idx = rng.integers(0, n, size=M).astype(np.int32)
+    g = 0.75
+    want, _ = oracle.grad(X, C.astype(np.float64), idx, g=g)
+    want = want.astype(np.float32)
+    Cd = torch.from_numpy(C).cuda()
+    bad = np.zeros(M, bool)
+    if M > 1:
+        bad[rng.choice(M, size=M // 50 + 1, replace=False)] = True
+    idx_bad = np.where(bad, n, idx).astype(np.int32)
+    for misaligned in (False, True):
+        if misaligned:
+            buf = torch.zeros(M * L + 1, dtype=torch.float32, device="cuda")
+            buf[1:] = torch.from_numpy(X).cuda().reshape(-1)
+            Xd = buf[1:].view(M, L)
+        else:
+            Xd = torch.from_numpy(X).cuda()
+        gX, _ = P.distortion_backward(Xd, Cd, torch.from_numpy(idx).cuda(), g, need_c=False)
+        np.testing.assert_array_equal(gX.cpu().numpy(), want)
+        gB, _ = P.distortion_backward(Xd, Cd, torch.from_numpy(idx_bad).cuda(), g,
+                                      need_c=False)
+        got = gB.cpu().numpy()
+        assert np.all(got[bad] == 0.0)
+        np.testing.assert_array_equal(got[~bad], want[~bad])

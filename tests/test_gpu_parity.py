@@ -250,6 +250,49 @@ def test_distortion(P, M, L, n):
     assert abs(got - want) <= 1e-12 * abs(want)
 
 
+@pytest.mark.parametrize("M,L,n", [(1, 16, 1), (1000, 20, 37), (4097, 64, 300),
+                                   (70001, 16, 256), (999, 3, 5), (3001, 200, 20),
+                                   (2049, 32, 8), (5000, 17, 40)])
+def test_distortion_rows_in_lds(P, M, L, n):
+    # the distortion pass stages rows through LDS 16 dimensions at a time:
+    # ragged chunks (L = 17, 20, 200), one row, misaligned X (scalar path)
+    X = _gmm(M + 3, M, L, 5)
+    rng = np.random.default_rng(L)
+    C = rng.normal(size=(n, L)).astype(np.float32) * 10
+    idx = rng.integers(0, n, size=M).astype(np.int32)
+    if M > 1:
+        idx[rng.choice(M, size=M // 100 + 1, replace=False)] = n  # rows that add 0
+    good = idx < n
+    want_sum = oracle.distortion(X[good], C.astype(np.float64), idx[good]) * int(good.sum())
+    got = float(P.distortion(dev(X), dev(C), dev(idx)))
+    assert abs(got * M - want_sum) <= 1e-12 * abs(want_sum)
+    buf = torch.zeros(M * L + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = dev(X).reshape(-1)
+    got_mis = float(P.distortion(buf[1:].view(M, L), dev(C), dev(idx)))
+    assert got_mis == got  # same per-row values, same order
+
+
+@pytest.mark.parametrize("M,L,n,prec", [(70001, 16, 256, "fp32"), (4097, 64, 300, "fp32"),
+                                        (999, 3, 5, "fp32"), (3001, 200, 20, "fp32"),
+                                        (2049, 32, 8, "fp32"), (1, 16, 4, "fp32"),
+                                        (5000, 64, 129, "bf16"), (5000, 16, 64, "bf16")])
+def test_assign_distortion_one_pass(P, M, L, n, prec):
+    # allocation + distortion in one pass: the allocation of lbg_assign, and
+    # the oracle's FP64 distortion of it (same per-row values, another order)
+    X = _img_rows(M) if (L == 16 and M <= 16384) else _gmm(M + 11, M, L, 9)
+    rng = np.random.default_rng(M + L)
+    C = np.ascontiguousarray(X[rng.choice(M, size=min(n, M), replace=False)])
+    while C.shape[0] < n:
+        C = np.concatenate([C, C[-1:] + 1.0])
+    Xd, Cd = dev(X), dev(C)
+    idx, mind, D = P.assign_distortion(Xd, Cd, prec, with_mind=True)
+    idx2, mind2 = P.assign(Xd, Cd, prec)
+    assert torch.equal(idx, idx2) and torch.equal(mind, mind2)
+    want = oracle.distortion(X, C.astype(np.float64), host(idx))
+    assert abs(float(D) - want) <= 1e-12 * abs(want)
+    assert abs(float(D) - float(P.distortion(Xd, Cd, idx))) <= 1e-12 * abs(want)
+
+
 def _config0():
     return synth.image_training_set((0,), 256, 256, 4)
 
