@@ -193,6 +193,17 @@ __global__ __launch_bounds__(kThreads) void segsum_kernel(
   double acc[DPL];
 #pragma unroll
   for (int q = 0; q < DPL; ++q) acc[q] = 0.0;
+  // MODE 1: the current cell's codevector, held in registers and reloaded
+  // when the cell changes (not once per row)
+  double cq[DPL];
+  auto load_c = [&]() {
+#pragma unroll
+    for (int q = 0; q < DPL; ++q) {
+      const int d = gl + q * G;
+      cq[q] = (MODE == 1 && d < L) ? (double)C_old[(int64_t)k * L + d] : 0.0;
+    }
+  };
+  load_c();
 
   for (int64_t j0 = s0; j0 < s1; j0 += U) {
     int32_t rows[U];
@@ -212,12 +223,10 @@ __global__ __launch_bounds__(kThreads) void segsum_kernel(
       if (jj >= s1) break;
 #pragma unroll
       for (int q = 0; q < DPL; ++q) {
-        const int d = gl + q * G;
         if (MODE == 0) {
           acc[q] += (double)xs[u][q];
         } else {
-          const double c = (d < L) ? (double)C_old[(int64_t)k * L + d] : 0.0;
-          acc[q] += c - (double)xs[u][q];
+          acc[q] += cq[q] - (double)xs[u][q];
         }
       }
       if (jj + 1 == cend || jj + 1 == s1) {
@@ -241,6 +250,7 @@ __global__ __launch_bounds__(kThreads) void segsum_kernel(
             ++k;
           } while (bin_off[k + 1] <= jj + 1);
           cend = bin_off[k + 1];
+          load_c();
         }
       }
     }

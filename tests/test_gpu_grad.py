@@ -151,3 +151,27 @@ def test_grad_x_exact_layouts(P, M, L, n):
         got = gB.cpu().numpy()
         assert np.all(got[bad] == 0.0)
         np.testing.assert_array_equal(got[~bad], want[~bad])
+
+
+@pytest.mark.parametrize("M,L,N", [(20000, 64, 4096), (7777, 48, 6000), (300, 64, 4096)])
+def test_grad_c_sorted_cells(P, M, L, N):
+    # codebooks beyond the fixed-point path's LDS budget sum the cells through
+    # the sorted allocation: sum_cell (c - x) in FP64, times 2g/M, rounded
+    # once; the oracle accumulates -(2g/M)(x - c) row by row in FP64, so the
+    # two agree to FP32 rounding (empty cells: exactly 0)
+    X = synth.gmm(M + 9, M, L, 31).astype(np.float32)
+    rng = np.random.default_rng(N + L)
+    C = (X[rng.choice(M, size=min(M, N), replace=False)] + 0.5).astype(np.float32)
+    if C.shape[0] < N:
+        C = np.concatenate([C, rng.normal(size=(N - C.shape[0], L)).astype(np.float32)])
+    idx = rng.integers(0, min(M, N), size=M).astype(np.int32)
+    g = 1.25
+    _, want = oracle.grad(X, C.astype(np.float64), idx, g=g)
+    _, gC = P.distortion_backward(torch.from_numpy(X).cuda(), torch.from_numpy(C).cuda(),
+                                  torch.from_numpy(idx).cuda(), g, need_x=False)
+    got = gC.cpu().numpy().astype(np.float64)
+    used = np.zeros(N, bool)
+    used[idx] = True
+    assert np.all(got[~used] == 0.0)
+    scale = np.abs(want[used]).max()
+    np.testing.assert_allclose(got[used], want[used], rtol=2.0 ** -22, atol=1e-12 * scale)
