@@ -198,7 +198,10 @@ def test_centroid(P, M, L):
 
 
 UPDATE_CASES = [(1, 1, 1), (100, 16, 7), (4096, 16, 64), (20000, 16, 256), (9000, 64, 1024),
-                (5000, 3, 9), (3000, 100, 50), (1000, 200, 5), (70000, 8, 4096)]
+                (5000, 3, 9), (3000, 100, 50), (1000, 200, 5), (70000, 8, 4096),
+                # codebooks beyond the fixed-point path's LDS budget: cells summed
+                # through the sorted allocation (LDS histogram; N > 8192: global one)
+                (30000, 64, 4096), (4000, 128, 2000), (3000, 256, 1000), (50000, 16, 20000)]
 
 
 @pytest.mark.parametrize("M,L,n", UPDATE_CASES)
@@ -346,6 +349,21 @@ def test_train_wide_codebook_matches_oracle(P):
     X = _img_rows(4096, 64, 11)
     C, idx, D, st = P.train(dev(X), 512)
     ref = oracle.train(X, 512, store_fp32=True)
+    np.testing.assert_array_equal(st["level_iters"], ref["level_iters"])
+    np.testing.assert_array_equal(host(idx), ref["idx"])
+    np.testing.assert_array_equal(host(C), ref["C"].astype(np.float32))
+    assert abs(D - ref["D"]) <= 1e-12 * ref["D"]
+
+
+@pytest.mark.parametrize("M,L,N", [(2000, 200, 16), (2048, 256, 1024)])
+def test_train_host_loop_matches_oracle(P, M, L, N):
+    # L > 128 runs the host-controlled loop (FP64 allocation); at L = 256,
+    # N = 1024 its updates sum the cells through the sorted allocation.
+    # Integer-valued data: every sum is exact, so the run equals the oracle's
+    # with FP32 codebook storage
+    X = np.rint(_gmm(L + N, M, L, 12)).astype(np.float32)
+    C, idx, D, st = P.train(dev(X), N)
+    ref = oracle.train(X, N, store_fp32=True)
     np.testing.assert_array_equal(st["level_iters"], ref["level_iters"])
     np.testing.assert_array_equal(host(idx), ref["idx"])
     np.testing.assert_array_equal(host(C), ref["C"].astype(np.float32))
