@@ -29,6 +29,17 @@ constexpr int kT = 256;        // threads per workgroup
 constexpr int kU = 4;          // rows per thread in flight
 constexpr int kMaxGrid = 2048; // eight workgroups per CU
 
+// Decoder outputs are written once and not read again by the kernel: stores
+// marked non-temporal where a wave's store covers whole cache lines
+// (consecutive lanes on consecutive 16-byte words).  Where each lane writes
+// its own run (pictures -> blocks), non-temporal partial-line writes
+// measured three times slower than plain stores, which L2 combines.
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_nt(float4* p, float4 v) {
+  const f4v x = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(x, reinterpret_cast<f4v*>(p));
+}
+
 __device__ __forceinline__ float4 nan4() {
   const float q = __builtin_nanf("");
   return make_float4(q, q, q, q);
@@ -64,7 +75,7 @@ __global__ __launch_bounds__(kT) void decode_kernel(const int32_t* __restrict__ 
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int64_t m = base + u * RB + r;
-        if (lane_on && m < M) Y4[m * W + q] = v[u];
+        if (lane_on && m < M) st_nt(&Y4[m * W + q], v[u]);
       }
     } else {
       float v[kU];
@@ -166,7 +177,7 @@ __global__ __launch_bounds__(kT) void block_rows_kernel(const int32_t* __restric
 #pragma unroll
         for (int dy = 0; dy < B; ++dy)
 #pragma unroll
-          for (int q = 0; q < BQ; ++q) dst[dy * W4 + q] = w[dy * BQ + q];
+          for (int q = 0; q < BQ; ++q) st_nt(&dst[dy * W4 + q], w[dy * BQ + q]);
       } else {
         const float4* src = reinterpret_cast<const float4*>(in) + prow + (int64_t)bx * BQ;
 #pragma unroll
@@ -175,7 +186,7 @@ __global__ __launch_bounds__(kT) void block_rows_kernel(const int32_t* __restric
           for (int q = 0; q < BQ; ++q) w[dy * BQ + q] = src[dy * W4 + q];
         float4* dst = reinterpret_cast<float4*>(out) + v * L4;
 #pragma unroll
-        for (int e = 0; e < L4; ++e) dst[e] = w[e];
+        for (int e = 0; e < L4; ++e) dst[e] = w[e];  // (plain: see st_nt)
       }
     }
   }
