@@ -243,6 +243,10 @@ __global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ ins
   const int i = tb.b2i[tb.off[kPreFin] + blockIdx.x];
   const BInst& B = inst[i];
   const int k = (int)((int64_t)blockIdx.x - fin_pre[i]);
+  // A cell beyond the codebook this round updates or splits has nothing to
+  // do in any case (and a finished run does nothing at all); only cell 0
+  // commits the state.  Such workgroups leave before loading partials.
+  if (k != 0 && k >= B.pend->n_src) return;
   const Ctl ctl{B.st, B.pend, B.dpart, (B.M + 31) / 32, B.Dtrace, B.Atrace};
   const CbPair cbp{{B.Cb[0], B.Cb[1]}};
   int N = B.N;
