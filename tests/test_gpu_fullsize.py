@@ -13,6 +13,11 @@ times, against the FP64 oracle.
   its 8 best codevectors by the expanded form: the rows kept have a gap of
   at least 1e-3 (d1 + 1) between their two best distances, far above what a
   perturbation of 1e-3 changes, so the minimum stays among them.
+* Precision form (256 pictures of 1024 x 1024 in 8 x 8 blocks: M =
+  4,194,304, L = 64, N = 1024): from the codebook of 10 exact iterations,
+  the exact step equals the oracle (allocation on a 65,536-row subsample,
+  update on every row); the BF16 step is within relative 1e-3 per
+  codevector and in D, with few and cheap misallocations on the subsample.
 """
 import numpy as np
 import pytest
@@ -113,3 +118,51 @@ def test_differentiation_full_size(P):
     assert np.all(gC[~nz] == 0.0)
     scale = np.abs(want_C).max()
     np.testing.assert_allclose(gC, want_C, rtol=2.0 ** -21, atol=1e-9 * scale)
+
+
+def _pictures_b8(seeds):
+    import concurrent.futures as cf
+    # threads (NumPy releases the GIL in the blob sums): no fork of a process
+    # that holds the GPU
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:
+        parts = list(ex.map(lambda s: synth.blocks(synth.image(s, 1024, 1024), 8), seeds))
+    return np.ascontiguousarray(np.concatenate(parts).astype(np.float32))
+
+
+def test_precision_form_full_size(P):
+    # 256 pictures of 1024 x 1024 in 8 x 8 blocks (M = 4,194,304, L = 64),
+    # N = 1024 distinct training vectors, 10 exact iterations give the
+    # reference codebook; then one exact step and one BF16 step from it
+    cfg = synth.CONFIG2
+    X = _pictures_b8(cfg["seeds"])
+    M, L, N = X.shape[0], X.shape[1], cfg["N"]
+    assert (M, L) == (4_194_304, 64)
+    C0 = np.ascontiguousarray(X[synth.distinct_rows(X, N, 1000)])
+    Xd = torch.from_numpy(X).cuda()
+    Cref, _, _, st = P.train(Xd, N, C_init=torch.from_numpy(C0).cuda(), fixed_iters=10)
+    assert st["level_iters"] == [10]
+    idx_f, _ = P.assign(Xd, Cref, P.FP32, with_mind=False)
+    idx_b, _ = P.assign(Xd, Cref, P.BF16_RESCORE, with_mind=False)
+    Cf1, _ = P.update(Xd, idx_f, Cref)
+    Cb1, _ = P.update(Xd, idx_b, Cref)
+    D_f = float(P.distortion(Xd, Cref, idx_f))
+    D_b = float(P.distortion(Xd, Cref, idx_b))
+    Ch = Cref.cpu().numpy().astype(np.float64)
+    f_idx = idx_f.cpu().numpy()
+    # exact step: allocation on a 65,536-row subsample, update on all rows
+    rows = np.sort(np.random.default_rng(1001).choice(M, 65_536, replace=False))
+    idx_o, d1, d2 = oracle.assign(X[rows], Ch)
+    np.testing.assert_array_equal(f_idx[rows], idx_o)
+    want_C, _ = oracle.update(X, f_idx, Ch, store_fp32=True)
+    np.testing.assert_array_equal(Cf1.cpu().numpy(), want_C.astype(np.float32))
+    # BF16 step: per-codevector relative 1e-3 against the exact step, D 1e-3;
+    # a row it allocates differently costs at most a small excess distance
+    cb, cf = Cb1.cpu().numpy().astype(np.float64), Cf1.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(cb - cf, axis=1) / np.maximum(np.linalg.norm(cf, axis=1), 1e-30)
+    assert rel.max() <= 1e-3
+    assert abs(D_b - D_f) <= 1e-3 * D_f
+    ib = idx_b.cpu().numpy()[rows]
+    dsel = ((X[rows].astype(np.float64) - Ch[ib]) ** 2).sum(1)
+    assert np.all(dsel >= d1 * (1.0 - 1e-12))  # (numpy sums in another order)
+    assert ((dsel - d1) / np.maximum(d1, 1e-30)).max() <= 1e-2
+    assert (ib != idx_o).mean() <= 1e-3
