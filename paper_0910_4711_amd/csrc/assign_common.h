@@ -642,25 +642,16 @@ __device__ __forceinline__ Bound bound_of(int L, int tile_bits) {
 }
 
 // Half of the codevector row that lane half h scores in the chained FP64
-// distance: dimensions [h LP/2, (h+1) LP/2), from the resident screen copy
-// (-2c, exact: times -1/2) or from C.
+// distance: dimensions [h LP/2, (h+1) LP/2), from the resident FP32 screen
+// copy (-2c, exact: times -1/2) or from C.  The split screen's resident rows
+// hold BF16 parts; its candidates are read from C (a cache hit), which
+// measured faster than rebuilding the FP32 values from the parts.
 template <class SC, bool VEC>
 __device__ __forceinline__ void c_half(const float* __restrict__ C, int L,
                                        const typename SC::elem* resident, int w, int h,
                                        float (&cr)[SC::LP / 2]) {
   constexpr int H = SC::LP / 2;
-  if (resident && SC::SPLIT) {
-    // -2c from its three parts (exact), times -1/2 (exact)
-    const __bf16* r = reinterpret_cast<const __bf16*>(resident) + (int64_t)w * SC::S + h * H;
-#pragma unroll
-    for (int q = 0; q < H; q += 8) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(r + q);
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(r + SC::LP + q);
-      const bf16x8 c = *reinterpret_cast<const bf16x8*>(r + 2 * SC::LP + q);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) cr[q + e] = -0.5f * join3(a[e], b[e], c[e]);
-    }
-  } else if (resident) {
+  if (resident && !SC::SPLIT) {
     const float* r = reinterpret_cast<const float*>(resident) + (int64_t)w * SC::S + h * H;
 #pragma unroll
     for (int q = 0; q < H; q += 4) {
