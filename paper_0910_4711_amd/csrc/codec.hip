@@ -33,7 +33,9 @@ constexpr int kMaxGrid = 2048; // eight workgroups per CU
 // marked non-temporal where a wave's store covers whole cache lines
 // (consecutive lanes on consecutive 16-byte words).  Where each lane writes
 // its own run (pictures -> blocks), non-temporal partial-line writes
-// measured three times slower than plain stores, which L2 combines.
+// measured three times slower than plain stores, which L2 combines; that
+// direction stages through LDS when the layout allows (STAGE below) and
+// stores plainly otherwise.
 typedef float f4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void st_nt(float4* p, float4 v) {
   const f4v x = {v.x, v.y, v.z, v.w};
@@ -153,12 +155,18 @@ __global__ __launch_bounds__(kT) void decode_image_kernel(const int32_t* __restr
 // across lanes (consecutive lanes take consecutive blocks of a block row).
 // Block rows R = p (H / b) + by start at picture row R b.  DIR 0: decoder,
 // DIR 1: pictures -> vectors.
-template <int BQ, int TPR, int DIR>
+// STAGE (pictures -> vectors, b = 4, W / b a multiple of 64): a wave's 64
+// lanes then hold 64 consecutive blocks of one block row, whose vectors are
+// one contiguous run; the wave passes them through LDS so that every store
+// instruction writes whole lines (consecutive lanes on consecutive words).
+template <int BQ, int TPR, int DIR, bool STAGE = false>
 __global__ __launch_bounds__(kT) void block_rows_kernel(const int32_t* __restrict__ idx,
                                                         const float* __restrict__ C, int N,
                                                         Geo g, const float* __restrict__ in,
                                                         float* __restrict__ out) {
   constexpr int B = 4 * BQ, L4 = B * BQ, RB = kT / TPR;  // L4: float4 words per block
+  static_assert(!STAGE || (DIR == 1 && TPR >= 64), "staged stores: whole waves in one row");
+  __shared__ float4 stg[STAGE ? kT * L4 : 1];
   const int c = threadIdx.x % TPR, rr = threadIdx.x / TPR;
   const int64_t W4 = g.W / 4;
   const int64_t nrows = g.rows / B;  // block rows of all pictures
@@ -184,9 +192,21 @@ __global__ __launch_bounds__(kT) void block_rows_kernel(const int32_t* __restric
         for (int dy = 0; dy < B; ++dy)
 #pragma unroll
           for (int q = 0; q < BQ; ++q) w[dy * BQ + q] = src[dy * W4 + q];
-        float4* dst = reinterpret_cast<float4*>(out) + v * L4;
+        if constexpr (STAGE) {
+          const int wl = threadIdx.x & 63;
+          float4* sw = stg + (threadIdx.x >> 6) * 64 * L4;
 #pragma unroll
-        for (int e = 0; e < L4; ++e) dst[e] = w[e];  // (plain: see st_nt)
+          for (int e = 0; e < L4; ++e) sw[wl * L4 + e] = w[e];
+          __builtin_amdgcn_wave_barrier();
+          float4* dst = reinterpret_cast<float4*>(out) + (v - wl) * L4;
+#pragma unroll
+          for (int e = 0; e < L4; ++e) st_nt(&dst[e * 64 + wl], sw[e * 64 + wl]);
+          __builtin_amdgcn_wave_barrier();
+        } else {
+          float4* dst = reinterpret_cast<float4*>(out) + v * L4;
+#pragma unroll
+          for (int e = 0; e < L4; ++e) dst[e] = w[e];  // (plain: see st_nt)
+        }
       }
     }
   }
@@ -337,6 +357,7 @@ int launch_image(int dir, const int32_t* idx, const float* C, int64_t N, int64_t
                    (dir == 0 ? a16(C) && a16(out) : a16(img_in) && a16(out));
   if (vec && b <= 8) {
     const int TB = pow2_at_least(g.nbx, kT);
+    const bool stage = dir == 1 && b == 4 && g.nbx % 64 == 0;  // then TB >= 64
     const unsigned gb = grid_for(g.rows / b, kT / TB);
     const int n0 = (int)N;
 #define LBG_BR(BB, TT)                                                                       \
@@ -344,6 +365,9 @@ int launch_image(int dir, const int32_t* idx, const float* C, int64_t N, int64_t
     if (dir == 0)                                                                            \
       hipLaunchKernelGGL((block_rows_kernel<BB, TT, 0>), dim3(gb), dim3(kT), 0, s, idx, C, n0, \
                          g, nullptr, out);                                                   \
+    else if (stage)                                                                          \
+      hipLaunchKernelGGL((block_rows_kernel<BB, (TT < 64 ? 64 : TT), 1, true>), dim3(gb),     \
+                         dim3(kT), 0, s, nullptr, nullptr, 0, g, img_in, out);               \
     else                                                                                     \
       hipLaunchKernelGGL((block_rows_kernel<BB, TT, 1>), dim3(gb), dim3(kT), 0, s, nullptr,    \
                          nullptr, 0, g, img_in, out);                                        \

@@ -99,6 +99,8 @@ PICTURE_CASES = [
     (1, 7, 13, 1),
     (5, 40, 40, 5),
     (1, 16, 2048, 8),
+    (2, 16, 256, 4),    # 64 blocks per block row: stores staged through LDS
+    (1, 8, 1280, 4),    # 320 blocks per row: staged, whole waves idle on the second pass
 ]
 
 
