@@ -455,7 +455,7 @@ def form_codec(args):
                                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                      "frac": blk_gbs / PEAK_HBM_GBS,
                                      "algorithmic_bytes": blk_bytes,
-                                     "kernel": "block_rows_kernel<1, 128, 1> (pictures to blocks)"},
+                                     "kernel": "block_rows_kernel<1, 128, 1, true> (pictures to blocks, stores staged through LDS)"},
            "encode": {"distances_per_s": M * N / (ms_enc * 1e-3), "tflops": enc_tf,
                       "frac_fp32_mfma": enc_tf / PEAK_FP32_MFMA_TFLOPS}}
     print(json.dumps(out), flush=True)
