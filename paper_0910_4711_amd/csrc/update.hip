@@ -143,9 +143,22 @@ __global__ __launch_bounds__(64) void scatter_kernel(
   __syncthreads();
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t r0 = tile * T, r1 = min(M, r0 + T);
+  // the cell indices of kPF steps are loaded together, ahead of the steps
+  constexpr int kPF = 16;
+  int kq[kPF];
   for (int64_t base = r0; base < r1; base += 64) {
+    const int st = (int)(((base - r0) >> 6) % kPF);
+    if (st == 0) {
+#pragma unroll
+      for (int u = 0; u < kPF; ++u) {
+        const int64_t ru = base + 64 * u + lane;
+        kq[u] = (ru < r1) ? idx[ru] : -1;
+      }
+    }
+    int k = kq[0];
+#pragma unroll
+    for (int u = 1; u < kPF; ++u) k = (st == u) ? kq[u] : k;
     const int64_t r = base + lane;
-    const int k = (r < r1) ? idx[r] : -1;
     const bool valid = (unsigned)k < (unsigned)N;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < nbits; ++b) {
