@@ -31,6 +31,15 @@
  *   - Cell indices are int32; codevector index ties go to the lowest index.
  *   - Results are deterministic: the same inputs give bit-identical outputs
  *     on every run (no floating-point atomics anywhere).
+ *   - Non-finite values: a training vector with a NaN or infinite coordinate
+ *     has no finite distance to any codevector; the allocation gives it
+ *     index 0 and distance +inf (the first strictly smaller distance,
+ *     starting from +inf, never occurs), so a distortion over it is +inf
+ *     (lbg_assign_distortion) or NaN / +inf (lbg_distortion, the direct
+ *     distance to codevector 0).  lbg_train and lbg_train_batched stop a run
+ *     whose distortion is not finite at that allocation and report
+ *     LBG_EINVAL.  Codebooks must be finite; lbg_update and the gradient
+ *     assume finite X.
  */
 #ifndef LBG_H
 #define LBG_H
@@ -96,7 +105,8 @@ int lbg_centroid(const float* X, int64_t M, int64_t L, float* c0, void* ws,
  * x_m of X (M x L) the index of the nearest row of C (N x L) under the
  * squared Euclidean distance, lowest index on ties:
  *   idx[m] = min { k : d(x_m, c_k) = min_j d(x_m, c_j) }.
- * mind[m] (nullable) receives d(x_m, c_idx[m]) rounded to FP32.
+ * mind[m] (nullable) receives d(x_m, c_idx[m]) rounded to FP32 (+inf and
+ * index 0 for a row with a non-finite coordinate).
  *
  * precision == LBG_FP32: distances are screened on matrix cores in the
  * expanded form |x|^2 - 2 x.c + |c|^2 with FP32 accuracy (from exact
@@ -121,8 +131,13 @@ int lbg_assign(const float* X, int64_t M, int64_t L, const float* C, int64_t N,
  * Codebook Updation (Algorithm 1, "Codebook Updation"; Sec. 3.2): every
  * codevector becomes the centroid of its cell,
  *   C_new[k] = (1/|S_k|) sum_{m : idx[m] = k} x_m,
- * summed in FP64 in a fixed order (cell by cell, rows in index order within
- * fixed-size runs, runs combined in order) and rounded to FP32.  An empty
+ * rounded to FP32.  The sum is formed exactly, in 64-bit integers, from
+ * every coordinate taken as round(x 2^s) (s from the largest |x| and M) and,
+ * for data off that grid, its residual as a second integer word at 2^-(s+t)
+ * (t = min(52, 63 - log2 M)): exact for coordinates down to 2^-(s+t), about
+ * 2^-80 of the largest |x| at M = 2^22, so the result does not depend on the
+ * order of the rows; it is divided once in FP64.  (Codebooks with more than
+ * 32 x 60 KB of sums use fixed-order FP64 segmented sums instead.)  An empty
  * cell keeps C_old[k].  counts[k] (nullable, int32) receives |S_k|.
  * C_new may equal C_old (in place); otherwise they must not overlap.
  * Entries of idx outside [0, N) are ignored (they join no cell).
@@ -163,9 +178,11 @@ int lbg_assign_distortion(const float* X, int64_t M, int64_t L, const float* C,
  * scaled by g (the upstream gradient of a scalar loss):
  *   gX[m] = g * 2/M * (x_m - c_idx[m])
  *   gC[k] = g * 2/M * sum_{m : idx[m] = k} (c_k - x_m)
- * gC sums the differences in FP64 in the fixed order of lbg_update.  Either
- * output may be NULL.  At a tie the gradient is the one of the lowest-index
- * minimiser (the allocation passed in).
+ * gC[k] is formed as count * c_k - (the cell sum of lbg_update), the
+ * difference taken exactly in integers on the sums' grid (and in FP64 for
+ * a codevector beyond 2^62 of that grid, where it cannot cancel) before
+ * one rounding.  Either output may be NULL.  At a tie the gradient is the
+ * one of the lowest-index minimiser (the allocation passed in).
  */
 int lbg_distortion_backward(const float* X, int64_t M, int64_t L,
                             const float* C, int64_t N, const int32_t* idx,
@@ -278,7 +295,9 @@ typedef struct lbg_stats {
  * On return C_out (DEVICE, N x L) holds the codebook that produced the last
  * allocation, idx_out (DEVICE, M) that allocation and *D_out (HOST) its
  * distortion.  st (HOST, nullable) receives statistics.  Synchronises
- * ``stream``.
+ * ``stream``.  A distortion that is not finite (a NaN or infinite value in
+ * X or C_init) stops the run at that allocation with LBG_EINVAL; C_out,
+ * idx_out and *D_out then hold that allocation's state.
  */
 int lbg_train(const float* X, int64_t M, int64_t L, int64_t N,
               const lbg_params* p, float* C_out, int32_t* idx_out,
@@ -358,8 +377,11 @@ size_t lbg_train_batched_workspace(const lbg_instance* inst, int32_t n_inst);
  * the shared parameters p (precision LBG_FP32; C_init and forced_iters are
  * not supported).  res (HOST, nullable) receives one lbg_batch_result per
  * instance, st (HOST, nullable) the statistics.  Returns LBG_OK,
- * LBG_WMAXITER if any instance hit the cap, or an error code (nothing is
- * trained then).  Synchronises ``stream``.
+ * LBG_WMAXITER if any instance hit the cap, LBG_EINVAL if an instance's
+ * distortion was not finite (a NaN or infinite training value: that
+ * instance's status is LBG_EINVAL, the other instances are trained and
+ * their results valid), or another error code (nothing is trained then).
+ * Synchronises ``stream``.
  */
 int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const lbg_params* p,
                       const lbg_batch_config* cfg, lbg_batch_result* res,

@@ -527,7 +527,10 @@ def train_batched(Xs, Ns, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta
     st = BatchStats()
     rc = lib.lbg_train_batched(inst, n, ct.byref(p), ct.byref(cfg), res, ct.byref(st), _ptr(ws),
                                nb, _stream(dev))
-    _check(rc, "lbg_train_batched")
+    # an instance stopped on non-finite data reports it in its own status;
+    # the other instances' results are valid
+    if not (rc == EINVAL and any(res[i].status == EINVAL for i in range(n))):
+        _check(rc, "lbg_train_batched")
     results = []
     for i, (C, idx) in enumerate(outs):
         r = res[i]

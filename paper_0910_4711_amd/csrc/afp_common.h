@@ -16,20 +16,41 @@ constexpr int kT = 256;
 constexpr int kLdsBytes = 61440;
 constexpr int kUnroll = 16;  // rows in flight per group
 
+// Fine bits of one coordinate (FP32 bits b): -log2 of the spacing of its
+// significand's lowest set bit, plus 256 (always positive), or 0 for zero,
+// Inf and NaN; a coordinate is a multiple of 2^-s exactly when its fine bits
+// are at most s + 256.
+__device__ __forceinline__ uint32_t fine_bits(uint32_t b) {
+  b &= 0x7fffffffu;
+  if (b == 0u || b >= 0x7f800000u) return 0u;
+  const uint32_t e = b >> 23;
+  const uint32_t sig = e ? ((b & 0x7fffffu) | 0x800000u) : b;
+  const int q = (int)(e ? e : 1u) - 150 + __builtin_ctz(sig);  // spacing 2^q
+  return (uint32_t)(256 - q);
+}
+
+// Block maxima over X (n floats): part[block] = largest finite |x| (as
+// float bits), part[nblocks + block] = largest fine bits.  The blocks also
+// clear the nlo words of ``lo`` (the residual sums of the update, see
+// fin_body), so that every accumulation starts from zero.
 __device__ __forceinline__ void absmax_body(const float* __restrict__ X, int64_t n,
                                             uint32_t* __restrict__ part, int64_t block,
-                                            int64_t nblocks) {
+                                            int64_t nblocks, unsigned long long* __restrict__ lo,
+                                            int64_t nlo) {
   __shared__ uint32_t s[kT];
+  __shared__ uint32_t sf[kT];
   typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-  uint32_t m = 0;
-  auto upd = [&m](uint32_t b) {
+  uint32_t m = 0, f = 0;
+  auto upd = [&m, &f](uint32_t b) {
+    f = max(f, fine_bits(b));
     b &= 0x7fffffffu;
     m = (b > m && b < 0x7f800000u) ? b : m;  // ignore Inf / NaN
   };
+  const int64_t stride = nblocks * kT;
+  for (int64_t e = block * kT + threadIdx.x; e < nlo; e += stride) lo[e] = 0ull;
   // 16-byte loads, four per thread in flight, then the scalar tail
   const int64_t nv = (reinterpret_cast<uintptr_t>(X) & 15) == 0 ? n / 4 : 0;
   const u32x4* X4 = reinterpret_cast<const u32x4*>(X);
-  const int64_t stride = nblocks * kT;
   int64_t i = block * kT + threadIdx.x;
   for (; i + 3 * stride < nv; i += 4 * stride) {
     u32x4 v[4];
@@ -53,23 +74,48 @@ __device__ __forceinline__ void absmax_body(const float* __restrict__ X, int64_t
   for (int64_t e = 4 * nv + block * kT + threadIdx.x; e < n; e += stride)
     upd(__float_as_uint(X[e]));
   s[threadIdx.x] = m;
+  sf[threadIdx.x] = f;
   __syncthreads();
   for (int off = kT / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + off]);
+    if ((int)threadIdx.x < off) {
+      s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + off]);
+      sf[threadIdx.x] = max(sf[threadIdx.x], sf[threadIdx.x + off]);
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[block] = s[0];
+  if (threadIdx.x == 0) {
+    part[block] = s[0];
+    part[nblocks + block] = sf[0];
+  }
 }
 
+// The fixed-point scales of the update from the block maxima (nparts of
+// each kind, laid out as absmax_body writes them): shift[0] = s, with
+// |x| < 2^e and M < 2^b, s = min(51, 62 - b) - e, so that every round(x 2^s)
+// is below 2^51 and a sum of M of them below 2^62; shift[1] = t = 0 when
+// every coordinate is a multiple of 2^-s (the sums are then exact, as for
+// integer pixels), else t = min(52, 63 - b): each coordinate's residual
+// x 2^s - round(x 2^s), at most 1/2, is then also summed, as round(residual
+// 2^t), so coordinates down to 2^-(s+t) count exactly and the update keeps
+// about 2^-(s+t) of max|x| (2^-80 of it at M = 2^22) where one word kept
+// 2^-s.
 __device__ __forceinline__ void shift_body(const uint32_t* __restrict__ part, int nparts,
                                            int64_t M, int* __restrict__ shift) {
   __shared__ uint32_t s[kT];
-  uint32_t m = 0;
-  for (int i = threadIdx.x; i < nparts; i += kT) m = max(m, part[i]);
+  __shared__ uint32_t sf[kT];
+  uint32_t m = 0, f = 0;
+  for (int i = threadIdx.x; i < nparts; i += kT) {
+    m = max(m, part[i]);
+    f = max(f, part[nparts + i]);
+  }
   s[threadIdx.x] = m;
+  sf[threadIdx.x] = f;
   __syncthreads();
   for (int off = kT / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + off]);
+    if ((int)threadIdx.x < off) {
+      s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + off]);
+      sf[threadIdx.x] = max(sf[threadIdx.x], sf[threadIdx.x + off]);
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -78,10 +124,11 @@ __device__ __forceinline__ void shift_body(const uint32_t* __restrict__ part, in
     const float mx = __uint_as_float(s[0]);
     int e = 0;
     if (mx > 0.0f) frexpf(mx, &e);  // mx < 2^e
-    *shift = (s[0] == 0) ? 0 : (min(51, 62 - b) - e);
+    const int sh = (s[0] == 0) ? 0 : (min(51, 62 - b) - e);
+    shift[0] = sh;
+    shift[1] = (sf[0] != 0u && (int)sf[0] - 256 > sh) ? min(52, 63 - b) : 0;
   }
 }
-
 
 // round(v * 2^s), nearest with ties to even, as a two's-complement 64-bit
 // integer, for |v * 2^s| < 2^51 (the shift guarantees it for the training
@@ -89,17 +136,48 @@ __device__ __forceinline__ void shift_body(const uint32_t* __restrict__ part, in
 // integer (the sum lies in [2^52, 2^53), whose spacing is 1; 1.5 * 2^52 is
 // even, so ties go to even as rint's do), and the integer is the sum's bit
 // pattern minus that of 1.5 * 2^52, whose low word is zero.  p2s = 2^s.
-__device__ __forceinline__ unsigned long long fixed(float v, double p2s) {
-  const double y = __builtin_fma((double)v, p2s, 0x1.8p52);
+__device__ __forceinline__ unsigned long long fixed_of(double y) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(y);
   const uint32_t hi = (uint32_t)(b >> 32) - 0x43380000u;  // no borrow: the low word is kept
   return ((unsigned long long)hi << 32) | (b & 0xffffffffull);
 }
 
-// The same for any magnitude below 2^62 (codevectors outside the data's
-// range, in the gradient).
-__device__ __forceinline__ long long fixed_wide(float v, int s) {
-  return llrint(ldexp((double)v, s));
+__device__ __forceinline__ unsigned long long fixed(float v, double p2s) {
+  return fixed_of(__builtin_fma((double)v, p2s, 0x1.8p52));
+}
+
+// The coordinate's second word (see shift_body): round(r 2^t) for its
+// residual r = v 2^s - round(v 2^s), |r| <= 1/2.  r is exact in FP64 (v 2^s
+// and the integer are exact and within 1/2 of each other), and 2^t <= 2^52
+// keeps |r 2^t| within the range of the rounding trick.  p2t = 2^t.
+__device__ __forceinline__ unsigned long long fixed_res(float v, double p2s, double p2t) {
+  const double n = __builtin_fma((double)v, p2s, 0x1.8p52) - 0x1.8p52;  // round(v 2^s)
+  const double r = __builtin_fma((double)v, p2s, -n);
+  return fixed_of(__builtin_fma(r, p2t, 0x1.8p52));
+}
+
+// cnt c - S 2^-s (FP64) for the gradient of a cell with cnt rows whose
+// fixed-point sum is S at shift s.  When c 2^s lies below 2^62 in magnitude
+// it is rounded onto the sums' grid (ck) and cnt ck - S is formed exactly in
+// two 64-bit limbs of base 2^32 (cnt < 2^31, so no limb overflows) before
+// the conversion, so nearly equal cnt c and sum lose nothing to cancellation
+// and a codevector far outside the data cannot overflow 64 bits.  Beyond
+// 2^62 the codevector is at least 2^(62-s) >= 2^11 max|x| away from every
+// coordinate, |S 2^-s| <= cnt max|x| is far below |cnt c|, and FP64 forms
+// the difference without cancellation.
+__device__ __forceinline__ double grad_diff(float c, long long cnt, long long S, int s) {
+  const double cs = ldexp((double)c, s);  // exact
+  if (fabs(cs) < 0x1p62) {
+    const long long ck = llrint(cs);
+    const long long ck_hi = ck >> 32;                        // |ck_hi| < 2^30
+    const unsigned long long ck_lo = (unsigned long long)ck & 0xffffffffull;
+    const long long a = cnt * ck_hi;                         // |a| < 2^61
+    const unsigned long long b = (unsigned long long)cnt * ck_lo;  // < 2^63
+    const long long top = a + (long long)(b >> 32) - (S >> 32);  // |top| < 2^62
+    const long long low = (long long)(b & 0xffffffffull) - (long long)((unsigned long long)S & 0xffffffffull);
+    return ldexp(ldexp((double)top, 32) + (double)low, -s);
+  }
+  return (double)cnt * (double)c - ldexp((double)S, -s);
 }
 
 // Row layout of the accumulation: a row is handled by G lanes; lane gl
@@ -127,10 +205,13 @@ struct VLoad<1> {
 // adds need no branch.  In a full row (L = G VW DPL) dimension
 // (gl + q G) VW + e is kept at position e G DPL + q G + gl, so that the G
 // lanes of a group add into consecutive words (no LDS bank conflicts among
-// them); otherwise at position d.
-template <int G, int VW, int DPL>
+// them); otherwise at position d.  FINE: the coordinates' nonzero second
+// words (fixed_res) are added into lo_row (global, natural dimension
+// order; NULL for a row that is off) -- rare for data near their grid.
+template <int G, int VW, int DPL, bool FINE = false>
 __device__ __forceinline__ void add_row(unsigned long long* row, int32_t* cnt, int L, int gl,
-                                        double p2s, const float (&v)[DPL][VW]) {
+                                        double p2s, const float (&v)[DPL][VW],
+                                        unsigned long long* lo_row = nullptr, double p2t = 0.0) {
   if (G * VW * DPL == L) {  // a uniform test, once per row
 #pragma unroll
     for (int q = 0; q < DPL; ++q)
@@ -144,6 +225,18 @@ __device__ __forceinline__ void add_row(unsigned long long* row, int32_t* cnt, i
         const int d = (gl + q * G) * VW + e;
         if (d < L) atomicAdd(&row[d], fixed(v[q][e], p2s));
       }
+  }
+  if constexpr (FINE) {
+    if (lo_row) {
+#pragma unroll
+      for (int q = 0; q < DPL; ++q)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          const int d = (gl + q * G) * VW + e;
+          const unsigned long long r = fixed_res(v[q][e], p2s, p2t);
+          if (d < L && r != 0ull) atomicAdd(&lo_row[d], r);
+        }
+    }
   }
   if (gl == 0) atomicAdd(cnt, 1);
 }
@@ -230,16 +323,18 @@ __device__ __forceinline__ bool acc_decide(const Ctl& ctl, bool lead, int* N) {
 // cells of this update; ns: cells per chunk in the partials' layout (the
 // planned codebook size, so that the finishing kernel can address them
 // before it knows N).
-template <int G, int VW, int DPL, bool SEL, int US = kUnrollSel, int NT = kT>
+template <int G, int VW, int DPL, bool SEL, int US = kUnrollSel, int NT = kT, bool FINE = false>
 __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M, int L,
                                          const int32_t* __restrict__ idx, int N, int ns,
                                          int cps, int nslices, int64_t rows_per_chunk, int s,
                                          unsigned long long* __restrict__ part,
                                          int32_t* __restrict__ pcnt, int64_t blk,
                                          unsigned long long* sacc, int32_t* slist,
-                                         int32_t& snsel) {
+                                         int32_t& snsel, unsigned long long* lo = nullptr,
+                                         int tfine = 0) {
   const int chunk = (int)(blk / nslices), slice = (int)(blk % nslices);
   const double p2s = ldexp(1.0, s);
+  const double p2t = ldexp(1.0, tfine);
   const int k0 = slice * cps, k1 = min(N, k0 + cps), nk = max(0, k1 - k0);
   constexpr int NG = NT / G;  // rows in parallel
   // With a single slice and few cells, R private copies of the table (row
@@ -286,8 +381,9 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
         for (int u = 0; u < KU1; ++u) {
           const bool on = k[u] >= k0 && k[u] < k1;
           const int kl = k[u] - k0;
-          add_row<G, VW, DPL>(on ? my_acc + __umul24(kl, LS) : spare, on ? my_cnt + kl : cspare,
-                              L, gl, p2s, v[u]);
+          add_row<G, VW, DPL, FINE>(on ? my_acc + __umul24(kl, LS) : spare,
+                                    on ? my_cnt + kl : cspare, L, gl, p2s, v[u],
+                                    (FINE && on) ? lo + (int64_t)k[u] * L : nullptr, p2t);
         }
       }
     }
@@ -341,16 +437,20 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
           const bool on = kka[u] >= 0;
-          add_row<G, VW, DPL>(on ? sacc + __umul24(kka[u], LS) : spare, on ? scnt + kka[u] : cspare,
-                              L, gl, p2s, va[u]);
+          add_row<G, VW, DPL, FINE>(on ? sacc + __umul24(kka[u], LS) : spare,
+                                    on ? scnt + kka[u] : cspare, L, gl, p2s, va[u],
+                                    (FINE && on) ? lo + (int64_t)(k0 + kka[u]) * L : nullptr,
+                                    p2t);
         }
         if (e1 >= nsel) break;
         if (e2 < nsel) load_stage(e2, kka, va);
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
           const bool on = kkb[u] >= 0;
-          add_row<G, VW, DPL>(on ? sacc + __umul24(kkb[u], LS) : spare, on ? scnt + kkb[u] : cspare,
-                              L, gl, p2s, vb[u]);
+          add_row<G, VW, DPL, FINE>(on ? sacc + __umul24(kkb[u], LS) : spare,
+                                    on ? scnt + kkb[u] : cspare, L, gl, p2s, vb[u],
+                                    (FINE && on) ? lo + (int64_t)(k0 + kkb[u]) * L : nullptr,
+                                    p2t);
         }
       }
       __syncthreads();
@@ -424,16 +524,27 @@ __device__ __forceinline__ bool fin_state(const Ctl& ctl, const CbPair& cbp, int
 // overlap them; gate returns false (the same in every thread) when cell k
 // is not to be updated.  Thread (q, d) adds the partials of chunks q, q+Q,
 // ... (integers, so the order is immaterial), then the Q lane sums.
+//   With second words (tfine > 0, see shift_body) cell k's residual sums
+// lo[k L + d] are read and cleared before ``gate`` (whatever the decision,
+// so the next accumulation starts from zero) and enter as lo 2^-(s+tfine).
 template <int MODE, class Gate>
 __device__ __forceinline__ void fin_body(const unsigned long long* __restrict__ part,
                                          const int32_t* __restrict__ pcnt, int nchunks, int ns,
                                          int L, int s, int32_t* __restrict__ counts, double g2,
-                                         int k, Gate&& gate) {
+                                         int k, Gate&& gate, unsigned long long* lo = nullptr,
+                                         int tfine = 0) {
   constexpr int U = 16;  // partials in flight per thread
   constexpr int UC = 8;  // counts in flight per thread
   __shared__ unsigned long long red[kT];
   __shared__ long long scount;
+  __shared__ long long slo[kT];
   const int t = threadIdx.x;
+  const bool fine = lo != nullptr && tfine > 0;
+  if (fine && t < L) {
+    unsigned long long* p = lo + (int64_t)k * L + t;
+    slo[t] = (long long)*p;
+    *p = 0ull;
+  }
   int G2 = 1;
   while (G2 < L && G2 < kT) G2 <<= 1;
   const int Q = kT / G2;
@@ -497,12 +608,11 @@ __device__ __forceinline__ void fin_body(const unsigned long long* __restrict__ 
         unsigned long long sum = 0;
         for (int qi = 0; qi < Q; ++qi) sum += red[qi * G2 + t];
         const long long S = (long long)sum;
+        const double low = fine ? ldexp((double)slo[d], -(s + tfine)) : 0.0;
         if (MODE == 0) {
-          out[e] = (float)(ldexp((double)S, -s) / (double)cnt);
+          out[e] = (float)((ldexp((double)S, -s) + low) / (double)cnt);
         } else {
-          const long long ck = fixed_wide(C_old[e], s);
-          const long long diff = (long long)((unsigned long long)(cnt * ck) - (unsigned long long)S);
-          out[e] = (float)(g2 * ldexp((double)diff, -s));
+          out[e] = (float)(g2 * (grad_diff(C_old[e], cnt, S, s) - low));
         }
       }
     }

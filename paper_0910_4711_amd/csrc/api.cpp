@@ -523,6 +523,11 @@ int lbg_train(const float* X, int64_t M, int64_t L, int64_t N, const lbg_params*
                                 w.D, s));
     LBG_TRY(read_scalar(w.D, Dh, s));
     LBG_TRY(tm.collect());
+    if (!isfinite(*Dh)) {
+      set_error("the distortion is not finite: the training set or the starting codebook "
+                "holds a NaN or infinite value");
+      return LBG_EINVAL;
+    }
     if (st) {
       if (st->D_trace && st->n_D < st->D_cap) st->D_trace[st->n_D] = *Dh;
       st->n_D++;

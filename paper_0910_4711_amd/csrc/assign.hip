@@ -21,9 +21,11 @@ __global__ __launch_bounds__(256) void assign_exact_kernel(
   double best = 0.0;
   if (m < M) {
     const float* x = X + m * (int64_t)L;
+    // the first strictly smaller distance from +inf: a row with no finite
+    // distance (a non-finite coordinate) gets index 0 and +inf
     int bi = 0;
-    best = d64(x, C, L);
-    for (int k = 1; k < n; ++k) {
+    best = INFINITY;
+    for (int k = 0; k < n; ++k) {
       const double d = d64(x, C + (int64_t)k * L, L);
       if (d < best) {
         best = d;

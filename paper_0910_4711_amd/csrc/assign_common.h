@@ -875,6 +875,13 @@ __device__ __forceinline__ double finish_rows(const Slots& sl, const float* __re
       }
     }
   }
+  // A row whose distances are all NaN or infinite (a non-finite coordinate)
+  // has no nearest codevector: index 0 and distance +inf, which is what a
+  // search keeping the first strictly smaller distance returns.
+  if (!(d < INFINITY)) {
+    win = 0;
+    d = INFINITY;
+  }
   if (live) {
     idx[m] = win;
     if (mind) mind[m] = (float)d;
@@ -1345,6 +1352,7 @@ __device__ __forceinline__ void direct_rows(const float* __restrict__ X, int64_t
         bi = k;
       }
     }
+    if (!(best < INFINITY)) bi = 0;  // no finite distance: index 0, as finish_rows
     const bool live = m < M;
     if (live) {
       idx[m] = bi;

@@ -65,6 +65,7 @@ struct BInst {
   int32_t* pcnt;
   uint32_t* amax;
   int* shift;
+  unsigned long long* lo;  // second-word sums of the update (N x L)
   double* cpart;
   double* Dtrace;
   int32_t* Atrace;
@@ -187,18 +188,26 @@ __global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ ins
   if (B.st->done) return;
   if (local == 0) (void)afp::acc_decide(ctl, true, &N);  // the instance's decision
   N = B.st->n;
-  const int s = *B.shift;
+  const int s = B.shift[0], tf = B.shift[1];
   const int L = B.L;
-#define LBG_BACC(GG, VV)                                                                      \
+#define LBG_BACC1(GG, VV, FF)                                                                 \
   do {                                                                                     \
     if (B.nslices > 1)                                                                     \
-      afp::acc_body<GG, VV, 1, true, 8>(B.X, B.M, L, B.idx, N, B.N, B.cps, B.nslices,           \
-                                     B.rows_per_chunk, s, B.part, B.pcnt, local, sacc,     \
-                                     slist, snsel);                                        \
+      afp::acc_body<GG, VV, 1, true, 8, kT, FF>(B.X, B.M, L, B.idx, N, B.N, B.cps,          \
+                                                B.nslices, B.rows_per_chunk, s, B.part,    \
+                                                B.pcnt, local, sacc, slist, snsel, B.lo,   \
+                                                tf);                                       \
     else                                                                                   \
-      afp::acc_body<GG, VV, 1, false>(B.X, B.M, L, B.idx, N, B.N, B.cps, B.nslices,             \
-                                      B.rows_per_chunk, s, B.part, B.pcnt, local, sacc,    \
-                                      slist, snsel);                                       \
+      afp::acc_body<GG, VV, 1, false, afp::kUnrollSel, kT, FF>(                                  \
+          B.X, B.M, L, B.idx, N, B.N, B.cps, B.nslices, B.rows_per_chunk, s, B.part,         \
+          B.pcnt, local, sacc, slist, snsel, B.lo, tf);                                     \
+  } while (0)
+#define LBG_BACC(GG, VV)        \
+  do {                          \
+    if (tf > 0)                 \
+      LBG_BACC1(GG, VV, true);  \
+    else                        \
+      LBG_BACC1(GG, VV, false); \
   } while (0)
   if (B.vec && (L & 3) == 0) {
     const int lanes = L / 4;
@@ -229,6 +238,7 @@ __global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ ins
       LBG_BACC(64, 1);
   }
 #undef LBG_BACC
+#undef LBG_BACC1
 }
 
 // Block 0 also rearms the allocation queue for the next round (the round's
@@ -250,10 +260,12 @@ __global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ ins
   const Ctl ctl{B.st, B.pend, B.dpart, (B.M + 31) / 32, B.Dtrace, B.Atrace};
   const CbPair cbp{{B.Cb[0], B.Cb[1]}};
   int N = B.N;
-  afp::fin_body<0>(B.part, B.pcnt, B.nchunks, B.N, B.L, *B.shift, nullptr, 0.0, k,
-                   [&](const float** c_old, float** dst) {
-                     return afp::fin_state(ctl, cbp, k, k == 0, B.L, &N, c_old, dst, ndone);
-                   });
+  afp::fin_body<0>(
+      B.part, B.pcnt, B.nchunks, B.N, B.L, B.shift[0], nullptr, 0.0, k,
+      [&](const float** c_old, float** dst) {
+        return afp::fin_state(ctl, cbp, k, k == 0, B.L, &N, c_old, dst, ndone);
+      },
+      B.lo, B.shift[1]);
 }
 
 // ------------------------------------------------------------- set-up, end --
@@ -290,7 +302,8 @@ __global__ __launch_bounds__(kT) void b_absmax_kernel(const BInst* __restrict__ 
   if ((int64_t)blockIdx.x >= p[n_inst]) return;
   const int i = tb.b2i[tb.off[kPreAmax] + blockIdx.x];
   const BInst& B = inst[i];
-  afp::absmax_body(B.X, B.M * B.L, B.amax, (int64_t)blockIdx.x - p[i], B.absmax_blocks);
+  afp::absmax_body(B.X, B.M * B.L, B.amax, (int64_t)blockIdx.x - p[i], B.absmax_blocks, B.lo,
+                   (int64_t)B.N * B.L);
 }
 
 __global__ __launch_bounds__(kT) void b_shift_kernel(const BInst* __restrict__ inst) {
@@ -805,6 +818,7 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
     B.part = q.afp.part;
     B.pcnt = q.afp.pcnt;
     B.amax = q.afp.amax;
+    B.lo = q.afp.lo;
     B.shift = q.afp.shift;
     B.cpart = q.cpart;
     B.Dtrace = q.Dtrace;
@@ -987,7 +1001,8 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
   int64_t dist = 0;
   for (int i = 0; i < n; ++i) {
     const DevState& d = hs[i];
-    if (d.status != LBG_OK) status = d.status;
+    // an instance stopped on non-finite data outranks a capped one
+    if (d.status == LBG_EINVAL || (d.status != LBG_OK && status == LBG_OK)) status = d.status;
     dist += d.distances;
     if (res) {
       res[i].D = d.D;
@@ -999,6 +1014,10 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
       res[i].distances = d.distances;
     }
   }
+  if (status == LBG_EINVAL)
+    set_error("lbg_train_batched: the distortion of an instance is not finite (a NaN or "
+              "infinite training value); that instance's status is LBG_EINVAL, the others "
+              "were trained");
   if (stats) {
     stats->rounds = rounds;
     stats->grab = grab;

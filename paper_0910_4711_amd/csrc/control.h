@@ -15,16 +15,19 @@ namespace lbg {
 //     max_iter updates (status LBG_WMAXITER);
 //   - on a stop: done if the codebook has N codevectors, else split;
 //   - otherwise update.
+//   - a distortion that is not finite (a NaN or infinite coordinate in the
+//     training set or the starting codebook) ends the run with LBG_EINVAL.
 struct Step {
   int action;
-  bool stop, capped;
+  bool stop, capped, bad;
 };
 
 __device__ inline Step step_of(const DevState* st, double D) {
+  if (!isfinite(D)) return Step{kActNone, true, false, true};
   int forced = -1;
   if (st->fixed_iters > 0) forced = st->fixed_iters;
   if (st->level < st->n_forced && st->level < 32) forced = st->forced[st->level];
-  Step r{kActUpdate, false, false};
+  Step r{kActUpdate, false, false, false};
   if (forced >= 0) {
     r.stop = st->it >= forced;
   } else {
@@ -50,6 +53,7 @@ __device__ inline void apply_step(const DevState* in, DevState* out, double D, S
   if (Dtrace && a < in->D_cap) Dtrace[a] = D;
   if (Atrace && a < in->D_cap) Atrace[a] = r.action;
   if (r.capped) out->status = LBG_WMAXITER;
+  if (r.bad) out->status = LBG_EINVAL;
   out->action = r.action;
   if (r.stop) {
     if (in->level < 32) {

@@ -122,8 +122,10 @@ int launch_reduce_parts(const double* parts, int64_t nparts, double denom,
 struct AfpWs {
   unsigned long long* part;  // [nchunks][N][L] integer partial sums
   int32_t* pcnt;             // [nchunks][N] partial counts
-  uint32_t* amax;            // [absmax_blocks] block maxima of |x|
-  int* shift;                // [1] fixed-point shift s
+  uint32_t* amax;            // [2 absmax_blocks] block maxima of |x| and fine bits
+  int* shift;                // [2] fixed-point shift s, second-word shift t (0: none)
+  unsigned long long* lo;    // [N][L] second-word sums (kept zero between updates)
+  int64_t nlo;
   int cps, nslices, nchunks, absmax_blocks;
   int64_t rows_per_chunk;
 };
@@ -158,7 +160,7 @@ int launch_update(const float* X, int64_t M, int64_t L, const int32_t* idx,
 // ----------------------------------------------------------------- misc --
 struct CentroidWs {
   double* part;    // [nwg][L]
-  uint32_t* amax;  // [nwg] block maxima of |x| (set-up of a training run)
+  uint32_t* amax;  // [2 nwg] block maxima of |x| and fine bits (set-up of a training run)
   int64_t nwg;
 };
 void plan_centroid(Carver& c, int64_t M, int64_t L, CentroidWs* ws);
@@ -170,6 +172,7 @@ int launch_centroid(const float* X, int64_t M, int64_t L, float* c0,
 // launch_centroid, launch_split, launch_afp_shift and the state copy.
 int launch_setup(const float* X, int64_t M, int64_t L, float* c0, float* C2, int mode,
                  double eps, double delta, const CentroidWs& ws, int* shift,
+                 unsigned long long* lo, int64_t nlo,
                  const DevState& init, DevState* st, unsigned long long* nfb, hipStream_t s);
 
 int launch_split(const float* C, int64_t n, int64_t L, int mode, double eps,

@@ -208,32 +208,39 @@ int launch_split(const float* C, int64_t n, int64_t L, int mode, double eps,
 
 // Set-up of a training run in two launches.  setup_pass_kernel: the column
 // sums of colsum_kernel (same blocks, same order) and, from the same loads,
-// each block's largest finite |x| (as absmax_kernel forms it; a maximum does
-// not depend on the order).
+// each block's largest finite |x| and largest fine bits (as absmax_kernel
+// forms them; a maximum does not depend on the order); the blocks also clear
+// the update's second-word array lo (nlo words).
 __global__ __launch_bounds__(kThreads) void setup_pass_kernel(const float* __restrict__ X,
                                                               int64_t M, int L,
                                                               int64_t rows_per_block,
                                                               double* __restrict__ part,
-                                                              uint32_t* __restrict__ amax) {
+                                                              uint32_t* __restrict__ amax,
+                                                              unsigned long long* __restrict__ lo,
+                                                              int64_t nlo) {
   __shared__ double s[kThreads];
   __shared__ uint32_t sm[kThreads];
+  __shared__ uint32_t sf[kThreads];
   const int R = kThreads / L;
   const int t = threadIdx.x;
   const int q = t / L, d = t % L;
   const int64_t blk = blockIdx.x;
+  for (int64_t e = blk * kThreads + t; e < nlo; e += (int64_t)gridDim.x * kThreads) lo[e] = 0ull;
   const int64_t r0 = blk * rows_per_block;
   const int64_t r1 = min(M, r0 + rows_per_block);
   double acc = 0.0;
-  uint32_t m = 0;
+  uint32_t m = 0, f = 0;
   if (q < R)
     for (int64_t r = r0 + q; r < r1; r += R) {
       const float v = X[r * L + d];
       acc += (double)v;
       const uint32_t b = __float_as_uint(v) & 0x7fffffffu;
       m = (b > m && b < 0x7f800000u) ? b : m;  // ignore Inf / NaN
+      f = max(f, afp::fine_bits(b));
     }
   s[t] = acc;
   sm[t] = m;
+  sf[t] = f;
   __syncthreads();
   if (t < L) {
     double v = 0.0;
@@ -241,10 +248,16 @@ __global__ __launch_bounds__(kThreads) void setup_pass_kernel(const float* __res
     part[blk * L + t] = v;
   }
   for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if (t < off) sm[t] = max(sm[t], sm[t + off]);
+    if (t < off) {
+      sm[t] = max(sm[t], sm[t + off]);
+      sf[t] = max(sf[t], sf[t + off]);
+    }
     __syncthreads();
   }
-  if (t == 0) amax[blk] = sm[0];
+  if (t == 0) {
+    amax[blk] = sm[0];
+    amax[gridDim.x + blk] = sf[0];
+  }
 }
 
 // setup_final_kernel, one block per dimension d: c0[d] as colsum_final_kernel
@@ -300,15 +313,16 @@ int launch_decide(const double* dpart, int64_t nparts, DevState* st, double* Dtr
 void plan_centroid(Carver& c, int64_t M, int64_t L, CentroidWs* ws) {
   ws->nwg = std::min<int64_t>(1024, std::max<int64_t>(1, (M + 255) / 256));
   ws->part = c.take<double>((size_t)(ws->nwg * L));
-  ws->amax = c.take<uint32_t>((size_t)ws->nwg);
+  ws->amax = c.take<uint32_t>((size_t)(2 * ws->nwg));
 }
 
 int launch_setup(const float* X, int64_t M, int64_t L, float* c0, float* C2, int mode,
                  double eps, double delta, const CentroidWs& ws, int* shift,
-                 const DevState& init, DevState* st, unsigned long long* nfb, hipStream_t s) {
+                 unsigned long long* lo, int64_t nlo, const DevState& init, DevState* st,
+                 unsigned long long* nfb, hipStream_t s) {
   const int64_t rpb = (M + ws.nwg - 1) / ws.nwg;
   hipLaunchKernelGGL(setup_pass_kernel, dim3((unsigned)ws.nwg), dim3(kThreads), 0, s, X, M,
-                     (int)L, rpb, ws.part, ws.amax);
+                     (int)L, rpb, ws.part, ws.amax, lo, nlo);
   LBG_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(setup_final_kernel, dim3((unsigned)L), dim3(kThreads), 0, s, ws.part,
                      ws.nwg, (int)L, M, c0, C2, mode, eps, delta, ws.amax, (int)ws.nwg, shift,

@@ -233,7 +233,7 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
   memcpy(pin, &hs, sizeof(hs));
   if (fused_setup) {
     LBG_TRY(launch_setup(X, M, L, w.Cb[0], w.Cb[1], p->split_mode, p->eps_split, p->delta, w.ce,
-                         w.up.afp.shift, hs, w.st, w.as.nfb, s));
+                         w.up.afp.shift, w.up.afp.lo, w.up.afp.nlo, hs, w.st, w.as.nfb, s));
   } else {
     LBG_TRY_HIP(hipMemcpyAsync(w.st, pin, sizeof(DevState), hipMemcpyHostToDevice, s));
     LBG_TRY_HIP(hipMemsetAsync(w.as.nfb, 0, sizeof(unsigned long long), s));
@@ -406,6 +406,9 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
     LBG_TRY_HIP(hipStreamSynchronize(s));
   }
   *D_out = pin->D;
+  if (pin->status == LBG_EINVAL)
+    set_error("the distortion is not finite: the training set or the starting codebook holds "
+              "a NaN or infinite value");
   return pin->status;
 }
 

@@ -10,19 +10,26 @@
 // accumulation uses) cannot change the result: the update is deterministic.
 // For data whose coordinates are multiples of 2^-s (for instance integer
 // pixels) the sums are the exact sums and the centroid is the exact mean
-// rounded once to FP64 and once to FP32.  Otherwise each coordinate is
-// rounded to a multiple of 2^-s first (relative error below 2^-(s+e+1) of
-// the largest |x|: 2^-52 for small M, 2^-(63-b) beyond M = 2^11).
+// rounded once to FP64 and once to FP32.  Otherwise every coordinate also
+// contributes a second word, the rounding residual x 2^s - round(x 2^s)
+// scaled by 2^t (t = min(52, 63 - b)) and rounded, added (when nonzero) by
+// 64-bit integer atomics into an N x L array in global memory; the sums are
+// then exact for coordinates down to 2^-(s+t), about 2^-80 of the largest
+// |x| at M = 2^22, so a cell of values far below the largest coordinate
+// keeps its precision.
 //
-//   absmax    per block: largest |x| (as float bits; max is order-free)
-//   shift     one block: s from the block maxima
+//   absmax    per block: largest |x| (as float bits; max is order-free) and
+//             the largest fine bits (the finest binary digit any coordinate
+//             needs); the blocks also clear the second-word array
+//   shift     one block: s and t from the block maxima
 //   acc       one block per (row chunk, cell slice): LDS int64 sums and
 //             counts for the cells of its slice over the rows of its chunk;
 //             dense partials per chunk
 //   fin       one block per cell: partials of all chunks added (integers),
 //             centroid = sum * 2^-s / count (FP64, rounded to FP32); an empty
 //             cell keeps its codevector.  For the gradient, (count * c_k - sum)
-//             is formed in integers before the single rounding.
+//             is formed in integers before the single rounding.  The cell's
+//             second words join in FP64 and are cleared for the next update.
 
 #include "afp_common.h"
 
@@ -32,8 +39,10 @@ namespace {
 using namespace afp;
 
 __global__ __launch_bounds__(kT) void absmax_kernel(const float* __restrict__ X, int64_t n,
-                                                     uint32_t* __restrict__ part) {
-  absmax_body(X, n, part, blockIdx.x, gridDim.x);
+                                                     uint32_t* __restrict__ part,
+                                                     unsigned long long* __restrict__ lo,
+                                                     int64_t nlo) {
+  absmax_body(X, n, part, blockIdx.x, gridDim.x, lo, nlo);
 }
 
 __global__ __launch_bounds__(kT) void shift_kernel(const uint32_t* __restrict__ part, int nparts,
@@ -48,7 +57,8 @@ template <int G, int VW, int DPL, bool SEL>
 __global__ __launch_bounds__(SEL ? kT : 1024) void acc_kernel(
     const float* __restrict__ X, int64_t M, int L, const int32_t* __restrict__ idx, int N,
     int cps, int nslices, int64_t rows_per_chunk, const int* __restrict__ shift_p,
-    unsigned long long* __restrict__ part, int32_t* __restrict__ pcnt, Ctl ctl) {
+    unsigned long long* __restrict__ part, int32_t* __restrict__ pcnt,
+    unsigned long long* __restrict__ lo, Ctl ctl) {
   extern __shared__ unsigned long long sacc[];
   __shared__ int32_t slist[SEL ? kSel : 1];
   __shared__ int32_t snsel;
@@ -60,9 +70,15 @@ __global__ __launch_bounds__(SEL ? kT : 1024) void acc_kernel(
     if (blockIdx.x == 0) (void)acc_decide(ctl, true, &N);
     N = ctl.st->n;
   }
-  acc_body<G, VW, DPL, SEL, kUnrollSel, SEL ? kT : 1024>(X, M, L, idx, N, ns, cps, nslices,
-                                                         rows_per_chunk, *shift_p, part, pcnt,
-                                                         blockIdx.x, sacc, slist, snsel);
+  const int s = shift_p[0], tf = shift_p[1];
+  if (tf > 0)  // data off the 2^-s grid: second words
+    acc_body<G, VW, DPL, SEL, kUnrollSel, SEL ? kT : 1024, true>(
+        X, M, L, idx, N, ns, cps, nslices, rows_per_chunk, s, part, pcnt, blockIdx.x, sacc,
+        slist, snsel, lo, tf);
+  else
+    acc_body<G, VW, DPL, SEL, kUnrollSel, SEL ? kT : 1024>(X, M, L, idx, N, ns, cps, nslices,
+                                                           rows_per_chunk, s, part, pcnt,
+                                                           blockIdx.x, sacc, slist, snsel);
 }
 
 // One block per cell.
@@ -70,27 +86,30 @@ template <int MODE>
 __global__ __launch_bounds__(kT) void fin_kernel(
     const unsigned long long* __restrict__ part, const int32_t* __restrict__ pcnt, int nchunks,
     int N, int L, const int* __restrict__ shift_p, const float* __restrict__ C_old,
-    float* __restrict__ out, int32_t* __restrict__ counts, double g2, Ctl ctl, CbPair cbp) {
+    float* __restrict__ out, int32_t* __restrict__ counts, double g2,
+    unsigned long long* __restrict__ lo, Ctl ctl, CbPair cbp) {
   const int k = blockIdx.x;
-  const int s = *shift_p;
-  fin_body<MODE>(part, pcnt, nchunks, N, L, s, counts, g2, k,
-                 [&](const float** c_old, float** dst) {
-                   *c_old = C_old;
-                   *dst = out;
-                   return !ctl.st || fin_state(ctl, cbp, k, k == 0, L, &N, c_old, dst);
-                 });
+  const int s = shift_p[0];
+  fin_body<MODE>(
+      part, pcnt, nchunks, N, L, s, counts, g2, k,
+      [&](const float** c_old, float** dst) {
+        *c_old = C_old;
+        *dst = out;
+        return !ctl.st || fin_state(ctl, cbp, k, k == 0, L, &N, c_old, dst);
+      },
+      lo, shift_p[1]);
 }
 
 template <int G, int VW, int DPL>
 void launch_acc(dim3 grid, size_t lds, hipStream_t st, const float* X, int64_t M, int L,
                 const int32_t* idx, int N, int cps, int nslices, int64_t rpc, const int* sp,
-                unsigned long long* part, int32_t* pcnt, Ctl ctl) {
+                unsigned long long* part, int32_t* pcnt, unsigned long long* lo, Ctl ctl) {
   if (nslices > 1)
     hipLaunchKernelGGL((acc_kernel<G, VW, DPL, true>), grid, dim3(kT), lds, st, X, M, L, idx, N,
-                       cps, nslices, rpc, sp, part, pcnt, ctl);
+                       cps, nslices, rpc, sp, part, pcnt, lo, ctl);
   else
     hipLaunchKernelGGL((acc_kernel<G, VW, DPL, false>), grid, dim3(1024), lds, st, X, M, L, idx,
-                       N, cps, nslices, rpc, sp, part, pcnt, ctl);
+                       N, cps, nslices, rpc, sp, part, pcnt, lo, ctl);
 }
 
 }  // namespace
@@ -109,8 +128,10 @@ void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w) {
   w->absmax_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (M * L + 4095) / 4096));
   w->part = c.take<unsigned long long>((size_t)(nch * N * L));
   w->pcnt = c.take<int32_t>((size_t)(nch * N));
-  w->amax = c.take<uint32_t>((size_t)w->absmax_blocks);
-  w->shift = c.take<int>(1);
+  w->amax = c.take<uint32_t>((size_t)(2 * w->absmax_blocks));
+  w->shift = c.take<int>(2);
+  w->lo = c.take<unsigned long long>((size_t)(N * L));
+  w->nlo = N * L;
 }
 
 bool afp_usable(int64_t L, int64_t N) {
@@ -120,7 +141,7 @@ bool afp_usable(int64_t L, int64_t N) {
 
 int launch_afp_shift(const float* X, int64_t M, int64_t L, const AfpWs& w, hipStream_t s) {
   hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)w.absmax_blocks), dim3(kT), 0, s, X, M * L,
-                     w.amax);
+                     w.amax, w.lo, w.nlo);
   LBG_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(shift_kernel, dim3(1), dim3(kT), 0, s, w.amax, w.absmax_blocks, M, w.shift);
   LBG_TRY_HIP(hipGetLastError());
@@ -148,7 +169,7 @@ int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const f
 #define LBG_ACC(GG, VV, DD)                                                                     \
   if (G == GG && VW == VV && DPL == DD) {                                                       \
     launch_acc<GG, VV, DD>(grid, lds, s, X, M, Li, idx, n, w.cps, w.nslices, w.rows_per_chunk, \
-                           w.shift, w.part, w.pcnt, ctl);                                       \
+                           w.shift, w.part, w.pcnt, w.lo, ctl);                                 \
   } else
   LBG_ACC(1, 4, 1) LBG_ACC(2, 4, 1) LBG_ACC(4, 4, 1) LBG_ACC(8, 4, 1) LBG_ACC(16, 4, 1)
   LBG_ACC(32, 4, 1) LBG_ACC(64, 4, 1)
@@ -162,10 +183,10 @@ int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const f
   LBG_TRY_HIP(hipGetLastError());
   if (mode == 0)
     hipLaunchKernelGGL(fin_kernel<0>, dim3((unsigned)N), dim3(kT), 0, s, w.part, w.pcnt,
-                       w.nchunks, n, Li, w.shift, C_old, C_out, counts, g2, ctl, cbp);
+                       w.nchunks, n, Li, w.shift, C_old, C_out, counts, g2, w.lo, ctl, cbp);
   else
     hipLaunchKernelGGL(fin_kernel<1>, dim3((unsigned)N), dim3(kT), 0, s, w.part, w.pcnt,
-                       w.nchunks, n, Li, w.shift, C_old, C_out, counts, g2, ctl, cbp);
+                       w.nchunks, n, Li, w.shift, C_old, C_out, counts, g2, w.lo, ctl, cbp);
   LBG_TRY_HIP(hipGetLastError());
   return LBG_OK;
 }
