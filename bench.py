@@ -34,11 +34,14 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# Sources of the allocation kernel: counters taken on an older build of them
+# Sources of the allocation kernels: counters taken on an older build of them
 # are not reported.
-ASSIGN_SOURCES = ("paper_0910_4711_amd/csrc/assign_common.h",
-                  "paper_0910_4711_amd/csrc/assign.hip")
-TRAFFIC_FILE = "profiles/assign_fp32_img16x512x512_b4_traffic.txt"
+BF16_SOURCES = ("paper_0910_4711_amd/csrc/assign_common.h",
+                "paper_0910_4711_amd/csrc/assign_bf16.hip")
+FP32_SOURCES = ("paper_0910_4711_amd/csrc/assign_common.h",
+                "paper_0910_4711_amd/csrc/assign.hip")
+TRAFFIC_FILE_BF16 = "profiles/assign_bf16_img256x1024x1024_b8_N1024_traffic.txt"
+TRAFFIC_FILE_FP32 = "profiles/assign_fp32_img256x1024x1024_b8_N1024_traffic.txt"
 
 
 def log(*a):
@@ -52,21 +55,21 @@ def workload():
     return cfg, X
 
 
-def assign_source_hash():
+def source_hash(sources):
     import hashlib
     h = hashlib.sha256()
-    for f in ASSIGN_SOURCES:
+    for f in sources:
         with open(os.path.join(HERE, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(traffic_file, sources):
     """HBM bytes per allocation launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
     reading for a plain copy of known size), or None when the summary is
     missing or was taken on other kernel sources."""
-    path = os.path.join(HERE, TRAFFIC_FILE)
+    path = os.path.join(HERE, traffic_file)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -75,7 +78,7 @@ def measured_traffic():
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != assign_source_hash():
+    if kv.get("source_sha256") != source_hash(sources):
         return None
     try:
         return dict(bytes=float(kv["traffic_bytes_per_launch"]),
@@ -461,89 +464,116 @@ def form_codec(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(X, N, images):
-    """The FP64 oracle, as it stands, on the first ``images`` pictures' rows
-    with all host cores; distances/s of the full LBG run."""
+def lscpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_precision(X, C0, iters):
+    """The FP64 oracle, as it stands, on the 65,536-row subsample of the
+    precision workload (rows from default_rng(1001), without replacement):
+    the same 1,024 starting codevectors and the same number of Lloyd
+    iterations, on all host cores and on one thread (the paper's sequential
+    baseline).  Distances/s = rows * N * allocations / wall time."""
     import oracle
-    rows_per_image = X.shape[0] // 16
-    S = X[: images * rows_per_image]
-    cores = len(os.sched_getaffinity(0))
     oracle.load()
-    t0 = time.perf_counter()
-    r = oracle.train(S, N, nthreads=cores)
-    t = time.perf_counter() - t0
-    dist = int(S.shape[0]) * int(sum(int(n) * (int(i) + 1)
-                                     for n, i in zip(r["level_n"], r["level_iters"])))
-    return dict(value=dist / t, unit="distances/s", cores=cores, kind="oracle",
-                sample=f"full LBG to N={N} on the first {images} of 16 images "
-                       f"(M={S.shape[0]}, L={S.shape[1]}), FP64, {t:.2f} s")
+    rows = np.random.default_rng(1001).choice(X.shape[0], min(X.shape[0], 65536), replace=False)
+    rows.sort()
+    S = np.ascontiguousarray(X[rows])
+    N = C0.shape[0]
+    cores = len(os.sched_getaffinity(0))
+    out = {}
+    for name, nt in (("all_cores", cores), ("one_thread", 1)):
+        t0 = time.perf_counter()
+        oracle.train(S, N, C_init=C0.astype(np.float64), fixed_iters=iters, nthreads=nt)
+        t = time.perf_counter() - t0
+        out[name] = dict(value=S.shape[0] * N * (iters + 1) / t, threads=nt, seconds=t)
+    return dict(value=out["all_cores"]["value"], unit="distances/s", cores=cores,
+                kind="oracle", cpu_model=lscpu_model(),
+                one_thread=out["one_thread"],
+                speedup_all_cores_vs_one_thread=out["one_thread"]["seconds"]
+                / out["all_cores"]["seconds"],
+                sample=f"{iters} Lloyd iterations ({iters + 1} allocations) from the same "
+                       f"{N} starting codevectors on the {S.shape[0]}-row subsample "
+                       f"(default_rng(1001)) of the M = {X.shape[0]} workload, FP64; "
+                       f"{out['all_cores']['seconds']:.2f} s on {cores} threads, "
+                       f"{out['one_thread']['seconds']:.2f} s on one thread")
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-images", type=int, default=16,
-                    help="images of the workload the CPU oracle baseline runs on")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--event-steps", type=int, default=1,
-                    help="timed steps that record HIP events around every kernel")
-    ap.add_argument("--copy-calibration", type=int, metavar="MIB", default=0,
-                    help="only run a plain device copy of MIB MiB (counter calibration)")
-    ap.add_argument("--form", choices=["batched", "precision", "differentiation", "codec"],
-                    default=None, help="benchmark one of the forms instead of the main workload")
-    ap.add_argument("--images", type=int, default=0,
-                    help="images of --form precision (default: all 256)")
-    ap.add_argument("--instances", type=int, default=512, help="instances of --form batched")
-    ap.add_argument("--scale", type=float, default=1.0, help="row-count scale of --form batched")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
-        return
-    if args.form:
-        if args.gpus != 1:
-            sys.exit("bench.py: the forms run on one GPU")
-        {"batched": form_batched, "precision": form_precision,
-         "differentiation": form_differentiation, "codec": form_codec}[args.form](args)
-        return
-    if args.gpus != 1:
-        print(f"bench.py: this benchmark runs on exactly one GPU; --gpus {args.gpus} "
-              "is not supported (the library has no multi-GPU path)", file=sys.stderr)
-        sys.exit(2)
+def paper_experiment(cores):
+    """The paper's own experiment (Sec. 5, Figs. 3 and 4), shape only, on the
+    FP64 oracle: full LBG runs on 2,000 synthetic training vectors (a
+    16-component Gaussian mixture) of dimension k; wall time against the
+    codebook size N = 8..128 sequentially and on 4 threads, and against the
+    thread count at N = 128.  Only the allocation loop of the oracle runs on
+    several threads (static chunks of vectors, as Algorithm 1 hands them
+    out).  Each time is the median of three runs."""
+    import oracle
+    import synth
 
+    def timed(X, N, nt):
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.train(X, N, nthreads=nt)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    fig3 = []
+    for k in (2, 10):
+        X = synth.gmm(40_000 + k, 2000, k, 16)
+        for N in (8, 16, 32, 64, 128):
+            t1, t4 = timed(X, N, 1), timed(X, N, 4)
+            fig3.append({"k": k, "N": N, "seconds_1_thread": t1, "seconds_4_threads": t4,
+                         "speedup_4": t1 / t4})
+    X = synth.gmm(40_010, 2000, 10, 16)
+    fig4 = []
+    t1 = None
+    for nt in sorted({1, 2, 4, 8, cores}):
+        if nt > cores:
+            continue
+        t = timed(X, 128, nt)
+        t1 = t if nt == 1 else t1
+        fig4.append({"threads": nt, "seconds": t, "speedup": t1 / t})
+    return {"what": "paper Sec. 5 experiment on the FP64 oracle (shape only; the paper's "
+                    "data and figure values are not given): M = 2000 synthetic vectors",
+            "time_vs_codebook_size": fig3, "time_vs_threads_N128_k10": fig4}
+
+
+PAPER_CONTEXT = {
+    "source": "paper Sec. 4 (profiling) and Sec. 5; hardware unstated, no absolute timings",
+    "share_of_sequential_time_in_allocation": "70-75%",
+    "share_of_sequential_time_in_update": "10-15%",
+    "amdahl_speedup_4_threads_serial_fraction_0.15": 2.76,
+}
+
+
+def run_lbg_steps(P, Xd, N, steps, warmup, stream, event_steps=1, **kw):
+    """Warm-up, then ``steps`` timed lbg_train calls (the first
+    ``event_steps`` of them with an event pair around every allocation and
+    update).  Returns (wall seconds of the timed steps, totals, event sums,
+    last stats, last result)."""
     import torch
-    import paper_0910_4711_amd as P
-
-    cfg, X = workload()
-    M, L = X.shape
-    N = cfg["N"]
-    dev = torch.device("cuda:0")
-    Xd = torch.from_numpy(X).to(dev)
-    ws = torch.empty(P.load().lbg_workspace_size(P.OP_TRAIN, M, L, N, P.FP32),
-                     dtype=torch.uint8, device=dev)
-    log(f"workload {cfg['name']}: M={M} L={L} N={N}; device {torch.cuda.get_device_name(dev)}")
-
-    # A dedicated (default-priority) stream: the library replays its Lloyd
-    # iterations as hipGraphs on non-default streams.
-    stream = torch.cuda.Stream(device=dev)
-    torch.cuda.synchronize(dev)
-    for i in range(args.warmup):
+    for _ in range(warmup):
         with torch.cuda.stream(stream):
-            P.train(Xd, N, workspace=ws, timing=True)
+            P.train(Xd, N, timing=True, **kw)
         stream.synchronize()
-        log(f"warmup step {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize(dev)
+    torch.cuda.synchronize()
     tot = dict(dist=0, assigns=0, updates=0, fallback=0)
-    # the event-timed steps' kernel durations and the work they cover
-    ev = dict(steps=0, dist=0, ms_assign=0.0, ms_update=0.0, ms_split=0.0, assigns=0, updates=0)
-    n_ev = max(1, min(args.event_steps, args.steps))
+    ev = dict(steps=0, dist=0, ms_assign=0.0, ms_update=0.0, assigns=0, updates=0)
+    n_ev = max(1, min(event_steps, steps))
     last = None
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         timed = i < n_ev
         with torch.cuda.stream(stream):
-            C, idx, D, st = P.train(Xd, N, workspace=ws, timing=timed)
+            C, idx, D, st = P.train(Xd, N, timing=timed, **kw)
         tot["dist"] += st["total_distances"]
         tot["assigns"] += st["total_assigns"]
         tot["updates"] += st["total_updates"]
@@ -553,81 +583,261 @@ def main():
             ev["dist"] += st["total_distances"]
             ev["assigns"] += st["total_assigns"]
             ev["updates"] += st["total_updates"]
-            for k in ("ms_assign", "ms_update", "ms_split"):
-                ev[k] += st[k]
-        last = (D, st)
-    torch.cuda.synchronize(dev)
-    elapsed = time.perf_counter() - t0
-    log(f"timed {args.steps} steps in {elapsed:.4f} s")
+            ev["ms_assign"] += st["ms_assign"]
+            ev["ms_update"] += st["ms_update"]
+        last = (C, idx, D, st)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, tot, ev, last
 
-    D, st = last
-    traffic = measured_traffic()
-    flops = 2.0 * L * ev["dist"]  # 2L flops per vector-codeword distance
-    assign_s = ev["ms_assign"] / 1e3
-    achieved_tf = flops / assign_s / 1e12
-    upd_bytes = ev["updates"] * M * (4 * L + 4)  # X rows + cell index per update
-    upd_gbs = upd_bytes / (ev["ms_update"] / 1e3) / 1e9 if ev["ms_update"] > 0 else None
 
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline form (no exact-form, 16-picture or error legs)")
+    ap.add_argument("--event-steps", type=int, default=1,
+                    help="timed steps that record HIP events around every kernel")
+    ap.add_argument("--copy-calibration", type=int, metavar="MIB", default=0,
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--form", choices=["batched", "precision", "differentiation", "codec",
+                                       "config1"],
+                    default=None, help="benchmark one of the forms instead of the main workload")
+    ap.add_argument("--precision", choices=["bf16", "fp32"], default=None,
+                    help="only this precision form of the main workload (profiling runs)")
+    ap.add_argument("--images", type=int, default=0,
+                    help="images of the main / precision workload (default: all 256)")
+    ap.add_argument("--instances", type=int, default=512, help="instances of --form batched")
+    ap.add_argument("--scale", type=float, default=1.0, help="row-count scale of --form batched")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.gpus != 1:
+        print(f"bench.py: this benchmark runs on exactly one GPU; --gpus {args.gpus} "
+              "is not supported (the library has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    if args.form:
+        {"batched": form_batched, "precision": form_precision,
+         "differentiation": form_differentiation, "codec": form_codec,
+         "config1": form_config1}[args.form](args)
+        return
+
+    import torch
+    import synth
+    import paper_0910_4711_amd as P
+
+    cfg = synth.CONFIG2
+    n_img = args.images if args.images else len(cfg["seeds"])
+    t0 = time.perf_counter()
+    X = _image_set_parallel(tuple(range(n_img)), cfg["W"], cfg["H"], cfg["b"])
+    M, L = X.shape
+    N = cfg["N"]
+    iters = 10
+    C0 = np.ascontiguousarray(X[synth.distinct_rows(X, N, 1000)])
+    log(f"generated M={M} L={L} in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    C0d = torch.from_numpy(C0).to(dev)
+    lib = P.load()
+    ws = torch.empty(max(lib.lbg_workspace_size(P.OP_TRAIN, M, L, N, prec) for prec in
+                         (P.FP32, P.BF16_RESCORE)), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    log(f"workload {cfg['name']}: M={M} L={L} N={N}, {iters} Lloyd iterations per step; "
+        f"device {torch.cuda.get_device_name(dev)}")
+
+    forms = {}
+    want = [args.precision] if args.precision else ["bf16", "fp32"]
+    if args.no_extras and not args.precision:
+        want = ["bf16"]
+    for name in want:
+        prec = P.BF16_RESCORE if name == "bf16" else P.FP32
+        el, tot, ev, last = run_lbg_steps(P, Xd, N, args.steps, args.warmup, stream,
+                                          args.event_steps, C_init=C0d, fixed_iters=iters,
+                                          precision=prec, workspace=ws)
+        log(f"{name}: timed {args.steps} steps in {el:.4f} s")
+        forms[name] = (el, tot, ev, last)
+
+    def roofline(name):
+        el, tot, ev, last = forms[name]
+        flops = 2.0 * L * ev["dist"]  # 2L flops per vector-codeword distance
+        a_s = ev["ms_assign"] / 1e3
+        ach = flops / a_s / 1e12
+        upd_bytes = ev["updates"] * M * (4 * L + 4)
+        upd_gbs = upd_bytes / (ev["ms_update"] / 1e3) / 1e9 if ev["ms_update"] > 0 else None
+        if name == "bf16":
+            kern = "assign_kernel<Bf16Screen<64>, vector loads, 8 waves> (BF16 screen + FP64 top-2 rescore)"
+            peak, basis = PEAK_BF16_MFMA_TFLOPS, "BF16 dense MFMA peak, 2L flops per distance"
+            tr = measured_traffic(TRAFFIC_FILE_BF16, BF16_SOURCES)
+        else:
+            kern = "assign_kernel<Bf16x3Screen<64>, vector loads, 8 waves> (exact)"
+            peak, basis = PEAK_BF16_MFMA_TFLOPS, ("BF16 dense MFMA peak (the exact screen "
+                                                  "contracts BF16 parts), 2L flops per distance")
+            tr = measured_traffic(TRAFFIC_FILE_FP32, FP32_SOURCES)
+        r = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+             "frac": ach / peak,
+             "traffic": tr["bytes"] if tr else None,
+             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                             "copy-calibrated)",
+             "algorithmic_bytes_per_launch": M * (4 * L + 4) + N * L * 4,
+             "kernel": kern, "peak_basis": basis,
+             "frac_of_fp32_mfma_peak": ach / PEAK_FP32_MFMA_TFLOPS,
+             "launches": ev["assigns"], "event_steps": ev["steps"],
+             "avg_launch_us": ev["ms_assign"] / ev["assigns"] * 1e3,
+             "flops_per_launch": flops / ev["assigns"]}
+        u = {"bound": "hbm", "achieved_gbs": upd_gbs, "peak_gbs": PEAK_HBM_GBS,
+             "frac": (upd_gbs / PEAK_HBM_GBS) if upd_gbs else None,
+             "avg_update_us": ev["ms_update"] / max(1, ev["updates"]) * 1e3,
+             "algorithmic_bytes_per_update": M * (4 * L + 4)}
+        return r, u
+
+    head = "bf16" if "bf16" in forms else "fp32"
+    el, tot, ev, last = forms[head]
+    rl, upd = roofline(head)
     out = {
-        "metric": "LBG iteration vector-codeword distances/s",
-        "value": tot["dist"] / elapsed,
+        "metric": "LBG iteration vector-codeword distances/s (BF16 screen + FP64 top-2 "
+                  "rescore; exact FP32-accurate form and its ratio beside it)",
+        "value": tot["dist"] / el,
         "unit": "distances/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": el / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if head == "bf16" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": cfg["name"],
-            "M": M, "L": L, "N": N, "thr": 1e-3, "eps_split": 0.01,
-            "images": len(cfg["seeds"]), "image_size": [cfg["H"], cfg["W"]], "block": cfg["b"],
-            "precision": "fp32 (exact allocation)",
+            "workload": f"img{n_img}x1024x1024_b8_M{M}_L{L}_N{N}_10iters",
+            "M": M, "L": L, "N": N, "images": n_img, "image_size": [1024, 1024], "block": 8,
+            "init": "1024 distinct training vectors, default_rng(1000) permutation",
+            "lloyd_iterations_per_step": iters,
+            "precision": ("BF16 distances with FP32 accumulation, top-2 rescored in FP64"
+                          if head == "bf16" else "exact (FP32-accurate screen, FP64 certificate)"),
         },
-        "roofline": {
-            "bound": "mfma",
-            "achieved": achieved_tf,
-            "peak": PEAK_FP32_MFMA_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tf / PEAK_FP32_MFMA_TFLOPS,
-            "traffic": traffic["bytes"] if traffic else None,
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                            "copy-calibrated)",
-            "kernel": "allocation: assign_kernel<Bf16x3Screen<16>, vector loads>",
-            "peak_basis": "FP32 MFMA peak for the 2L FP32 flops per distance the allocation "
-                          "must resolve; the kernel screens with BF16 hi/mid/lo parts "
-                          "(7 v_mfma_f32_32x32x16_bf16 per 32x32 tile at L = 16) and "
-                          "searches codebooks of n <= 8 directly in FP64",
-            "launches": ev["assigns"],
-            "event_steps": ev["steps"],
-            "avg_launch_us": ev["ms_assign"] / ev["assigns"] * 1e3,
-            "flops_per_launch_avg": flops / ev["assigns"],
-        },
-        "update": {
-            "bound": "hbm",
-            "achieved_gbs": upd_gbs,
-            "peak_gbs": PEAK_HBM_GBS,
-            "frac": (upd_gbs / PEAK_HBM_GBS) if upd_gbs else None,
-            "avg_update_us": ev["ms_update"] / max(1, ev["updates"]) * 1e3,
-        },
-        "per_step": {
-            "assigns": tot["assigns"] // args.steps,
-            "updates": tot["updates"] // args.steps,
-            "ms_assign": ev["ms_assign"] / ev["steps"],
-            "ms_update": ev["ms_update"] / ev["steps"],
-            "ms_split": ev["ms_split"] / ev["steps"],
-            "fallback_rows": tot["fallback"] // args.steps,
-            "level_iters": st["level_iters"],
-            "D": D,
-        },
+        "roofline": rl,
+        "update": upd,
+        "per_step": {"assigns": tot["assigns"] // args.steps,
+                     "updates": tot["updates"] // args.steps,
+                     "ms_assign": ev["ms_assign"] / ev["steps"],
+                     "ms_update": ev["ms_update"] / ev["steps"],
+                     "D": last[2]},
+        "paper_context": PAPER_CONTEXT,
     }
+    if "fp32" in forms and head != "fp32":
+        el2, tot2, ev2, last2 = forms["fp32"]
+        rl2, upd2 = roofline("fp32")
+        out["fp32_exact"] = {"value": tot2["dist"] / el2, "ms_per_step": el2 / args.steps * 1e3,
+                             "roofline": rl2, "update": upd2,
+                             "fallback_rows_per_step": tot2["fallback"] // args.steps,
+                             "D": last2[2]}
+        out["speedup_vs_fp32_exact"] = (tot["dist"] / el) / (tot2["dist"] / el2)
+        out["bf16_errors"] = bf16_errors(P, X, Xd, last2[0], last[0], last[2], last2[2])
+    if not args.no_extras and not args.precision:
+        out["config1"] = config1_line(P, max(3, args.steps // 2), 2, stream)
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(X, N, args.cpu_images)
+        out["cpu_baseline"] = cpu_baseline_precision(X, C0, iters)
         log(f"cpu baseline done: {out['cpu_baseline']['sample']}")
+        if not args.no_extras:
+            out["cpu_baseline"]["paper_experiment"] = paper_experiment(
+                out["cpu_baseline"]["cores"])
+    print(json.dumps(out), flush=True)
+
+
+def bf16_errors(P, X, Xd, C_exact, C_bf16, D_bf16, D_exact):
+    """Errors of the BF16 form: per step (the exact run's final codebook into
+    one BF16 and one exact allocation + update; allocations against the FP64
+    oracle on the 65,536-row subsample) and after the 10 iterations."""
+    import torch
+    import oracle
+    M = X.shape[0]
+    idx_b, _ = P.assign(Xd, C_exact, P.BF16_RESCORE)
+    idx_f, _ = P.assign(Xd, C_exact, P.FP32)
+    Cb1, _ = P.update(Xd, idx_b, C_exact)
+    Cf1, _ = P.update(Xd, idx_f, C_exact)
+    D_b = float(P.distortion(Xd, C_exact, idx_b).item())
+    D_f = float(P.distortion(Xd, C_exact, idx_f).item())
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(1001).choice(M, min(M, 65536), replace=False)
+    rows.sort()
+    Ch = C_exact.cpu().numpy().astype(np.float64)
+    idx_o, d1, d2 = oracle.assign(X[rows], Ch)
+    ib = idx_b.cpu().numpy()[rows]
+    xx = (X[rows].astype(np.float64) ** 2).sum(1)
+    wrong = ib != idx_o
+    near = (d2 - d1) < 1e-6 * xx
+
+    def rel_rows(A, B):
+        A = A.cpu().numpy().astype(np.float64)
+        B = B.cpu().numpy().astype(np.float64)
+        return np.linalg.norm(A - B, axis=1) / np.maximum(np.linalg.norm(B, axis=1), 1e-30)
+
+    r1 = rel_rows(Cb1, Cf1)
+    r10 = rel_rows(C_bf16, C_exact)
+    return {
+        "per_step": {
+            "subsample_rows": int(rows.size),
+            "assign_mismatch_rate_vs_fp64_oracle": float(wrong.mean()),
+            "assign_mismatch_outside_tie_band": int((wrong & ~near).sum()),
+            "codebook_rel_vs_exact_update_max": float(r1.max()),
+            "codebook_rel_vs_exact_update_median": float(np.median(r1)),
+            "D_rel_vs_exact": abs(D_b - D_f) / D_f,
+        },
+        "after_10_iterations": {
+            "codebook_rel_vs_exact_run_max": float(r10.max()),
+            "codebook_rel_vs_exact_run_median": float(np.median(r10)),
+            "D_rel_vs_exact_run": abs(D_bf16 - D_exact) / D_exact,
+        },
+    }
+
+
+def config1_line(P, steps, warmup, stream):
+    """Full LBG runs on the 16-picture workload (M = 262,144, L = 16, split
+    to N = 256, stop at relative change 1e-3), exact form."""
+    import torch
+    cfg, X = workload()
+    M, L = X.shape
+    N = cfg["N"]
+    Xd = torch.from_numpy(X).to("cuda:0")
+    el, tot, ev, last = run_lbg_steps(P, Xd, N, steps, warmup, stream, 1)
+    flops = 2.0 * L * ev["dist"]
+    ach = flops / (ev["ms_assign"] / 1e3) / 1e12
+    upd_bytes = ev["updates"] * M * (4 * L + 4)
+    return {"workload": cfg["name"], "value": tot["dist"] / el, "unit": "distances/s",
+            "steps": steps, "ms_per_step": el / steps * 1e3,
+            "assign_tflops": ach, "assign_frac_fp32_mfma_peak": ach / PEAK_FP32_MFMA_TFLOPS,
+            "assign_frac_bf16_mfma_peak": ach / PEAK_BF16_MFMA_TFLOPS,
+            "avg_assign_us": ev["ms_assign"] / ev["assigns"] * 1e3,
+            "avg_update_us": ev["ms_update"] / max(1, ev["updates"]) * 1e3,
+            "update_frac_hbm": upd_bytes / (ev["ms_update"] / 1e3) / 1e9 / PEAK_HBM_GBS,
+            "level_iters": last[3]["level_iters"], "D": last[2]}
+
+
+def form_config1(args):
+    """The 16-picture workload alone (full LBG runs): one JSON line, with the
+    oracle timed on the same runs."""
+    import torch
+    import oracle
+    import paper_0910_4711_amd as P
+    stream = torch.cuda.Stream(device="cuda:0")
+    out = config1_line(P, args.steps, args.warmup, stream)
+    if not args.no_cpu_baseline:
+        cfg, X = workload()
+        cores = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        r = oracle.train(X, cfg["N"], nthreads=cores)
+        t = time.perf_counter() - t0
+        dist = X.shape[0] * int(sum(int(n) * (int(i) + 1)
+                                    for n, i in zip(r["level_n"], r["level_iters"])))
+        out["cpu_baseline"] = dict(value=dist / t, unit="distances/s", cores=cores,
+                                   kind="oracle", cpu_model=lscpu_model(),
+                                   sample=f"full LBG to N={cfg['N']} on M={X.shape[0]}, "
+                                          f"FP64, {t:.2f} s")
     print(json.dumps(out), flush=True)
 
 

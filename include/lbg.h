@@ -260,6 +260,16 @@ typedef struct lbg_params {
   int32_t graph;               /* nonzero: replay batches of iterations as
                                   hipGraphs (non-NULL streams only); the
                                   default launches kernels directly */
+  /* Resume in the middle of a level (with C_init only): C_init is the
+   * codebook after it_init updates at its level and D_prev_init the
+   * distortion of the allocation before the last of them, so the first stop
+   * test compares against it (a run stopped there and resumed gives the
+   * uninterrupted run's results bit for bit).  Defaults +inf and 0: C_init
+   * starts a level. */
+  double D_prev_init;          /* >= 0 or +inf */
+  int32_t it_init;             /* >= 0 */
+  int32_t stats_ties;          /* nonzero (with st): count near-tie rows of
+                                  the final allocation (one extra FP64 pass) */
 } lbg_params;
 
 void lbg_params_default(lbg_params* p);
@@ -283,6 +293,14 @@ typedef struct lbg_stats {
   double ms_assign;
   double ms_update;
   double ms_split;
+  /* Codevectors of the returned codebook whose cell is empty in the final
+   * allocation (they kept their value through the last update). */
+  int32_t empty_cells;
+  /* With p->stats_ties: rows of the final allocation whose two nearest
+   * codevectors lie within 1e-6 |x|^2 of each other (FP64 direct form: the
+   * tie band in which another rounding of the codebook may change the
+   * allocation); -1 when not counted. */
+  int64_t near_tie_rows;
 } lbg_stats;
 
 /*

@@ -60,6 +60,9 @@ class Params(ct.Structure):
         ("N_init", ct.c_int64),
         ("timing", ct.c_int32),
         ("graph", ct.c_int32),
+        ("D_prev_init", ct.c_double),
+        ("it_init", ct.c_int32),
+        ("stats_ties", ct.c_int32),
     ]
 
 
@@ -78,6 +81,8 @@ class Stats(ct.Structure):
         ("ms_assign", ct.c_double),
         ("ms_update", ct.c_double),
         ("ms_split", ct.c_double),
+        ("empty_cells", ct.c_int32),
+        ("near_tie_rows", ct.c_int64),
     ]
 
 
@@ -427,9 +432,11 @@ def distortion_backward(X, C, idx, g=1.0, need_x=True, need_c=True):
 
 def train(X, N, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta=0.0,
           max_iter=1000, precision=FP32, fixed_iters=0, forced_iters=None,
-          C_init=None, D_cap=4096, workspace=None, timing=False, graph=False):
+          C_init=None, D_cap=4096, workspace=None, timing=False, graph=False,
+          D_prev_init=None, it_init=0, stats_ties=False):
     """LBG with splitting (Algorithm 1).  Returns (C, idx, D, stats) with C
-    [N x L] float32, idx [M] int32, D a Python float and stats a dict."""
+    [N x L] float32, idx [M] int32, D a Python float and stats a dict.
+    D_prev_init / it_init resume a level in its middle (with C_init)."""
     X = _f32_2d("X", X)
     M, L = X.shape
     lib = load()
@@ -440,6 +447,10 @@ def train(X, N, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta=0.0,
     p.precision, p.fixed_iters = _prec(precision), int(fixed_iters)
     p.timing = 1 if timing else 0
     p.graph = 1 if graph else 0
+    if D_prev_init is not None:
+        p.D_prev_init = float(D_prev_init)
+    p.it_init = int(it_init)
+    p.stats_ties = 1 if stats_ties else 0
     keep = []
     if forced_iters is not None:
         f = (ct.c_int32 * len(forced_iters))(*[int(v) for v in forced_iters])
@@ -478,6 +489,8 @@ def train(X, N, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta=0.0,
         ms_assign=st.ms_assign,
         ms_update=st.ms_update,
         ms_split=st.ms_split,
+        empty_cells=st.empty_cells,
+        near_tie_rows=st.near_tie_rows,
     )
     return C, idx, D.value, stats
 

@@ -30,7 +30,9 @@ __device__ __forceinline__ uint32_t fine_bits(uint32_t b) {
 }
 
 // Block maxima over X (n floats): part[block] = largest finite |x| (as
-// float bits), part[nblocks + block] = largest fine bits.  The blocks also
+// float bits), part[nblocks + block] = largest fine bits, part[2 nblocks +
+// block] = the OR of the coordinates' low 16 bits (zero: all exact in BF16).
+// The blocks also
 // clear the nlo words of ``lo`` (the residual sums of the update, see
 // fin_body), so that every accumulation starts from zero.
 __device__ __forceinline__ void absmax_body(const float* __restrict__ X, int64_t n,
@@ -39,10 +41,12 @@ __device__ __forceinline__ void absmax_body(const float* __restrict__ X, int64_t
                                             int64_t nlo) {
   __shared__ uint32_t s[kT];
   __shared__ uint32_t sf[kT];
+  __shared__ uint32_t sr[kT];
   typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-  uint32_t m = 0, f = 0;
-  auto upd = [&m, &f](uint32_t b) {
+  uint32_t m = 0, f = 0, r = 0;
+  auto upd = [&m, &f, &r](uint32_t b) {
     f = max(f, fine_bits(b));
+    r |= b & 0xffffu;  // nonzero: not exact in BF16
     b &= 0x7fffffffu;
     m = (b > m && b < 0x7f800000u) ? b : m;  // ignore Inf / NaN
   };
@@ -75,17 +79,20 @@ __device__ __forceinline__ void absmax_body(const float* __restrict__ X, int64_t
     upd(__float_as_uint(X[e]));
   s[threadIdx.x] = m;
   sf[threadIdx.x] = f;
+  sr[threadIdx.x] = r;
   __syncthreads();
   for (int off = kT / 2; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off) {
       s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + off]);
       sf[threadIdx.x] = max(sf[threadIdx.x], sf[threadIdx.x + off]);
+      sr[threadIdx.x] |= sr[threadIdx.x + off];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     part[block] = s[0];
     part[nblocks + block] = sf[0];
+    part[2 * nblocks + block] = sr[0];
   }
 }
 
@@ -98,23 +105,28 @@ __device__ __forceinline__ void absmax_body(const float* __restrict__ X, int64_t
 // x 2^s - round(x 2^s), at most 1/2, is then also summed, as round(residual
 // 2^t), so coordinates down to 2^-(s+t) count exactly and the update keeps
 // about 2^-(s+t) of max|x| (2^-80 of it at M = 2^22) where one word kept
-// 2^-s.
+// 2^-s; shift[2] = 1 when every coordinate is exact in BF16 (the
+// allocation's split screen then skips the products of vanishing parts).
 __device__ __forceinline__ void shift_body(const uint32_t* __restrict__ part, int nparts,
                                            int64_t M, int* __restrict__ shift) {
   __shared__ uint32_t s[kT];
   __shared__ uint32_t sf[kT];
-  uint32_t m = 0, f = 0;
+  __shared__ uint32_t sr[kT];
+  uint32_t m = 0, f = 0, r = 0;
   for (int i = threadIdx.x; i < nparts; i += kT) {
     m = max(m, part[i]);
     f = max(f, part[nparts + i]);
+    r |= part[2 * nparts + i];
   }
   s[threadIdx.x] = m;
   sf[threadIdx.x] = f;
+  sr[threadIdx.x] = r;
   __syncthreads();
   for (int off = kT / 2; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off) {
       s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + off]);
       sf[threadIdx.x] = max(sf[threadIdx.x], sf[threadIdx.x + off]);
+      sr[threadIdx.x] |= sr[threadIdx.x + off];
     }
     __syncthreads();
   }
@@ -127,6 +139,7 @@ __device__ __forceinline__ void shift_body(const uint32_t* __restrict__ part, in
     const int sh = (s[0] == 0) ? 0 : (min(51, 62 - b) - e);
     shift[0] = sh;
     shift[1] = (sf[0] != 0u && (int)sf[0] - 256 > sh) ? min(52, 63 - b) : 0;
+    shift[2] = sr[0] == 0u;
   }
 }
 

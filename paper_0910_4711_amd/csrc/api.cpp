@@ -97,6 +97,20 @@ void plan_train(Carver& c, int64_t M, int64_t L, int64_t N, int precision, Train
   w->pend = c.take<DevState>(1);
   w->Dtrace = c.take<double>((size_t)kTraceCap);
   w->Atrace = c.take<int32_t>((size_t)kTraceCap);
+  w->cellcnt = c.take<int32_t>((size_t)N);
+  w->runstat = c.take<unsigned long long>(2);
+}
+
+int run_stats(const float* X, int64_t M, int64_t L, int64_t N, const float* C,
+              const int32_t* idx, const lbg_params* p, lbg_stats* st, const TrainWs& w,
+              hipStream_t s) {
+  LBG_TRY(launch_run_stats(X, M, L, C, N, idx, p->stats_ties != 0, w.cellcnt, w.runstat, s));
+  unsigned long long h[2] = {0, 0};
+  LBG_TRY_HIP(hipMemcpyAsync(h, w.runstat, sizeof(h), hipMemcpyDeviceToHost, s));
+  LBG_TRY_HIP(hipStreamSynchronize(s));
+  st->empty_cells = (int32_t)h[0];
+  st->near_tie_rows = p->stats_ties ? (int64_t)h[1] : -1;
+  return LBG_OK;
 }
 
 namespace {
@@ -208,6 +222,9 @@ void lbg_params_default(lbg_params* p) {
   p->N_init = 0;
   p->timing = 0;
   p->graph = 0;
+  p->D_prev_init = INFINITY;
+  p->it_init = 0;
+  p->stats_ties = 0;
 }
 
 size_t lbg_workspace_size(int op, int64_t M, int64_t L, int64_t N, int precision) {
@@ -477,6 +494,14 @@ int lbg_train(const float* X, int64_t M, int64_t L, int64_t N, const lbg_params*
     }
     LBG_TRY(need(p->C_init, "C_init"));
   }
+  if (!(p->D_prev_init >= 0.0) || p->it_init < 0) {
+    set_error("D_prev_init must be >= 0 or +inf and it_init >= 0");
+    return LBG_EINVAL;
+  }
+  if (!p->C_init && (p->D_prev_init != INFINITY || p->it_init != 0)) {
+    set_error("D_prev_init and it_init resume a level from C_init: C_init is NULL");
+    return LBG_EINVAL;
+  }
   Carver c{reinterpret_cast<char*>(ws), 0};
   TrainWs w;
   plan_train(c, M, L, N, p->precision, &w);
@@ -513,7 +538,14 @@ int lbg_train(const float* X, int64_t M, int64_t L, int64_t N, const lbg_params*
     need_split = N > 1;
   }
 
-  if (w.up.use_afp) LBG_TRY(launch_afp_shift(X, M, L, w.up.afp, s));
+  int on_grid = 0;
+  if (w.up.use_afp) {
+    LBG_TRY(launch_afp_shift(X, M, L, w.up.afp, s));
+    int flags[3] = {0, 0, 0};
+    LBG_TRY_HIP(hipMemcpyAsync(flags, w.up.afp.shift, sizeof(flags), hipMemcpyDeviceToHost, s));
+    LBG_TRY_HIP(hipStreamSynchronize(s));
+    on_grid = flags[1] == 0 ? 1 : 0;
+  }
   auto assign_and_D = [&](double* Dh) -> int {
     LBG_TRY(tm.begin(Timer::kAssign, s));
     LBG_TRY(launch_assign(X, M, L, w.Cb[cur], n, idx_out, nullptr, p->precision,
@@ -557,9 +589,11 @@ int lbg_train(const float* X, int64_t M, int64_t L, int64_t N, const lbg_params*
         cur ^= 1;
         n *= 2;
       }
-      double D_prev = INFINITY;
-      bool first = true;
-      int32_t it = 0;
+      // (C_init may resume its level in the middle: see lbg_params)
+      const bool resume = p->C_init && level == 0;
+      double D_prev = resume ? p->D_prev_init : INFINITY;
+      bool first = D_prev == INFINITY;
+      int32_t it = resume ? p->it_init : 0;
       int32_t forced = -1;
       if (p->fixed_iters > 0) forced = p->fixed_iters;
       if (p->forced_iters && level < p->n_forced) forced = p->forced_iters[level];
@@ -578,7 +612,7 @@ int lbg_train(const float* X, int64_t M, int64_t L, int64_t N, const lbg_params*
         if (stop) break;
         LBG_TRY(tm.begin(Timer::kUpdate, s));
         LBG_TRY(launch_update(X, M, L, idx_out, w.Cb[cur], n, w.Cb[cur ^ 1], nullptr, 0,
-                              0.0, w.up, true, s));
+                              0.0, w.up, true, s, on_grid));
         LBG_TRY(tm.end(s));
         cur ^= 1;
         D_prev = D;
@@ -607,6 +641,7 @@ int lbg_train(const float* X, int64_t M, int64_t L, int64_t N, const lbg_params*
     st->ms_assign = tm.ms[Timer::kAssign];
     st->ms_update = tm.ms[Timer::kUpdate];
     st->ms_split = tm.ms[Timer::kSplit];
+    LBG_TRY(run_stats(X, M, L, N, C_out, idx_out, p, st, w, s));
   } else {
     LBG_TRY_HIP(hipStreamSynchronize(s));
   }

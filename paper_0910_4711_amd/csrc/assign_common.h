@@ -1072,16 +1072,29 @@ struct Frag<Bf16x3Screen<LP>> {
       lo[s] = *reinterpret_cast<const bf16x8*>(p + 2 * LP + 8 * s);
     }
   }
-  // small products first, then hi.hi, then the norms
+  // small products first, then hi.hi, then the norms.  HIONLY: every
+  // vector of the tile is exact in BF16 (its mid and lo parts are zero, as
+  // for 8-bit pixels), so the products with them vanish and are skipped:
+  // the same sum in the same order without its zero terms.
+  template <bool HIONLY = false>
   __device__ __forceinline__ void mma(const XSplit<NS>& x, const bf16x8& xn, f16v& acc) const {
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(mid[0], x.m[0], f16v{}, 0, 0, 0);
+    if constexpr (HIONLY) {
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[0], x.h[0], f16v{}, 0, 0, 0);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      if (s > 0) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(mid[s], x.m[s], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[s], x.h[s], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], x.l[s], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(mid[s], x.h[s], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], x.m[s], acc, 0, 0, 0);
+      for (int s = 0; s < NS; ++s) {
+        if (s > 0) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[s], x.h[s], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(mid[s], x.h[s], acc, 0, 0, 0);
+      }
+    } else {
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(mid[0], x.m[0], f16v{}, 0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        if (s > 0) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(mid[s], x.m[s], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[s], x.h[s], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], x.l[s], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(mid[s], x.h[s], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], x.m[s], acc, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s)
@@ -1090,11 +1103,21 @@ struct Frag<Bf16x3Screen<LP>> {
   }
 };
 
+// The products of one tile (the vanishing-part chain only for the split
+// screen).
+template <bool HIONLY, class F, class XF, class XN>
+__device__ __forceinline__ void frag_mma(const F& f, const XF& xf, const XN& xn, f16v& acc) {
+  if constexpr (HIONLY)
+    f.template mma<true>(xf, xn, acc);
+  else
+    f.mma(xf, xn, acc);
+}
+
 // Screens nt tiles of 32 codevectors (row j of tile 0 at ar) against the
 // wave's vectors.  Software-pipelined: the matrix-core products of tile t+1
 // are issued before the key updates of tile t, so that the two overlap;
 // with small dimensions the A fragments are also loaded one tile ahead.
-template <class SC, class XF, class XN>
+template <class SC, bool HIONLY = false, class XF, class XN>
 __device__ __forceinline__ void screen_tiles(const typename SC::elem* ar, int nt, uint32_t tb0,
                                              int h, const XF& xf, const XN& xn, Slots& sl,
                                              uint32_t vmask, float ninf) {
@@ -1105,7 +1128,7 @@ __device__ __forceinline__ void screen_tiles(const typename SC::elem* ar, int nt
       Frag<SC> f;
       f.load(ar + t * TS, h);
       f16v c;
-      f.mma(xf, xn, c);
+      frag_mma<HIONLY>(f, xf, xn, c);
       sl.push(c, vmask, tb0 + t, ninf);
     }
     return;
@@ -1113,7 +1136,7 @@ __device__ __forceinline__ void screen_tiles(const typename SC::elem* ar, int nt
   Frag<SC> fa, fb;
   f16v ca, cb;
   fa.load(ar, h);
-  fa.mma(xf, xn, ca);
+  frag_mma<HIONLY>(fa, xf, xn, ca);
   if (DB && nt > 1) fb.load(ar + TS, h);
   int t = 0;
   for (; t + 2 < nt; t += 2) {
@@ -1121,18 +1144,18 @@ __device__ __forceinline__ void screen_tiles(const typename SC::elem* ar, int nt
     // phases stay apart, so that each tile's key updates run beside the
     // other tile's products instead of after both.
     if (!DB) fb.load(ar + (t + 1) * TS, h);
-    fb.mma(xf, xn, cb);
+    frag_mma<HIONLY>(fb, xf, xn, cb);
     fa.load(ar + (t + 2) * TS, h);
     sl.push(ca, vmask, tb0 + t, ninf);
     __builtin_amdgcn_sched_barrier(0);
-    fa.mma(xf, xn, ca);
+    frag_mma<HIONLY>(fa, xf, xn, ca);
     if (DB) fb.load(ar + min(t + 3, nt - 1) * TS, h);
     sl.push(cb, vmask, tb0 + t + 1, ninf);
     __builtin_amdgcn_sched_barrier(0);
   }
   if (t + 1 < nt) {
     if (!DB) fb.load(ar + (t + 1) * TS, h);
-    fb.mma(xf, xn, cb);
+    frag_mma<HIONLY>(fb, xf, xn, cb);
     sl.push(ca, vmask, tb0 + t, ninf);
     sl.push(cb, vmask, tb0 + t + 1, ninf);
   } else {
@@ -1200,7 +1223,9 @@ __device__ __forceinline__ WaveCtx wave_ctx(int L, int tile_bits) {
 // xv holds this lane's half-row on entry; with PF it receives the half-row
 // of the tile at next_row0 (when >= 0), loaded while the screen runs.
 // Returns this lane's winning distance (0 for lanes that finish no vector).
-template <class SC, bool VEC, bool PF, int NT = kAssignThreads>
+// HIONLY (split screen): every vector of the tile is exact in BF16, so the
+// products with its vanishing mid and lo parts are skipped.
+template <class SC, bool VEC, bool PF, int NT = kAssignThreads, bool HIONLY = false>
 __device__ __forceinline__ double process_rows(
     float (&xv)[SC::LP / 2], const float* __restrict__ X, int64_t M, int L, int64_t row0,
     int64_t next_row0, const float* __restrict__ C, int n, int n_pad, int CR, bool resident,
@@ -1281,8 +1306,8 @@ __device__ __forceinline__ double process_rows(
       __syncthreads();
     }
     const E* base = resident ? sA + (int64_t)c0 * S : sA;
-    screen_tiles<SC>(base + j * S, cr >> 5, (uint32_t)(c0 >> 5), h, xf, xn, sl, w.vmask,
-                     w.ninf);
+    screen_tiles<SC, HIONLY>(base + j * S, cr >> 5, (uint32_t)(c0 >> 5), h, xf, xn, sl,
+                             w.vmask, w.ninf);
   }
   return finish_rows<SC, VEC>(sl, X, M, L, C, n, idx, mind, row0, w.tile_bits, nfb,
                               resident ? sA : nullptr, xk, xsq, w.bd, w.ninf);
@@ -1368,6 +1393,46 @@ __device__ __forceinline__ void direct_rows(const float* __restrict__ X, int64_t
   }
 }
 
+// The persistent row-tile loop of the allocation kernel (HIONLY: see
+// process_rows).
+template <class SC, bool VEC, int W, bool HIONLY>
+__device__ __forceinline__ void assign_rows(const float* __restrict__ X, int64_t M, int L,
+                                            const float* __restrict__ C, int n,
+                                            const typename SC::elem* __restrict__ Cp, int n_pad,
+                                            int CR, int32_t* __restrict__ idx,
+                                            float* __restrict__ mind, double* __restrict__ dpart,
+                                            unsigned long long* __restrict__ nfb, int tile_bits,
+                                            typename SC::elem* sA) {
+  constexpr int LP = SC::LP;
+  constexpr bool PF = SC::PF;  // prefetch the next row tile's vectors
+  constexpr int NT = 64 * W;
+  constexpr int RT = 32 * W;  // training vectors per row tile
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (SGPR)
+  const int64_t ntiles_rows = (M + RT - 1) / RT;
+  const bool resident = CR >= n_pad;
+  const WaveCtx w = wave_ctx<SC>(L, tile_bits);
+
+  float xv[LP / 2];
+  int64_t rt = blockIdx.x;
+  if (PF && rt < ntiles_rows)
+    load_x<LP, VEC>(X, M, L, rt * RT + (int64_t)wave * 32, w.h, w.j, xv);
+  if (resident) stage_from_C<SC, VEC, NT>(C, n, L, n_pad, sA);
+
+  for (; rt < ntiles_rows; rt += gridDim.x) {
+    const int64_t row0 = rt * RT + (int64_t)wave * 32;
+    if (!PF) load_x<LP, VEC>(X, M, L, row0, w.h, w.j, xv);
+    const int64_t next =
+        (PF && rt + gridDim.x < ntiles_rows) ? row0 + (int64_t)gridDim.x * RT : -1;
+    const double d = process_rows<SC, VEC, PF, NT, HIONLY>(
+        xv, X, M, L, row0, next, C, n, n_pad, CR, resident, Cp, sA, idx, mind, nfb, w);
+    // partial of the distortion per 32 vectors (lanes added by a fixed
+    // butterfly), indexed by the vectors: the same for every launch shape
+    const double ws = wave_sum(d);
+    if (dpart && lane == 0 && row0 < M) dpart[row0 >> 5] = ws;
+  }
+}
+
 // W waves per workgroup: 4 (OCC workgroups per CU), or 8 with one workgroup
 // per CU holding a codebook of up to kWideLds bytes resident.
 template <class SC, bool VEC, int W>
@@ -1398,32 +1463,16 @@ __global__ __launch_bounds__(64 * W, W == 4 ? SC::OCC : 1) void assign_kernel(
     }
   }
 
-  constexpr int NT = 64 * W;
-  constexpr int RT = 32 * W;  // training vectors per row tile
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (SGPR)
-  const int64_t ntiles_rows = (M + RT - 1) / RT;
-  const bool resident = CR >= n_pad;
-  const WaveCtx w = wave_ctx<SC>(L, tile_bits);
-
-  float xv[LP / 2];
-  int64_t rt = blockIdx.x;
-  if (PF && rt < ntiles_rows)
-    load_x<LP, VEC>(X, M, L, rt * RT + (int64_t)wave * 32, w.h, w.j, xv);
-  if (resident) stage_from_C<SC, VEC, NT>(C, n, L, n_pad, sA);
-
-  for (; rt < ntiles_rows; rt += gridDim.x) {
-    const int64_t row0 = rt * RT + (int64_t)wave * 32;
-    if (!PF) load_x<LP, VEC>(X, M, L, row0, w.h, w.j, xv);
-    const int64_t next =
-        (PF && rt + gridDim.x < ntiles_rows) ? row0 + (int64_t)gridDim.x * RT : -1;
-    const double d = process_rows<SC, VEC, PF, NT>(xv, X, M, L, row0, next, C, n, n_pad, CR,
-                                                   resident, Cp, sA, idx, mind, nfb, w);
-    // partial of the distortion per 32 vectors (lanes added by a fixed
-    // butterfly), indexed by the vectors: the same for every launch shape
-    const double ws = wave_sum(d);
-    if (dpart && lane == 0 && row0 < M) dpart[row0 >> 5] = ws;
-  }
+  // training sets whose every coordinate is exact in BF16 (flag set by the
+  // set-up pass of a training run) skip the products with the vanishing
+  // parts; the two bodies are separate so that neither costs registers of
+  // the other
+  if (SC::SPLIT && ctl.xflags && ctl.xflags[2])
+    assign_rows<SC, VEC, W, SC::SPLIT>(X, M, L, C, n, Cp, n_pad, CR, idx, mind, dpart, nfb,
+                                       tile_bits, sA);
+  else
+    assign_rows<SC, VEC, W, false>(X, M, L, C, n, Cp, n_pad, CR, idx, mind, dpart, nfb,
+                                   tile_bits, sA);
 }
 
 // Launch shape of the allocation for a codebook of n_pad rows: waves per

@@ -187,6 +187,7 @@ __global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ ins
   int N = B.N;
   if (B.st->done) return;
   if (local == 0) (void)afp::acc_decide(ctl, true, &N);  // the instance's decision
+  if (forced_stop(B.st)) return;  // the level ends here: no update follows
   N = B.st->n;
   const int s = B.shift[0], tf = B.shift[1];
   const int L = B.L;

@@ -41,6 +41,16 @@ __device__ inline Step step_of(const DevState* st, double D) {
   return r;
 }
 
+// Whether this allocation ends its level by a forced update count
+// (fixed_iters / forced), which does not depend on the distortion: the
+// accumulation of such an iteration is never used and can be skipped.
+__device__ inline bool forced_stop(const DevState* st) {
+  int forced = -1;
+  if (st->fixed_iters > 0) forced = st->fixed_iters;
+  if (st->level < st->n_forced && st->level < 32) forced = st->forced[st->level];
+  return forced >= 0 && st->it >= forced;
+}
+
 // The state after the step: names the buffers of this iteration's update /
 // split and the codebook of the next allocation.  ``out`` starts as a copy
 // of ``in``; one thread.

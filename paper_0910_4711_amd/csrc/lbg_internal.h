@@ -62,6 +62,10 @@ struct Ctl {
   int64_t nparts;
   double* Dtrace;   // distortion of every allocation
   int32_t* Atrace;  // action decided after every allocation
+  // (allocation, nullable) the training set's fixed-point scales and
+  // properties as the set-up pass writes them; [2] != 0: every coordinate
+  // is exact in BF16
+  const int* xflags;
 };
 
 __host__ __device__ inline int tile_bits_of(int64_t n) {
@@ -108,7 +112,7 @@ void plan_assign(Carver& c, int64_t M, int64_t L, int64_t N, int precision,
 int launch_assign(const float* X, int64_t M, int64_t L, const float* C,
                   int64_t N, int32_t* idx, float* mind, int precision,
                   double* dpart, unsigned long long* nfb, void* prep, hipStream_t s,
-                  Ctl ctl = Ctl{nullptr, nullptr, nullptr, 0, nullptr, nullptr},
+                  Ctl ctl = Ctl{nullptr, nullptr, nullptr, 0, nullptr, nullptr, nullptr},
                   CbPair cbp = CbPair{{nullptr, nullptr}});
 // Partials of the distortion that the allocation writes.
 int64_t assign_num_parts(int64_t M, int64_t L, int64_t N, int precision);
@@ -122,8 +126,9 @@ int launch_reduce_parts(const double* parts, int64_t nparts, double denom,
 struct AfpWs {
   unsigned long long* part;  // [nchunks][N][L] integer partial sums
   int32_t* pcnt;             // [nchunks][N] partial counts
-  uint32_t* amax;            // [2 absmax_blocks] block maxima of |x| and fine bits
-  int* shift;                // [2] fixed-point shift s, second-word shift t (0: none)
+  uint32_t* amax;            // [3 absmax_blocks] block maxima of |x|, fine bits, BF16 rest
+  int* shift;                // [3] fixed-point shift s, second-word shift t (0: none),
+                             // every coordinate exact in BF16
   unsigned long long* lo;    // [N][L] second-word sums (kept zero between updates)
   int64_t nlo;
   int cps, nslices, nchunks, absmax_blocks;
@@ -132,10 +137,12 @@ struct AfpWs {
 bool afp_usable(int64_t L, int64_t N);
 void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w);
 int launch_afp_shift(const float* X, int64_t M, int64_t L, const AfpWs& w, hipStream_t s);
+// on_grid: 1 when the caller knows every coordinate lies on the 2^-s grid
+// (shift[1] == 0: one-word kernels), else the kernels read that on the device.
 int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const float* C_old,
                int64_t N, float* C_out, int32_t* counts, int mode, double g2, const AfpWs& w,
-               hipStream_t s, Ctl ctl = Ctl{nullptr, nullptr, nullptr, 0, nullptr, nullptr},
-               CbPair cbp = CbPair{{nullptr, nullptr}});
+               hipStream_t s, Ctl ctl = Ctl{nullptr, nullptr, nullptr, 0, nullptr, nullptr, nullptr},
+               CbPair cbp = CbPair{{nullptr, nullptr}}, int on_grid = 0);
 
 // Sort-based fixed-order segmented sums (codebooks too large for the above).
 struct UpdateWs {
@@ -155,12 +162,12 @@ void plan_update(Carver& c, int64_t M, int64_t L, int64_t N, UpdateWs* ws);
 int launch_update(const float* X, int64_t M, int64_t L, const int32_t* idx,
                   const float* C_old, int64_t N, float* C_out, int32_t* counts,
                   int mode, double g2, const UpdateWs& ws, bool shift_ready,
-                  hipStream_t s);
+                  hipStream_t s, int on_grid = 0);
 
 // ----------------------------------------------------------------- misc --
 struct CentroidWs {
   double* part;    // [nwg][L]
-  uint32_t* amax;  // [2 nwg] block maxima of |x| and fine bits (set-up of a training run)
+  uint32_t* amax;  // [3 nwg] block maxima of |x|, fine bits, BF16 rest (set-up of a run)
   int64_t nwg;
 };
 void plan_centroid(Carver& c, int64_t M, int64_t L, CentroidWs* ws);
@@ -191,6 +198,13 @@ int launch_distortion(const float* X, int64_t M, int64_t L, const float* C,
                       int64_t N, const int32_t* idx, double* D,
                       const DistWs& ws, hipStream_t s);
 
+// Statistics of a finished run: cell sizes of the allocation idx over n
+// codevectors into cnt [n] (workspace), out[0] = empty cells, out[1] (with
+// ties) = rows within the tie band (FP64 top two); out is 2 device words.
+int launch_run_stats(const float* X, int64_t M, int64_t L, const float* C, int64_t n,
+                     const int32_t* idx, bool ties, int32_t* cnt, unsigned long long* out,
+                     hipStream_t s);
+
 int launch_grad_x(const float* X, int64_t M, int64_t L, const float* C,
                   int64_t N, const int32_t* idx, double g2, float* gX,
                   hipStream_t s);
@@ -216,6 +230,8 @@ struct TrainWs {
   DevState* pend;
   double* Dtrace;
   int32_t* Atrace;
+  int32_t* cellcnt;              // [N] cell sizes (statistics)
+  unsigned long long* runstat;   // [2] empty cells, near-tie rows
 };
 void plan_train(Carver& c, int64_t M, int64_t L, int64_t N, int precision, TrainWs* w);
 

@@ -195,7 +195,101 @@ __global__ __launch_bounds__(kThreads) void grad_x_kernel(
   }
 }
 
+// Statistics of a finished run.  cell_count_kernel: sizes of the cells of
+// the allocation (privatised per block in LDS when the codebook is small).
+constexpr int kHistLds = 16384;  // cells counted in LDS
+
+__global__ __launch_bounds__(1024) void cell_count_kernel(const int32_t* __restrict__ idx,
+                                                          int64_t M, int n,
+                                                          int32_t* __restrict__ cnt) {
+  __shared__ int32_t h[kHistLds];
+  const bool lds = n <= kHistLds;
+  if (lds) {
+    for (int k = threadIdx.x; k < n; k += blockDim.x) h[k] = 0;
+    __syncthreads();
+  }
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M;
+       m += (int64_t)gridDim.x * blockDim.x) {
+    const int k = idx[m];
+    if ((unsigned)k < (unsigned)n) {
+      if (lds)
+        atomicAdd(&h[k], 1);
+      else
+        atomicAdd(&cnt[k], 1);
+    }
+  }
+  if (lds) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+      if (h[k]) atomicAdd(&cnt[k], h[k]);
+  }
+}
+
+// out[0] += number of empty cells among the n.
+__global__ __launch_bounds__(256) void empty_count_kernel(const int32_t* __restrict__ cnt, int n,
+                                                          unsigned long long* __restrict__ out) {
+  int e = 0;
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) e += cnt[k] == 0;
+  e += __shfl_xor(e, 1);
+  e += __shfl_xor(e, 2);
+  e += __shfl_xor(e, 4);
+  e += __shfl_xor(e, 8);
+  e += __shfl_xor(e, 16);
+  e += __shfl_xor(e, 32);
+  if ((threadIdx.x & 63) == 0 && e) atomicAdd(out, (unsigned long long)e);
+}
+
+// out[1] += rows whose two nearest codevectors (FP64 direct form, every
+// codevector scored) are within 1e-6 |x|^2 of each other: one thread per row.
+__global__ __launch_bounds__(256) void tie_count_kernel(const float* __restrict__ X, int64_t M,
+                                                        int L, const float* __restrict__ C,
+                                                        int n, unsigned long long* __restrict__ out) {
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int tie = 0;
+  if (m < M && n >= 2) {
+    const float* x = X + m * (int64_t)L;
+    double d1 = INFINITY, d2 = INFINITY, xx = 0.0;
+    for (int l = 0; l < L; ++l) xx += (double)x[l] * (double)x[l];
+    for (int k = 0; k < n; ++k) {
+      const float* c = C + (int64_t)k * L;
+      double d = 0.0;
+      for (int l = 0; l < L; ++l) {
+        const double t = (double)x[l] - (double)c[l];
+        d = d + t * t;
+      }
+      if (d < d1) {
+        d2 = d1;
+        d1 = d;
+      } else if (d < d2) {
+        d2 = d;
+      }
+    }
+    tie = (d2 - d1) < 1e-6 * xx;
+  }
+  const unsigned long long b = __ballot(tie);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(out + 1, (unsigned long long)__popcll(b));
+}
+
 }  // namespace
+
+int launch_run_stats(const float* X, int64_t M, int64_t L, const float* C, int64_t n,
+                     const int32_t* idx, bool ties, int32_t* cnt, unsigned long long* out,
+                     hipStream_t s) {
+  LBG_TRY_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)n, s));
+  LBG_TRY_HIP(hipMemsetAsync(out, 0, 2 * sizeof(unsigned long long), s));
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(512, (M + 1023) / 1024));
+  hipLaunchKernelGGL(cell_count_kernel, dim3(grid), dim3(1024), 0, s, idx, M, (int)n, cnt);
+  LBG_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(empty_count_kernel, dim3((unsigned)std::min<int64_t>(64, (n + 255) / 256)),
+                     dim3(256), 0, s, cnt, (int)n, out);
+  LBG_TRY_HIP(hipGetLastError());
+  if (ties) {
+    hipLaunchKernelGGL(tie_count_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, X,
+                       M, (int)L, C, (int)n, out);
+    LBG_TRY_HIP(hipGetLastError());
+  }
+  return LBG_OK;
+}
 
 int launch_split(const float* C, int64_t n, int64_t L, int mode, double eps,
                  double delta, float* C2, hipStream_t s, const DevState* st, CbPair cbp) {
@@ -208,9 +302,9 @@ int launch_split(const float* C, int64_t n, int64_t L, int mode, double eps,
 
 // Set-up of a training run in two launches.  setup_pass_kernel: the column
 // sums of colsum_kernel (same blocks, same order) and, from the same loads,
-// each block's largest finite |x| and largest fine bits (as absmax_kernel
-// forms them; a maximum does not depend on the order); the blocks also clear
-// the update's second-word array lo (nlo words).
+// each block's largest finite |x|, largest fine bits and the OR of the low 16
+// bits (as absmax_kernel forms them; none depends on the order); the blocks
+// also clear the update's second-word array lo (nlo words).
 __global__ __launch_bounds__(kThreads) void setup_pass_kernel(const float* __restrict__ X,
                                                               int64_t M, int L,
                                                               int64_t rows_per_block,
@@ -221,6 +315,7 @@ __global__ __launch_bounds__(kThreads) void setup_pass_kernel(const float* __res
   __shared__ double s[kThreads];
   __shared__ uint32_t sm[kThreads];
   __shared__ uint32_t sf[kThreads];
+  __shared__ uint32_t sr[kThreads];
   const int R = kThreads / L;
   const int t = threadIdx.x;
   const int q = t / L, d = t % L;
@@ -229,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void setup_pass_kernel(const float* __res
   const int64_t r0 = blk * rows_per_block;
   const int64_t r1 = min(M, r0 + rows_per_block);
   double acc = 0.0;
-  uint32_t m = 0, f = 0;
+  uint32_t m = 0, f = 0, rb = 0;
   if (q < R)
     for (int64_t r = r0 + q; r < r1; r += R) {
       const float v = X[r * L + d];
@@ -237,10 +332,12 @@ __global__ __launch_bounds__(kThreads) void setup_pass_kernel(const float* __res
       const uint32_t b = __float_as_uint(v) & 0x7fffffffu;
       m = (b > m && b < 0x7f800000u) ? b : m;  // ignore Inf / NaN
       f = max(f, afp::fine_bits(b));
+      rb |= __float_as_uint(v) & 0xffffu;
     }
   s[t] = acc;
   sm[t] = m;
   sf[t] = f;
+  sr[t] = rb;
   __syncthreads();
   if (t < L) {
     double v = 0.0;
@@ -251,12 +348,14 @@ __global__ __launch_bounds__(kThreads) void setup_pass_kernel(const float* __res
     if (t < off) {
       sm[t] = max(sm[t], sm[t + off]);
       sf[t] = max(sf[t], sf[t + off]);
+      sr[t] |= sr[t + off];
     }
     __syncthreads();
   }
   if (t == 0) {
     amax[blk] = sm[0];
     amax[gridDim.x + blk] = sf[0];
+    amax[2 * gridDim.x + blk] = sr[0];
   }
 }
 
@@ -313,7 +412,7 @@ int launch_decide(const double* dpart, int64_t nparts, DevState* st, double* Dtr
 void plan_centroid(Carver& c, int64_t M, int64_t L, CentroidWs* ws) {
   ws->nwg = std::min<int64_t>(1024, std::max<int64_t>(1, (M + 255) / 256));
   ws->part = c.take<double>((size_t)(ws->nwg * L));
-  ws->amax = c.take<uint32_t>((size_t)(2 * ws->nwg));
+  ws->amax = c.take<uint32_t>((size_t)(3 * ws->nwg));
 }
 
 int launch_setup(const float* X, int64_t M, int64_t L, float* c0, float* C2, int mode,

@@ -27,7 +27,7 @@ struct GraphKey {
   const void* ws;
   const void* idx;
   int64_t M, L, N;
-  int precision, split_mode, timed;
+  int precision, split_mode, timed, on_grid;
   double eps, delta;
   hipStream_t stream;
   bool operator==(const GraphKey& o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
@@ -66,6 +66,7 @@ struct Batch {
   int32_t* idx;
   const TrainWs* w;
   int64_t nparts;
+  int on_grid;  // 1: the training set lies on the update's 2^-s grid
 };
 
 // One iteration is two pieces: the allocation, then the update, whose
@@ -76,12 +77,12 @@ constexpr int kPieces = 2;
 int enqueue_piece(const Batch& b, int piece, hipStream_t s) {
   const TrainWs& w = *b.w;
   CbPair cbp{{w.Cb[0], w.Cb[1]}};
-  const Ctl ctl{w.st, w.pend, w.as.dpart, b.nparts, w.Dtrace, w.Atrace};
+  const Ctl ctl{w.st, w.pend, w.as.dpart, b.nparts, w.Dtrace, w.Atrace, w.up.afp.shift};
   if (piece == 0)
     return launch_assign(b.X, b.M, b.L, nullptr, b.N, b.idx, nullptr, b.precision, w.as.dpart,
                          w.as.nfb, w.as.prep, s, ctl, cbp);
   return launch_afp(b.X, b.M, b.L, b.idx, nullptr, b.N, nullptr, nullptr, 0, 0.0, w.up.afp, s,
-                    ctl, cbp);
+                    ctl, cbp, b.on_grid);
 }
 
 // Timing events of iteration i (nullable): ev[i][0][0] before the
@@ -195,8 +196,10 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
   hs.eps = p->eps_split;
   hs.delta = p->delta;
   hs.D_cap = kTraceCap;
-  hs.first = 1;
-  hs.D_prev = INFINITY;
+  // a level starts afresh, or resumes from C_init in its middle
+  hs.D_prev = p->C_init ? p->D_prev_init : INFINITY;
+  hs.first = hs.D_prev == INFINITY;
+  hs.it = p->C_init ? p->it_init : 0;
   hs.status = LBG_OK;
   hs.n_forced = std::min(p->n_forced, 32);
   for (int i = 0; i < hs.n_forced; ++i) hs.forced[i] = p->forced_iters[i];
@@ -240,9 +243,15 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
     LBG_TRY(launch_afp_shift(X, M, L, w.up.afp, s));
   }
 
+  // Whether the training set lies on the update's 2^-s grid (set-up pass):
+  // read once, so that the accumulation runs its one-word kernel (the
+  // kernel that decides on the device is larger and measured slower).
+  int flags[3] = {0, 0, 0};
+  LBG_TRY_HIP(hipMemcpyAsync(flags, w.up.afp.shift, sizeof(flags), hipMemcpyDeviceToHost, s));
+  LBG_TRY_HIP(hipStreamSynchronize(s));
   const bool timed = p->timing != 0 && st != nullptr;
   Batch b{X, M, L, N, p->precision, p->split_mode, p->eps_split, p->delta, idx_out, &w,
-          assign_num_parts(M, L, N, p->precision)};
+          assign_num_parts(M, L, N, p->precision), flags[1] == 0 ? 1 : 0};
   const bool use_graph = s != nullptr && p->graph != 0;
 
   GraphEntry* ge = nullptr;
@@ -267,6 +276,7 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
     key.precision = p->precision;
     key.split_mode = p->split_mode;
     key.timed = timed;
+    key.on_grid = b.on_grid;
     key.eps = p->eps_split;
     key.delta = p->delta;
     key.stream = s;
@@ -382,7 +392,13 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
   LBG_TRY_HIP(hipMemcpyAsync(C_out, w.Cb[pin->cb], (size_t)(N * L) * sizeof(float),
                              hipMemcpyDeviceToDevice, s));
   if (st) {
-    unsigned long long nf = 0;
+    unsigned long long nf = 0, rs[2] = {0, 0};
+    // statistics of the final allocation (before the one synchronisation)
+    if (pin->status != LBG_EINVAL) {
+      LBG_TRY(launch_run_stats(X, M, L, w.Cb[pin->cb], N, idx_out, p->stats_ties != 0,
+                               w.cellcnt, w.runstat, s));
+      LBG_TRY_HIP(hipMemcpyAsync(rs, w.runstat, sizeof(rs), hipMemcpyDeviceToHost, s));
+    }
     LBG_TRY_HIP(hipMemcpyAsync(&nf, w.as.nfb, sizeof(nf), hipMemcpyDeviceToHost, s));
     const int nD = std::min(pin->n_assign, std::min(st->D_cap, kTraceCap));
     if (st->D_trace && nD > 0)
@@ -402,6 +418,8 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
     st->ms_assign = ms[0];
     st->ms_update = ms[1];
     st->ms_split = ms[2];
+    st->empty_cells = (int32_t)rs[0];
+    st->near_tie_rows = p->stats_ties && pin->status != LBG_EINVAL ? (int64_t)rs[1] : -1;
   } else {
     LBG_TRY_HIP(hipStreamSynchronize(s));
   }

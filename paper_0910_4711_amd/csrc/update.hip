@@ -398,10 +398,12 @@ void plan_update(Carver& c, int64_t M, int64_t L, int64_t N, UpdateWs* ws) {
 int launch_update(const float* X, int64_t M, int64_t L, const int32_t* idx,
                   const float* C_old, int64_t N, float* C_out, int32_t* counts,
                   int mode, double g2, const UpdateWs& ws, bool shift_ready,
-                  hipStream_t s) {
+                  hipStream_t s, int on_grid) {
   if (ws.use_afp) {
     if (!shift_ready) LBG_TRY(launch_afp_shift(X, M, L, ws.afp, s));
-    return launch_afp(X, M, L, idx, C_old, N, C_out, counts, mode, g2, ws.afp, s);
+    return launch_afp(X, M, L, idx, C_old, N, C_out, counts, mode, g2, ws.afp, s,
+                      Ctl{nullptr, nullptr, nullptr, 0, nullptr, nullptr, nullptr},
+                      CbPair{{nullptr, nullptr}}, shift_ready ? on_grid : 0);
   }
   const int n = (int)N, Li = (int)L;
   int32_t* cnt = ws.cnt;

@@ -13,9 +13,17 @@ readings):
     1e-6 of the threshold, and the oracle is run in lockstep with the
     library's counts;
   * codebooks: per codevector ||c - c_ref|| / ||c_ref|| <= 1e-5 (absolute
-    1e-5 for a zero codevector), against the oracle with FP32 storage and
-    with FP64 storage;
+    1e-5 for a zero codevector), end to end against the oracle with FP32
+    codebook storage (the library's storage), and per step against the
+    oracle with FP64 storage: one FP64 update of the library's final
+    codebook against the library's update of it;
   * distortion: relative 1e-6.
+End to end, the FP64-storage oracle follows another trajectory wherever a
+row sits in the tie band (gap below 1e-6 ||x||^2): a one-row cell split
+into two children equidistant from it in exact arithmetic goes to whichever
+child the storage rounding favours, and the other child keeps its value, a
+2 eps difference that later iterations can amplify.  Such runs are compared
+per step (C20, mode i), as above.
 """
 import numpy as np
 import pytest
@@ -51,7 +59,7 @@ def _rel_rows(C, R):
     return np.where(den > 0, num / np.maximum(den, 1e-300), num)
 
 
-def _check_run(X, N, C, idx, D, level_iters, where, tol_c=1e-5):
+def _check_run(P, X, N, C, idx, D, level_iters, where, tol_c=1e-5):
     """The library's run (C, idx, D, per-level update counts) against the
     oracle.  Returns the lockstep FP32-storage oracle result."""
     Cg = host(C).astype(np.float64)
@@ -72,10 +80,16 @@ def _check_run(X, N, C, idx, D, level_iters, where, tol_c=1e-5):
     r32 = _rel_rows(Cg, ref["C"])
     assert r32.max() <= tol_c, f"{where}: codebook vs FP32-storage oracle {r32.max():.3g}"
     assert abs(D - ref["D"]) <= 1e-6 * abs(ref["D"]), f"{where}: D {D!r} vs {ref['D']!r}"
-    r64 = oracle.train(X, N, store_fp32=False, forced_iters=list(level_iters))
-    rr = _rel_rows(Cg, r64["C"])
-    assert rr.max() <= tol_c, f"{where}: codebook vs FP64 oracle {rr.max():.3g}"
-    assert abs(D - r64["D"]) <= 1e-6 * abs(r64["D"]), f"{where}: D vs FP64 oracle"
+    # one more step from the library's final codebook: the FP64 oracle's
+    # update (FP64 storage) against the library's, and both distortions
+    Xd = dev(X)
+    Cn, _ = P.update(Xd, idx, C)
+    Dg = float(P.distortion(Xd, C, idx).item())
+    c64, _ = oracle.update(X, io, Cg)
+    rr = _rel_rows(host(Cn), c64)
+    assert rr.max() <= tol_c, f"{where}: one update vs the FP64 oracle {rr.max():.3g}"
+    d64 = oracle.distortion(X, Cg, io)
+    assert abs(Dg - d64) <= 1e-6 * abs(d64) and abs(D - d64) <= 1e-6 * abs(d64), where
     return ref
 
 
@@ -93,21 +107,23 @@ GMM_CASES = [
 def test_train_gmm_matches_oracle(P, M, L, N, seed):
     X = synth.gmm(seed, M, L, N)
     C, idx, D, st = P.train(dev(X), N)
-    _check_run(X, N, C, idx, D, st["level_iters"], f"gmm {M}x{L} N={N}")
+    _check_run(P, X, N, C, idx, D, st["level_iters"], f"gmm {M}x{L} N={N}")
 
 
 def test_train_batched_gmm_matches_oracle(P):
-    # instances of the batched workload's generator at full size (M_i up to
-    # 65,536, L_i in {16, 64}, N_i up to 256), plus small ones
-    inst = synth.batched_instances(6, base_seed=10_000)
-    inst += synth.batched_instances(4, base_seed=20_000, scale=0.05)
+    # twelve instances of the batched workload's generator at full size
+    # (M_i from 11,571 to 61,054, L_i in {16, 64}, N_i from 16 to 256; seed
+    # 20,000 is M = 50,389, L = 64, N = 256) and four small ones
+    inst = synth.batched_instances(8, base_seed=10_000)
+    inst += synth.batched_instances(4, base_seed=20_000)
+    inst += synth.batched_instances(4, base_seed=30_000, scale=0.05)
     res, stats = P.train_batched([dev(X) for X, _ in inst], [N for _, N in inst])
     for i, ((X, N), (C, idx, D, info)) in enumerate(zip(inst, res)):
         # the per-level counts of the instance come from a single run on it,
         # which the batched form reproduces bit for bit
         C1, idx1, D1, st1 = P.train(dev(X), N)
         assert torch.equal(C, C1) and torch.equal(idx, idx1) and D == D1, f"instance {i}"
-        _check_run(X, N, C, idx, D, st1["level_iters"], f"instance {i} ({X.shape}, N={N})")
+        _check_run(P, X, N, C, idx, D, st1["level_iters"], f"instance {i} ({X.shape}, N={N})")
 
 
 def _wide_range(M=8192, L=16, seed=7):
@@ -138,7 +154,7 @@ def test_update_wide_range_matches_oracle(P):
 def test_train_wide_range_matches_oracle(P):
     X, _ = _wide_range()
     C, idx, D, st = P.train(dev(X), 8)
-    _check_run(X, 8, C, idx, D, st["level_iters"], "wide range")
+    _check_run(P, X, 8, C, idx, D, st["level_iters"], "wide range")
 
 
 def test_nonfinite_rows_contract(P):
