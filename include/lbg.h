@@ -405,6 +405,27 @@ int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const lbg_params
                       const lbg_batch_config* cfg, lbg_batch_result* res,
                       lbg_batch_stats* st, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * lbg_assign_distortion without a workspace, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and error
+ * behaviour as lbg_assign_distortion, bit for bit, minus ws / ws_bytes: the
+ * scratch space (the distortion partials, the prepared codebook) is a fixed
+ * device array inside the library of lbg_noalloc_scratch_bytes() bytes
+ * (8 MiB), one per GPU, kept until the process ends.  A problem whose
+ * scratch, lbg_workspace_size(LBG_OP_ASSIGN, M, L, N, precision), exceeds
+ * it is rejected with LBG_EINVAL (roughly M <= 2^24 rows with a small
+ * codebook).  Allocates nothing: no hipMalloc / hipFree, no library
+ * allocation.  Every call on one GPU uses the same array: calls that overlap
+ * on one GPU (different streams, or threads) race and must be ordered by the
+ * caller.  D must be 8-byte aligned.
+ */
+int lbg_assign_distortion_noalloc(const float* X, int64_t M, int64_t L,
+                                  const float* C, int64_t N, int32_t* idx,
+                                  float* mind, int precision, double* D,
+                                  void* stream);
+size_t lbg_noalloc_scratch_bytes(void);
+
 /* Bytes of workspace the operation ``op`` (LBG_OP_*) needs. */
 size_t lbg_workspace_size(int op, int64_t M, int64_t L, int64_t N,
                           int precision);

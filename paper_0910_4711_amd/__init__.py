@@ -158,6 +158,7 @@ def load():
             "lbg_distortion_backward": [vp, i64, i64, vp, i64, vp, dbl, vp, vp, vp, sz, vp],
             "lbg_encode": [vp, i64, i64, vp, i64, vp, vp, sz, vp],
             "lbg_assign_distortion": [vp, i64, i64, vp, i64, vp, vp, i32, vp, vp, sz, vp],
+            "lbg_assign_distortion_noalloc": [vp, i64, i64, vp, i64, vp, vp, i32, vp, vp],
             "lbg_decode": [vp, i64, vp, i64, i64, vp, vp],
             "lbg_image_blocks": [vp, i64, i64, i64, i64, vp, vp],
             "lbg_decode_image": [vp, vp, i64, i64, i64, i64, i64, vp, vp],
@@ -173,6 +174,8 @@ def load():
             f = getattr(lib, name)
             f.argtypes = args
             f.restype = ct.c_int
+        lib.lbg_noalloc_scratch_bytes.argtypes = []
+        lib.lbg_noalloc_scratch_bytes.restype = ct.c_size_t
         lib.lbg_workspace_size.argtypes = [ct.c_int, i64, i64, i64, ct.c_int]
         lib.lbg_workspace_size.restype = ct.c_size_t
         lib.lbg_last_error.argtypes = []
@@ -297,6 +300,24 @@ def assign_distortion(X, C, precision=FP32, with_mind=False):
     _check(load().lbg_assign_distortion(_ptr(X), M, L, _ptr(C), N, _ptr(idx), _ptr(mind),
                                         _prec(precision), _ptr(D), _ptr(ws), nb,
                                         _stream(X.device)), "lbg_assign_distortion")
+    return idx, mind, D
+
+
+def assign_distortion_noalloc(X, C, precision=FP32, with_mind=False):
+    """assign_distortion through the entry point that takes no workspace (its
+    scratch is the library's fixed per-GPU array): (idx, mind or None, D)."""
+    X, C = _f32_2d("X", X), _f32_2d("C", C)
+    M, L = X.shape
+    N = C.shape[0]
+    if C.shape[1] != L or C.device != X.device:
+        raise ValueError("X and C differ in dimension or device")
+    idx = torch.empty(M, dtype=torch.int32, device=X.device)
+    mind = torch.empty(M, dtype=torch.float32, device=X.device) if with_mind else None
+    D = torch.empty((), dtype=torch.float64, device=X.device)
+    _check(load().lbg_assign_distortion_noalloc(_ptr(X), M, L, _ptr(C), N, _ptr(idx),
+                                                _ptr(mind), _prec(precision), _ptr(D),
+                                                _stream(X.device)),
+           "lbg_assign_distortion_noalloc")
     return idx, mind, D
 
 
