@@ -490,6 +490,115 @@ __device__ __forceinline__ void acc_body(const float* __restrict__ X, int64_t M,
   }
 }
 
+// Accumulation by dimension slices: block (chunk, q) adds dimensions
+// [16 q, 16 q + 16) of every row of its chunk into LDS sums of all cells (rows
+// of 17 words), so no block filters rows by cell (the cell-slice blocks each
+// walk their chunk's whole index stream and gather their rows).  For
+// codebooks whose N x 17 words fit one CU's LDS and L a multiple of 16; the
+// partials keep the [chunk][cell][L] layout (fin_body reads them as before),
+// the counts come from the q = 0 blocks.  1024 threads: 256 groups of four
+// lanes, a lane taking one 16-byte word of a row, kDsRows rows per group in
+// flight (16-byte loads when X is 16-byte aligned).  The blocks of one chunk
+// sit on one XCD (blocks are dealt to the eight XCDs in turn), so the lines
+// they share meet in one L2.
+constexpr int kDs = 16;      // dimensions per slice
+constexpr int kDsRows = 8;   // rows per lane group in flight
+constexpr int kDsThreads = 1024;
+
+// Dynamic LDS the dimension-slice kernel may take: a CU's 160 KiB less a
+// reserve for its static LDS (the reduction buffer and run-state copies of
+// the device-side stop decision, about 3 KiB).
+constexpr int kAccdLdsMax = 163840 - 8192;
+
+inline size_t accd_lds_bytes(int64_t N) {
+  return (size_t)(N + 1) * (kDs + 1) * 8 + (size_t)(N + 1) * 4;
+}
+
+// chunk and slice of block ``blk`` of nch x nds blocks
+__device__ __forceinline__ void accd_block(int blk, int nch, int nds, int* chunk, int* q) {
+  const int nb = nch * nds;
+  if ((nch & 7) == 0 && (nb & 7) == 0) {
+    const int x = blk & 7, i = blk >> 3;
+    *chunk = (i / nds) * 8 + x;
+    *q = i % nds;
+  } else {
+    *chunk = blk / nds;
+    *q = blk % nds;
+  }
+}
+
+template <bool FINE, bool VEC>
+__device__ __forceinline__ void accd_body(const float* __restrict__ X, int64_t M, int L,
+                                          const int32_t* __restrict__ idx, int N, int ns,
+                                          int64_t rows_per_chunk, int chunk, int q, int s,
+                                          unsigned long long* __restrict__ part,
+                                          int32_t* __restrict__ pcnt,
+                                          unsigned long long* sacc,
+                                          unsigned long long* __restrict__ lo, int tfine) {
+  constexpr int LS = kDs + 1;
+  constexpr int NG = kDsThreads / 4;
+  const double p2s = ldexp(1.0, s);
+  const double p2t = ldexp(1.0, tfine);
+  int32_t* scnt = reinterpret_cast<int32_t*>(sacc + (size_t)(N + 1) * LS);
+  const int t = threadIdx.x;
+  for (int e = t; e < (N + 1) * LS; e += kDsThreads) sacc[e] = 0ull;
+  if (q == 0)
+    for (int e = t; e <= N; e += kDsThreads) scnt[e] = 0;
+  __syncthreads();
+  const int g = t >> 2, gl = t & 3;
+  const int d0 = kDs * q + 4 * gl;  // this lane's four dimensions
+  const int64_t r0 = (int64_t)chunk * rows_per_chunk;
+  const int64_t r1 = min(M, r0 + rows_per_chunk);
+  for (int64_t b = r0 + g; b < r1; b += (int64_t)NG * kDsRows) {
+    int k[kDsRows];
+    float v[kDsRows][4];
+#pragma unroll
+    for (int u = 0; u < kDsRows; ++u) {
+      const int64_t m = b + (int64_t)u * NG;
+      const bool on = m < r1;
+      const int64_t mm = on ? m : r0;  // a row of this chunk
+      const int kv = idx[mm];
+      k[u] = (on && (unsigned)kv < (unsigned)N) ? kv : N;  // N: the spare row
+      if constexpr (VEC) {
+        const float4 x = *reinterpret_cast<const float4*>(X + mm * L + d0);
+        v[u][0] = x.x;
+        v[u][1] = x.y;
+        v[u][2] = x.z;
+        v[u][3] = x.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[u][e] = X[mm * L + d0 + e];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kDsRows; ++u) {
+      unsigned long long* row = sacc + __umul24(k[u], LS) + 4 * gl;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) atomicAdd(&row[e], fixed(v[u][e], p2s));
+      if constexpr (FINE) {
+        if (k[u] < N) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const unsigned long long r = fixed_res(v[u][e], p2s, p2t);
+            if (r != 0ull) atomicAdd(&lo[(int64_t)k[u] * L + d0 + e], r);
+          }
+        }
+      }
+      if (q == 0 && gl == 0) atomicAdd(&scnt[k[u]], 1);
+    }
+  }
+  __syncthreads();
+  unsigned long long* dst = part + (int64_t)chunk * ns * L + kDs * q;
+  for (int e = t; e < N * kDs; e += kDsThreads) {
+    const int kk = e / kDs, d = e - kk * kDs;
+    dst[(int64_t)kk * L + d] = sacc[kk * LS + d];
+  }
+  if (q == 0) {
+    int32_t* cdst = pcnt + (int64_t)chunk * ns;
+    for (int e = t; e < N; e += kDsThreads) cdst[e] = scnt[e];
+  }
+}
+
 // Under device control: acts on the pending state for cell ``k`` (a split
 // of codevector k, or nothing); the block with ``lead`` commits the state.
 // Returns true when cell k is to be updated, with N, C_old and out set.

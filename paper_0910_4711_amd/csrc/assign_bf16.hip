@@ -55,14 +55,21 @@ __device__ __forceinline__ void mma2(const Frag<Bf16Screen<LP>>& f, const bf16x8
   }
 }
 
+// Key of a screened value v for tile number tb: v with its low mantissa bits
+// (those the tile number needs) replaced by tb, one v_and_or_b32.  Only the
+// tile number is embedded: every further bit would coarsen the keys (at
+// n = 1024 five bits already merge values within 2^5 ulps), and the slot is
+// known from the register that holds the key.
+__device__ __forceinline__ float tile_key(float v, uint32_t vmask, uint32_t tb) {
+  return __uint_as_float((__float_as_uint(v) & vmask) | tb);
+}
+
 // mn[r] = min(mn[r], key of acc[r]) for tile number tb.
 __device__ __forceinline__ void keys1(const f16v& acc, float (&mn)[16], uint32_t vmask,
                                       uint32_t tb, float ninf) {
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const float k = __uint_as_float((__float_as_uint(acc[r]) & vmask) | tb);
-    mn[r] = __builtin_amdgcn_fmed3f(mn[r], k, ninf);
-  }
+  for (int r = 0; r < 16; ++r)
+    mn[r] = __builtin_amdgcn_fmed3f(mn[r], tile_key(acc[r], vmask, tb), ninf);
 }
 
 // Keys G0 .. G0+K-1 of the 32 a lane updates per tile (16 slots of vector
@@ -74,7 +81,7 @@ __device__ __forceinline__ void keys_part(const f16v& ka, const f16v& kb, float 
 #pragma unroll
   for (int g = G0; g < G0 + K; ++g) {
     const float v = g < 16 ? ka[g & 15] : kb[g & 15];
-    const float k = __uint_as_float((__float_as_uint(v) & vmask) | tb);
+    const float k = tile_key(v, vmask, tb);
     if (g < 16)
       ma[g & 15] = __builtin_amdgcn_fmed3f(ma[g & 15], k, ninf);
     else
@@ -137,18 +144,9 @@ __device__ __forceinline__ void phase(const Frag<Bf16Screen<LP>>& f, const bf16x
   static_assert(NS == 1 || NS == 2 || NS == 4, "phase: LP 16, 32 or 64");
 }
 
-// Half-row [h LP/2, (h+1) LP/2) of vector row0 + j as BF16 B-operand
-// fragments (zeros beyond M or L).
-template <int LP, bool VEC>
-__device__ __forceinline__ void load_xfrag(const float* __restrict__ X, int64_t M, int L,
-                                           int64_t row0, int h, int j, bf16x8 (&xf)[LP / 16]) {
-  float v[LP / 2];
-  load_x<LP, VEC>(X, M, L, row0, h, j, v);
-#pragma unroll
-  for (int s = 0; s < LP / 2; ++s) xf[s >> 3][s & 7] = (__bf16)v[s];
-}
-
-// Lane's two smallest slot keys (k1 <= k2) and their codevector indices.
+// Lane's two smallest slot keys (k1 <= k2; the lower slot first on equal
+// keys) and their codevector indices: tile from the key's low bits, slot r
+// holding row 8 (r >> 2) + 4 h + (r & 3) of its tile.
 __device__ __forceinline__ void lane_top2(const float (&mn)[16], uint32_t lowmask, int h,
                                           float& k1, int& i1, float& k2, int& i2) {
   k1 = INFINITY;
@@ -265,8 +263,7 @@ __global__ __launch_bounds__(kV2Threads, 1) void bf16v2_kernel(
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int h = lane >> 5, j = lane & 31;
-  const int tb = tile_bits_of(n);
-  const uint32_t lowmask = (1u << tb) - 1u;
+  const uint32_t lowmask = (1u << tile_bits_of(n)) - 1u;
   uint32_t vmask = ~lowmask;
   asm volatile("v_mov_b32 %0, %1" : "=v"(vmask) : "v"(vmask));
   float ninf = -INFINITY;
@@ -277,12 +274,23 @@ __global__ __launch_bounds__(kV2Threads, 1) void bf16v2_kernel(
   const __bf16* ar = sA + j * S;
 
   const int64_t ngroups = (M + 63) >> 6;
-  for (int64_t g = (int64_t)blockIdx.x * kV2Waves + wave; g < ngroups;
-       g += (int64_t)gridDim.x * kV2Waves) {
+  const int64_t step = (int64_t)gridDim.x * kV2Waves;
+  int64_t g = (int64_t)blockIdx.x * kV2Waves + wave;
+  // FP32 half-rows of the group's two vector tiles, loaded one group ahead
+  // (while the previous group finishes)
+  float pa[LP / 2], pb[LP / 2];
+  if (g < ngroups) {
+    load_x<LP, VEC>(X, M, L, g * 64, h, j, pa);
+    load_x<LP, VEC>(X, M, L, g * 64 + 32, h, j, pb);
+  }
+  for (; g < ngroups; g += step) {
     const int64_t row0 = g * 64;
     bf16x8 xa[NS], xb[NS];
-    load_xfrag<LP, VEC>(X, M, L, row0, h, j, xa);
-    load_xfrag<LP, VEC>(X, M, L, row0 + 32, h, j, xb);
+#pragma unroll
+    for (int q = 0; q < LP / 2; ++q) {
+      xa[q >> 3][q & 7] = (__bf16)pa[q];
+      xb[q >> 3][q & 7] = (__bf16)pb[q];
+    }
     float ma[16], mb[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -311,8 +319,13 @@ __global__ __launch_bounds__(kV2Threads, 1) void bf16v2_kernel(
       keys1(a0, ma, vmask, (uint32_t)t, ninf);
       keys1(b0, mb, vmask, (uint32_t)t, ninf);
     }
+    if (g + step < ngroups) {
+      load_x<LP, VEC>(X, M, L, (g + step) * 64, h, j, pa);
+      load_x<LP, VEC>(X, M, L, (g + step) * 64 + 32, h, j, pb);
+    }
     const float da = finish_tile<LP, VEC>(ma, X, M, L, C, n, row0, lowmask, idx, mind);
-    const float db = finish_tile<LP, VEC>(mb, X, M, L, C, n, row0 + 32, lowmask, idx, mind);
+    const float db =
+        finish_tile<LP, VEC>(mb, X, M, L, C, n, row0 + 32, lowmask, idx, mind);
     // distortion partials of the two 32-vector groups (FP64, fixed tree)
     const double sa = wave_sum((double)da), sb = wave_sum((double)db);
     if (dpart && lane == 0) {

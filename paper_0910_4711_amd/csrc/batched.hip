@@ -419,7 +419,7 @@ void plan_batch(Carver& c, const lbg_instance* in, int n, BatchWs* w) {
     q.cpart = c.take<double>((size_t)(q.cnwg * L));
     q.Dtrace = c.take<double>(kBatchTrace);
     q.Atrace = c.take<int32_t>(kBatchTrace);
-    plan_afp(c, M, L, N, &q.afp);
+    plan_afp(c, M, L, N, &q.afp, false);
   }
   for (int k = 0; k < kNumPre; ++k) w->tot[k] = 0;
   for (int i = 0; i < n; ++i) {

@@ -132,11 +132,17 @@ struct AfpWs {
   unsigned long long* lo;    // [N][L] second-word sums (kept zero between updates)
   int64_t nlo;
   int cps, nslices, nchunks, absmax_blocks;
+  int dslices;  // > 0: accumulation by this many 16-dimension slices (all cells per block)
   int64_t rows_per_chunk;
 };
 bool afp_usable(int64_t L, int64_t N);
-void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w);
+// dslices: the single-run kernels may accumulate by dimension slices
+void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices = true);
 int launch_afp_shift(const float* X, int64_t M, int64_t L, const AfpWs& w, hipStream_t s);
+// The finishing kernel of the update (centroids or gradient from the partials).
+int launch_fin(const float* X, int64_t M, int64_t L, const float* C_old, int64_t N,
+               float* C_out, int32_t* counts, int mode, double g2, const AfpWs& w,
+               hipStream_t s, Ctl ctl, CbPair cbp);
 // on_grid: 1 when the caller knows every coordinate lies on the 2^-s grid
 // (shift[1] == 0: one-word kernels), else the kernels read that on the device.
 int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const float* C_old,

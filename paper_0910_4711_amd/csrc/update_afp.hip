@@ -86,6 +86,32 @@ __global__ __launch_bounds__(SEL ? kT : 1024) void acc_kernel(
                                                            blockIdx.x, sacc, slist, snsel);
 }
 
+// Dimension slices (see accd_body): one 1024-thread block per (chunk, slice).
+template <bool GENERIC, bool VEC>
+__global__ __launch_bounds__(kDsThreads) void accd_kernel(
+    const float* __restrict__ X, int64_t M, int L, const int32_t* __restrict__ idx, int N,
+    int nch, int nds, int64_t rows_per_chunk, const int* __restrict__ shift_p,
+    unsigned long long* __restrict__ part, int32_t* __restrict__ pcnt,
+    unsigned long long* __restrict__ lo, Ctl ctl) {
+  extern __shared__ unsigned long long sacc[];
+  const int ns = N;
+  if (ctl.st) {
+    if (ctl.st->done) return;
+    if (blockIdx.x == 0) (void)acc_decide(ctl, true, &N);
+    if (forced_stop(ctl.st)) return;  // the level ends here: no update follows
+    N = ctl.st->n;
+  }
+  int chunk, q;
+  accd_block(blockIdx.x, nch, nds, &chunk, &q);
+  const int s = shift_p[0], tf = shift_p[1];
+  if (GENERIC && tf > 0)
+    accd_body<true, VEC>(X, M, L, idx, N, ns, rows_per_chunk, chunk, q, s, part, pcnt, sacc, lo,
+                         tf);
+  else
+    accd_body<false, VEC>(X, M, L, idx, N, ns, rows_per_chunk, chunk, q, s, part, pcnt, sacc,
+                          lo, 0);
+}
+
 // One block per cell.
 template <int MODE>
 __global__ __launch_bounds__(kT) void fin_kernel(
@@ -129,13 +155,22 @@ void launch_acc(dim3 grid, size_t lds, hipStream_t st, const float* X, int64_t M
 
 }  // namespace
 
-void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w) {
+void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices) {
   w->cps = (int)std::min<int64_t>(std::min<int64_t>(N, 8192), kLdsBytes / (8 * (L + 1) + 4) - 1);
   w->nslices = (int)((N + w->cps - 1) / w->cps);
+  // Dimension slices instead of several cell slices when all cells fit one
+  // CU's LDS: one block per CU, 256 in all
+  w->dslices = 0;
+  if (dslices && w->nslices > 1 && L % kDs == 0 && accd_lds_bytes(N) <= (size_t)kAccdLdsMax) {
+    w->dslices = (int)(L / kDs);
+    w->nslices = 1;
+    w->cps = (int)N;
+  }
   // Partials at most half of X's bytes, at least one chunk per 256 rows
   // of work; one 1024-thread block per CU with a single slice (one wave of
   // blocks), about 512 blocks in all with several.
-  int64_t nch = w->nslices == 1 ? 256 : std::max<int64_t>(1, 512 / w->nslices);
+  int64_t nch = w->dslices ? std::max<int64_t>(8, 256 / w->dslices)
+                           : (w->nslices == 1 ? 256 : std::max<int64_t>(1, 512 / w->nslices));
   nch = std::min<int64_t>(nch, std::max<int64_t>(1, M / (4 * N)));
   nch = std::min<int64_t>(nch, std::max<int64_t>(1, (M + 255) / 256));
   w->nchunks = (int)nch;
@@ -167,6 +202,28 @@ int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const f
                int64_t N, float* C_out, int32_t* counts, int mode, double g2, const AfpWs& w,
                hipStream_t s, Ctl ctl, CbPair cbp, int on_grid) {
   const bool vec = (L % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  if (w.dslices) {
+    const dim3 grid((unsigned)(w.nchunks * w.dslices));
+    const size_t lds = accd_lds_bytes(N);
+#define LBG_ACCD(GEN, VV)                                                                       \
+    {                                                                                           \
+      static const hipError_t a = hipFuncSetAttribute(                                          \
+          reinterpret_cast<const void*>(&accd_kernel<GEN, VV>),                                 \
+          hipFuncAttributeMaxDynamicSharedMemorySize, kAccdLdsMax);                              \
+      LBG_TRY_HIP(a);                                                                           \
+      hipLaunchKernelGGL((accd_kernel<GEN, VV>), grid, dim3(kDsThreads), lds, s, X, M, (int)L,  \
+                         idx, (int)N, w.nchunks, w.dslices, w.rows_per_chunk, w.shift, w.part,  \
+                         w.pcnt, w.lo, ctl);                                                    \
+    }
+    if (on_grid != 1) {
+      if (vec) LBG_ACCD(true, true) else LBG_ACCD(true, false)
+    } else {
+      if (vec) LBG_ACCD(false, true) else LBG_ACCD(false, false)
+    }
+#undef LBG_ACCD
+    LBG_TRY_HIP(hipGetLastError());
+    return launch_fin(X, M, L, C_old, N, C_out, counts, mode, g2, w, s, ctl, cbp);
+  }
   const int VW = vec ? 4 : 1;
   const int lanes = (int)((L + VW - 1) / VW);
   int G = 1;
@@ -196,6 +253,15 @@ int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const f
   }
 #undef LBG_ACC
   LBG_TRY_HIP(hipGetLastError());
+  return launch_fin(X, M, L, C_old, N, C_out, counts, mode, g2, w, s, ctl, cbp);
+}
+
+int launch_fin(const float* X, int64_t M, int64_t L, const float* C_old, int64_t N,
+               float* C_out, int32_t* counts, int mode, double g2, const AfpWs& w,
+               hipStream_t s, Ctl ctl, CbPair cbp) {
+  (void)X;
+  (void)M;
+  const int n = (int)N, Li = (int)L;
   if (mode == 0)
     hipLaunchKernelGGL(fin_kernel<0>, dim3((unsigned)N), dim3(kT), 0, s, w.part, w.pcnt,
                        w.nchunks, n, Li, w.shift, C_old, C_out, counts, g2, w.lo, ctl, cbp);

@@ -511,3 +511,22 @@ def test_train_statistics(P):
         assert st["near_tie_rows"] == int(((d2 - d1) < 1e-6 * xx).sum())
         _, _, _, st0 = P.train(dev(X), N)
         assert st0["near_tie_rows"] == -1 and st0["empty_cells"] == st["empty_cells"]
+
+
+def test_update_dimension_slices_misaligned(P):
+    # N = 1024, L = 64: the cells' sums are formed in 16-dimension slices;
+    # X 16-byte aligned (vector loads) and offset by one float (scalar loads)
+    rng = np.random.default_rng(77)
+    M, L, n = 20000, 64, 1024
+    X = np.rint(_gmm(3, M, L, 8)).astype(np.float32)
+    idx = rng.integers(0, n - 5, size=M).astype(np.int32)
+    C_old = rng.normal(size=(n, L)).astype(np.float32)
+    want, cnt = oracle.update(X, idx, C_old.astype(np.float64), store_fp32=True)
+    flat = torch.empty(M * L + 1, dtype=torch.float32, device="cuda")
+    Xm = flat[1:].view(M, L)
+    Xm.copy_(dev(X))
+    assert Xm.data_ptr() % 16 != 0
+    for Xd in (dev(X), Xm):
+        C_new, counts = P.update(Xd, dev(idx), dev(C_old))
+        np.testing.assert_array_equal(host(counts), cnt)
+        np.testing.assert_array_equal(host(C_new), want.astype(np.float32))
