@@ -223,7 +223,7 @@ def form_precision(args):
     """Precision form at the 8x8-block workload: M = 4,194,304 vectors of
     L = 64 from 256 synthetic 1024 x 1024 images, N = 1024 initial
     codevectors = distinct training vectors, 10 Lloyd iterations in exact FP32
-    and with the BF16 screen + FP64 top-2 rescore; errors against the FP64
+    and with the BF16 screen + FP32 top-2 rescore; errors against the FP64
     oracle on a 65,536-vector subsample."""
     import torch
     import oracle
@@ -242,7 +242,7 @@ def form_precision(args):
     C0d = torch.from_numpy(np.ascontiguousarray(C0)).to(dev)
     stream = torch.cuda.Stream(device=dev)
     out = {"metric": "precision form: allocation vector-codeword distances/s, BF16 screen + "
-                     "FP64 top-2 rescore vs exact FP32",
+                     "FP32 top-2 rescore vs exact FP32",
            "unit": "distances/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
            "config": {"workload": f"img{n_img}x1024x1024_b8_M{M}_L{L}_N{N}_10iters",
                       "M": M, "L": L, "N": N, "iterations": 10}}
@@ -669,11 +669,12 @@ def main():
         upd_bytes = ev["updates"] * M * (4 * L + 4)
         upd_gbs = upd_bytes / (ev["ms_update"] / 1e3) / 1e9 if ev["ms_update"] > 0 else None
         if name == "bf16":
-            kern = "assign_kernel<Bf16Screen<64>, vector loads, 8 waves> (BF16 screen + FP64 top-2 rescore)"
+            kern = ("bf16v2_kernel<64, vector loads> (BF16 screen, codebook resident in LDS, "
+                    "8 waves per CU, two 32-vector tiles per wave; FP32 top-2 rescore)")
             peak, basis = PEAK_BF16_MFMA_TFLOPS, "BF16 dense MFMA peak, 2L flops per distance"
             tr = measured_traffic(TRAFFIC_FILE_BF16, BF16_SOURCES)
         else:
-            kern = "assign_kernel<Bf16x3Screen<64>, vector loads, 8 waves> (exact)"
+            kern = "assign_kernel<Bf16x3Screen<64>, vector loads, 4 waves> (exact)"
             peak, basis = PEAK_BF16_MFMA_TFLOPS, ("BF16 dense MFMA peak (the exact screen "
                                                   "contracts BF16 parts), 2L flops per distance")
             tr = measured_traffic(TRAFFIC_FILE_FP32, FP32_SOURCES)
@@ -698,7 +699,7 @@ def main():
     el, tot, ev, last = forms[head]
     rl, upd = roofline(head)
     out = {
-        "metric": "LBG iteration vector-codeword distances/s (BF16 screen + FP64 top-2 "
+        "metric": "LBG iteration vector-codeword distances/s (BF16 screen + FP32 top-2 "
                   "rescore; exact FP32-accurate form and its ratio beside it)",
         "value": tot["dist"] / el,
         "unit": "distances/s",
@@ -716,7 +717,7 @@ def main():
             "M": M, "L": L, "N": N, "images": n_img, "image_size": [1024, 1024], "block": 8,
             "init": "1024 distinct training vectors, default_rng(1000) permutation",
             "lloyd_iterations_per_step": iters,
-            "precision": ("BF16 distances with FP32 accumulation, top-2 rescored in FP64"
+            "precision": ("BF16 distances with FP32 accumulation, top-2 rescored in FP32"
                           if head == "bf16" else "exact (FP32-accurate screen, FP64 certificate)"),
         },
         "roofline": rl,

@@ -119,9 +119,12 @@ int lbg_centroid(const float* X, int64_t M, int64_t L, float* c0, void* ws,
  * Codebooks of at most 8 codevectors (L <= 32) are searched directly in
  * FP64.  The result equals the FP64 direct-form argmin exactly.
  * precision == LBG_BF16_RESCORE: the screen runs in BF16 with FP32
- * accumulation; the two best candidates are rescored in FP64 and the
- * closer one (lowest index on ties) is taken.  Approximate: a row whose
- * true nearest codevector is not among the BF16 top two can be misassigned.
+ * accumulation; the two best candidates are rescored in the direct form and
+ * the closer one (lowest index on ties) is taken: in FP32 for codebooks of
+ * up to 64 dimensions whose BF16 copy fits one CU's LDS (N (L + 8) 2 bytes
+ * <= 160 KiB, L rounded up to 16, 32 or 64), in FP64 otherwise.
+ * Approximate: a row whose true nearest codevector is not among the BF16 top
+ * two can be misassigned.
  */
 int lbg_assign(const float* X, int64_t M, int64_t L, const float* C, int64_t N,
                int32_t* idx, float* mind, int precision, void* ws,

@@ -165,25 +165,19 @@ __device__ __forceinline__ void lane_top2(const float (&mn)[16], uint32_t lowmas
   i2 = (int)((__float_as_uint(k2) & lowmask) << 5) + 8 * (r2 >> 2) + 4 * h + (r2 & 3);
 }
 
-// Rescore and store the 32 vectors of one tile (rows row0 .. row0+31):
-// candidates from the slot keys, FP32 direct-form distances (lane (j, 0)
-// sums the first half of the dimensions, lane (j, 1) the second; the two
-// halves are added), the closer taken.  Returns the winning distance in lane
-// (j, 1) (0 elsewhere and past M).
-template <int LP, bool VEC>
-__device__ __forceinline__ float finish_tile(const float (&mn)[16], const float* __restrict__ X,
-                                             int64_t M, int L, const float* __restrict__ C,
-                                             int n, int64_t row0, uint32_t lowmask,
-                                             int32_t* __restrict__ idx,
-                                             float* __restrict__ mind) {
-  constexpr int H = LP / 2;
-  const int lane = threadIdx.x & 63;
-  const int h = lane >> 5, j = lane & 31;
+// Candidates of the 32 vectors of one tile: the smallest and the second
+// smallest of the four keys a vector's two lanes hold (lower index first on
+// equal keys).  w2 == w1 when there is no second candidate.
+struct Cands {
+  int w1, w2;
+  bool two;
+};
+
+__device__ __forceinline__ Cands tile_cands(const float (&mn)[16], uint32_t lowmask, int h,
+                                            int n) {
   float k1, k2;
   int i1, i2;
   lane_top2(mn, lowmask, h, k1, i1, k2, i2);
-  // merge with the partner lane: the smallest and the second smallest of
-  // the four (lower index first on equal keys)
   float a1, b1, a2, b2;
   int ai1, bi1, ai2, bi2;
   pair_values(k1, a1, b1);
@@ -191,22 +185,35 @@ __device__ __forceinline__ float finish_tile(const float (&mn)[16], const float*
   pair_values(i1, ai1, bi1);
   pair_values(i2, ai2, bi2);
   const bool aw = a1 < b1 || (a1 == b1 && ai1 < bi1);
-  int w1 = aw ? ai1 : bi1;
-  int w2;
+  Cands c;
+  c.w1 = aw ? ai1 : bi1;
   if (aw) {
     const bool s = a2 < b1 || (a2 == b1 && ai2 < bi1);
-    w2 = s ? ai2 : bi1;
+    c.w2 = s ? ai2 : bi1;
   } else {
     const bool s = b2 < a1 || (b2 == a1 && bi2 < ai1);
-    w2 = s ? bi2 : ai1;
+    c.w2 = s ? bi2 : ai1;
   }
-  if ((unsigned)w1 >= (unsigned)n) w1 = 0;  // non-finite keys
-  const bool two = (unsigned)w2 < (unsigned)n && w2 != w1;
-  if (!two) w2 = w1;
-  float xv[H], ca[H], cb[H];
-  load_x<LP, VEC>(X, M, L, row0, h, j, xv);
-  c_half<Bf16Screen<LP>, VEC>(C, L, nullptr, w1, h, ca);
-  c_half<Bf16Screen<LP>, VEC>(C, L, nullptr, w2, h, cb);
+  if ((unsigned)c.w1 >= (unsigned)n) c.w1 = 0;  // non-finite keys
+  c.two = (unsigned)c.w2 < (unsigned)n && c.w2 != c.w1;
+  if (!c.two) c.w2 = c.w1;
+  return c;
+}
+
+// FP32 direct-form distances of one tile's vectors to their two candidates
+// (lane (j, 0) sums the first half of the dimensions, lane (j, 1) the
+// second; the halves are added), the closer taken and stored for rows
+// row0 .. row0+31.  xv: the lane's FP32 half-row (zeros past M and L); ca,
+// cb: the candidates' half-rows.  Returns the winning distance in lane
+// (j, 1) (0 elsewhere and past M).
+template <int LP>
+__device__ __forceinline__ float rescore_tile(const float (&xv)[LP / 2], const float (&ca)[LP / 2],
+                                              const float (&cb)[LP / 2], Cands c, int64_t M,
+                                              int L, int64_t row0, int32_t* __restrict__ idx,
+                                              float* __restrict__ mind) {
+  constexpr int H = LP / 2;
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5, j = lane & 31;
   float pa = 0.0f, pb = 0.0f;
 #pragma unroll
   for (int q = 0; q < H; ++q) {
@@ -221,10 +228,10 @@ __device__ __forceinline__ float finish_tile(const float (&mn)[16], const float*
   pair_values(pb, pb0, pb1);
   float d = pa0 + pa1;
   const float db = pb0 + pb1;
-  int win = w1;
-  if (two && (db < d || (db == d && w2 < w1))) {
+  int win = c.w1;
+  if (c.two && (db < d || (db == d && c.w2 < c.w1))) {
     d = db;
-    win = w2;
+    win = c.w2;
   }
   if (!(d < INFINITY)) {  // no finite distance: index 0, +inf
     win = 0;
@@ -276,8 +283,10 @@ __global__ __launch_bounds__(kV2Threads, 1) void bf16v2_kernel(
   const int64_t ngroups = (M + 63) >> 6;
   const int64_t step = (int64_t)gridDim.x * kV2Waves;
   int64_t g = (int64_t)blockIdx.x * kV2Waves + wave;
-  // FP32 half-rows of the group's two vector tiles, loaded one group ahead
-  // (while the previous group finishes)
+  // FP32 half-rows of the group's two vector tiles: loaded while the
+  // previous group finishes, converted to BF16 for the screen and (HOLD)
+  // kept for the rescore
+  constexpr bool HOLD = VEC || LP < 64;
   float pa[LP / 2], pb[LP / 2];
   if (g < ngroups) {
     load_x<LP, VEC>(X, M, L, g * 64, h, j, pa);
@@ -319,18 +328,34 @@ __global__ __launch_bounds__(kV2Threads, 1) void bf16v2_kernel(
       keys1(a0, ma, vmask, (uint32_t)t, ninf);
       keys1(b0, mb, vmask, (uint32_t)t, ninf);
     }
-    if (g + step < ngroups) {
-      load_x<LP, VEC>(X, M, L, (g + step) * 64, h, j, pa);
-      load_x<LP, VEC>(X, M, L, (g + step) * 64 + 32, h, j, pb);
+    // rescore from the held rows (the unaligned LP = 64 form reloads them:
+    // holding them there would spill)
+    if (!HOLD) {
+      load_x<LP, VEC>(X, M, L, row0, h, j, pa);
+      load_x<LP, VEC>(X, M, L, row0 + 32, h, j, pb);
     }
-    const float da = finish_tile<LP, VEC>(ma, X, M, L, C, n, row0, lowmask, idx, mind);
-    const float db =
-        finish_tile<LP, VEC>(mb, X, M, L, C, n, row0 + 32, lowmask, idx, mind);
+    // both tiles' candidates first, then all four gathers in one round
+    const Cands qa = tile_cands(ma, lowmask, h, n), qb = tile_cands(mb, lowmask, h, n);
+    float caa[LP / 2], cab[LP / 2], cba[LP / 2], cbb[LP / 2];
+    c_half<SC, VEC>(C, L, nullptr, qa.w1, h, caa);
+    c_half<SC, VEC>(C, L, nullptr, qa.w2, h, cab);
+    c_half<SC, VEC>(C, L, nullptr, qb.w1, h, cba);
+    c_half<SC, VEC>(C, L, nullptr, qb.w2, h, cbb);
+    // the next group's rows are loaded into each tile's registers once its
+    // rescore is done: issued after the gathers, so that waiting for the
+    // gathers (loads complete in order) does not wait for them
+    const bool more = g + step < ngroups;
+    const float da = rescore_tile<LP>(pa, caa, cab, qa, M, L, row0, idx, mind);
+    if (more) load_x<LP, VEC>(X, M, L, (g + step) * 64, h, j, pa);
+    const float db = rescore_tile<LP>(pb, cba, cbb, qb, M, L, row0 + 32, idx, mind);
+    if (more) load_x<LP, VEC>(X, M, L, (g + step) * 64 + 32, h, j, pb);
     // distortion partials of the two 32-vector groups (FP64, fixed tree)
-    const double sa = wave_sum((double)da), sb = wave_sum((double)db);
-    if (dpart && lane == 0) {
-      if (row0 < M) dpart[row0 >> 5] = sa;
-      if (row0 + 32 < M) dpart[(row0 >> 5) + 1] = sb;
+    if (dpart) {
+      const double sa = wave_sum((double)da), sb = wave_sum((double)db);
+      if (lane == 0) {
+        if (row0 < M) dpart[row0 >> 5] = sa;
+        if (row0 + 32 < M) dpart[(row0 >> 5) + 1] = sb;
+      }
     }
   }
 }
