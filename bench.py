@@ -153,6 +153,19 @@ def form_batched(args):
     upd_bytes = sum(r[3]["n_update"] * M * (4.0 * L + 4.0) for M, L, r in zip(Ms, Ls, res_t))
     tf = flops / (st_t["ms_assign"] * 1e-3) / 1e12
     gbs = upd_bytes / (st_t["ms_update"] * 1e-3) / 1e9
+    # per-instance roofline: each instance's allocations take at least the
+    # longer of its flops at the FP32 MFMA peak (2L per distance, the
+    # arithmetic the allocation resolves) and its bytes at the HBM peak (X
+    # read and idx written per allocation); its updates at least their bytes
+    # at the HBM peak.  The bound is the sum over instances.
+    t_alloc = 0.0
+    t_upd = 0.0
+    for M, L, r in zip(Ms, Ls, res_t):
+        info = r[3]
+        f_i = 2.0 * L * info["distances"]
+        b_i = info["n_assign"] * M * (4.0 * L + 4.0)
+        t_alloc += max(f_i / (PEAK_FP32_MFMA_TFLOPS * 1e12), b_i / (PEAK_HBM_GBS * 1e9))
+        t_upd += info["n_update"] * M * (4.0 * L + 4.0) / (PEAK_HBM_GBS * 1e9)
     # one lbg_train per instance, same data, same GPU
     ws = None
     for X, N in zip(Xs[:2], Ns[:2]):
@@ -182,11 +195,17 @@ def form_batched(args):
                    "rounds": st["rounds"]},
         "allocation_roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_FP32_MFMA_TFLOPS,
                                 "unit": "TFLOP/s", "frac": tf / PEAK_FP32_MFMA_TFLOPS,
-                                "ms_all_rounds": st_t["ms_assign"]},
+                                "ms_all_rounds": st_t["ms_assign"],
+                                "per_instance_bound_ms": t_alloc * 1e3,
+                                "frac_per_instance": t_alloc * 1e3 / st_t["ms_assign"],
+                                "per_instance_basis": "sum_i max(2 L_i distances_i / FP32 MFMA "
+                                                      "peak, n_assign_i M_i (4 L_i + 4) / HBM peak)"},
         "update_roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
                             "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
                             "ms_all_rounds": st_t["ms_update"],
-                            "algorithmic_bytes": upd_bytes},
+                            "algorithmic_bytes": upd_bytes,
+                            "per_instance_bound_ms": t_upd * 1e3,
+                            "frac_per_instance": t_upd * 1e3 / st_t["ms_update"]},
         "per_instance_launches": {"value": dist / t_s, "ms_total": t_s * 1e3},
         "speedup_vs_per_instance": t_s / t_b,
         "identical_D_to_per_instance": f"{same}/{len(inst)}",

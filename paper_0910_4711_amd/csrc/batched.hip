@@ -140,6 +140,99 @@ __device__ __forceinline__ void alloc_chunk(const BInst& B, const DevState* st, 
   }
 }
 
+// Slots [b0, b0 + cnt) of instance B by direct FP64 search, for codebooks of
+// at most kDirectN codevectors: per vector the FP64 squared distances in
+// dimension order, the first smallest kept, and the partial of each 32
+// vectors by the 32-lane butterfly of the single-run kernel's direct path.
+// These are the screened path's numbers bit for bit (its FP64 rescore chains
+// the same operations in the same order), so the choice changes no result.
+// The two halves of a wave take consecutive tiles of the chunk's sequence
+// (slot b's tiles b, b + G, ..., then slot b + 1's), 32 vectors each.  XD:
+// the row is converted to FP64 once (registers) rather than per codevector.
+template <int LP, bool VEC, bool XD>
+__device__ __forceinline__ void direct_chunk(const BInst& B, const DevState* st, int b0, int cnt,
+                                             int i, int* staged, unsigned char* smem) {
+  const int n = st->n, cb = st->cb;
+  const float* C = B.Cb[cb];
+  const int L = VEC ? LP : B.L;
+  double* sC = reinterpret_cast<double*>(smem);
+  // the FP64 layout: never a screen layout's key (>= 0) nor "nothing staged" (-1)
+  const int key = -2 - ((i << 1) | cb);
+  if (*staged != key) {
+    __syncthreads();  // the previous chunk's waves are done with the LDS copy
+    for (int e = threadIdx.x; e < n * LP; e += kT) {
+      const int k = e / LP, l = e - k * LP;
+      sC[e] = l < L ? (double)C[(int64_t)k * L + l] : 0.0;
+    }
+    __syncthreads();
+    *staged = key;
+  }
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int half = lane >> 5, j = lane & 31;
+  const int G = B.G;
+  const int64_t nt = B.ntiles;
+  const int bend = b0 + cnt;
+  int b = b0;
+  int64_t rt = b0;
+  auto advance = [&]() {
+    rt += G;
+    if (rt >= nt) {
+      ++b;
+      rt = b;
+    }
+  };
+  if (half) advance();
+  for (;;) {
+    const bool valid = b < bend;
+    const int64_t row0 = rt * kRowsPerTile + (int64_t)wave * 32;
+    const int64_t m = row0 + j;
+    const bool live = valid && m < B.M;
+    float xr[LP];
+    if (live) {
+      load_row<LP, VEC>(B.X + m * (int64_t)L, L, xr);
+    } else {
+#pragma unroll
+      for (int q = 0; q < LP; ++q) xr[q] = 0.0f;
+    }
+    double xd[XD ? LP : 1];
+    if constexpr (XD) {
+#pragma unroll
+      for (int q = 0; q < LP; ++q) xd[q] = (double)xr[q];
+    }
+    double best = INFINITY;
+    int bi = 0x7fffffff;
+    for (int k = 0; k < n; ++k) {
+      const double* c = sC + k * LP;
+      double dk = 0.0;
+#pragma unroll
+      for (int l = 0; l < LP; ++l) {
+        if (l < L) {
+          const double t = (XD ? xd[l] : (double)xr[l]) - c[l];
+          dk = dk + t * t;
+        }
+      }
+      if (dk < best) {
+        best = dk;
+        bi = k;
+      }
+    }
+    if (!(best < INFINITY)) bi = 0;  // no finite distance: index 0
+    if (live) B.idx[m] = bi;
+    double v = live ? best : 0.0;
+    v += xor_lane<1>(v);
+    v += xor_lane<2>(v);
+    v += xor_lane<4>(v);
+    v += xor_lane<8>(v);
+    v += xor_lane<16>(v);
+    if (j == 0 && valid && row0 < B.M) B.dpart[row0 >> 5] = v;
+    advance();
+    advance();
+    // half 0 holds the earlier tile: the wave is done when it has none
+    if (__builtin_amdgcn_readfirstlane(b) >= bend) break;
+  }
+}
+
 // Persistent: workgroups take chunks (instance, first slot, slot count) from
 // the queue until none is left.
 __global__ __launch_bounds__(kT, 2) void b_assign_kernel(const BInst* __restrict__ inst,
@@ -158,6 +251,20 @@ __global__ __launch_bounds__(kT, 2) void b_assign_kernel(const BInst* __restrict
     const BInst& B = inst[i];
     const DevState* st = B.st;
     if (st->done) continue;
+    if (st->n <= kDirectN) {
+      if (B.LP == 16) {
+        if (B.vec)
+          direct_chunk<16, true, true>(B, st, b0, cnt, i, &staged, smem);
+        else
+          direct_chunk<16, false, true>(B, st, b0, cnt, i, &staged, smem);
+      } else {
+        if (B.vec)
+          direct_chunk<64, true, false>(B, st, b0, cnt, i, &staged, smem);
+        else
+          direct_chunk<64, false, false>(B, st, b0, cnt, i, &staged, smem);
+      }
+      continue;
+    }
     if (B.LP == 16) {
       if (B.vec)
         alloc_chunk<Fp32Screen<16>, true>(B, st, b0, cnt, i, &staged, smem);
@@ -257,6 +364,7 @@ __global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ ins
   // A cell beyond the codebook this round updates or splits has nothing to
   // do in any case (and a finished run does nothing at all); only cell 0
   // commits the state.  Such workgroups leave before loading partials.
+  if (B.st->done) return;  // finished in an earlier round: nothing left to commit
   if (k != 0 && k >= B.pend->n_src) return;
   const Ctl ctl{B.st, B.pend, B.dpart, (B.M + 31) / 32, B.Dtrace, B.Atrace};
   const CbPair cbp{{B.Cb[0], B.Cb[1]}};
@@ -419,7 +527,7 @@ void plan_batch(Carver& c, const lbg_instance* in, int n, BatchWs* w) {
     q.cpart = c.take<double>((size_t)(q.cnwg * L));
     q.Dtrace = c.take<double>(kBatchTrace);
     q.Atrace = c.take<int32_t>(kBatchTrace);
-    plan_afp(c, M, L, N, &q.afp, false);
+    plan_afp(c, M, L, N, &q.afp, false, true);
   }
   for (int k = 0; k < kNumPre; ++k) w->tot[k] = 0;
   for (int i = 0; i < n; ++i) {

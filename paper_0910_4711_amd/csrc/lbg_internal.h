@@ -137,7 +137,8 @@ struct AfpWs {
 };
 bool afp_usable(int64_t L, int64_t N);
 // dslices: the single-run kernels may accumulate by dimension slices
-void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices = true);
+void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices = true,
+              bool many = false);
 int launch_afp_shift(const float* X, int64_t M, int64_t L, const AfpWs& w, hipStream_t s);
 // The finishing kernel of the update (centroids or gradient from the partials).
 int launch_fin(const float* X, int64_t M, int64_t L, const float* C_old, int64_t N,

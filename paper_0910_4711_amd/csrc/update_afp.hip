@@ -155,7 +155,7 @@ void launch_acc(dim3 grid, size_t lds, hipStream_t st, const float* X, int64_t M
 
 }  // namespace
 
-void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices) {
+void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices, bool many) {
   w->cps = (int)std::min<int64_t>(std::min<int64_t>(N, 8192), kLdsBytes / (8 * (L + 1) + 4) - 1);
   w->nslices = (int)((N + w->cps - 1) / w->cps);
   // Dimension slices instead of several cell slices when all cells fit one
@@ -173,6 +173,12 @@ void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices
                            : (w->nslices == 1 ? 256 : std::max<int64_t>(1, 512 / w->nslices));
   nch = std::min<int64_t>(nch, std::max<int64_t>(1, M / (4 * N)));
   nch = std::min<int64_t>(nch, std::max<int64_t>(1, (M + 255) / 256));
+  if (many) {
+    // one of many instances updated together: the others fill the GPU, so
+    // chunks of at least 2048 rows and partials at most 1/16 of X's bytes
+    nch = std::min<int64_t>(nch, std::max<int64_t>(1, M / (32 * N)));
+    nch = std::min<int64_t>(nch, std::max<int64_t>(1, M / 2048));
+  }
   w->nchunks = (int)nch;
   w->rows_per_chunk = (M + nch - 1) / nch;
   w->absmax_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (M * L + 4095) / 4096));
