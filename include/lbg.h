@@ -355,13 +355,19 @@ typedef struct lbg_instance {
  * hipGraph (non-NULL streams), else launches them directly;
  * rounds_per_poll: rounds between host checks of the finished count
  * (direct launches); timing != 0: direct launches with an event pair around
- * every round's allocation and update (their sums in lbg_batch_stats). */
+ * every round's allocation and update (their sums in lbg_batch_stats).
+ * screen: the allocation's screen for codebooks of more than 8 codevectors
+ * (0 = chosen by the autotuner with grab and grid, 1 = FP32 screen, 2 = the
+ * split BF16 screen wherever its codebook layout fits the workgroup's LDS,
+ * the FP32 screen elsewhere).  Every choice gives the exact FP64 allocation,
+ * so results do not depend on it. */
 typedef struct lbg_batch_config {
   int32_t grab;
   int32_t grid;
   int32_t graph;
   int32_t rounds_per_poll;
   int32_t timing;
+  int32_t screen;
 } lbg_batch_config;
 
 void lbg_batch_config_default(lbg_batch_config* cfg);
@@ -387,6 +393,7 @@ typedef struct lbg_batch_stats {
   double ms_tune;   /* time spent timing candidates */
   double ms_assign; /* with timing: all rounds' allocation launches */
   double ms_update; /* with timing: all rounds' update launches */
+  int32_t screen;   /* screen used: 1 FP32, 2 split BF16 (where it fits) */
 } lbg_batch_stats;
 
 /* Workspace bytes for lbg_train_batched on these instances (0 on bad

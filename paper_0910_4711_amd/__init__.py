@@ -104,6 +104,7 @@ class BatchConfig(ct.Structure):
         ("graph", ct.c_int32),
         ("rounds_per_poll", ct.c_int32),
         ("timing", ct.c_int32),
+        ("screen", ct.c_int32),
     ]
 
 
@@ -130,6 +131,7 @@ class BatchStats(ct.Structure):
         ("ms_tune", ct.c_double),
         ("ms_assign", ct.c_double),
         ("ms_update", ct.c_double),
+        ("screen", ct.c_int32),
     ]
 
 
@@ -518,13 +520,14 @@ def train(X, N, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta=0.0,
 
 def train_batched(Xs, Ns, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta=0.0,
                   max_iter=1000, fixed_iters=0, grab=0, grid=0, graph=True,
-                  rounds_per_poll=8, workspace=None, timing=False):
+                  rounds_per_poll=8, workspace=None, timing=False, screen=0):
     """Independent LBG runs (Algorithm 1 on every instance) advanced together
     by the batched kernels.  Xs: list of [M_i x L_i] float32 device tensors,
     Ns: list of powers of two.  Returns (results, stats): results[i] =
     (C_i, idx_i, D_i, info_i), each bit-identical to train(Xs[i], Ns[i]).
     timing: direct launches with events around every round's allocation and
-    update (stats ms_assign, ms_update)."""
+    update (stats ms_assign, ms_update).  screen: 0 autotuned, 1 FP32, 2
+    split BF16 where it fits (the same results either way)."""
     if len(Xs) != len(Ns) or len(Xs) == 0:
         raise ValueError("need as many codebook sizes as training sets (at least one)")
     Xs = [_f32_2d(f"Xs[{i}]", X) for i, X in enumerate(Xs)]
@@ -551,6 +554,7 @@ def train_batched(Xs, Ns, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta
     cfg.grab, cfg.grid, cfg.graph = int(grab), int(grid), 1 if graph else 0
     cfg.rounds_per_poll = int(rounds_per_poll)
     cfg.timing = 1 if timing else 0
+    cfg.screen = int(screen)
     nb = lib.lbg_train_batched_workspace(inst, n)
     if nb == 0:
         raise LBGError("lbg_train_batched_workspace: bad instances")
@@ -574,7 +578,7 @@ def train_batched(Xs, Ns, thr=1e-3, eps_split=0.01, split_mode=SPLIT_MULT, delta
                                           distances=r.distances)))
     stats = dict(status=rc, rounds=st.rounds, grab=st.grab, grid=st.grid, graph=st.graph,
                  tuned=st.tuned, total_distances=st.total_distances, ms_tune=st.ms_tune,
-                 ms_assign=st.ms_assign, ms_update=st.ms_update)
+                 ms_assign=st.ms_assign, ms_update=st.ms_update, screen=st.screen)
     return results, stats
 
 

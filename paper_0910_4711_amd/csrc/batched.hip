@@ -101,7 +101,7 @@ __device__ __forceinline__ void alloc_chunk(const BInst& B, const DevState* st, 
   const float* C = B.Cb[cb];
   const int n_pad = (n + 31) & ~31;
   const int L = VEC ? LP : B.L;
-  const int key = (i << 1) | cb;
+  const int key = (((i << 1) | cb) << 1) | (SC::SPLIT ? 1 : 0);
   if (*staged != key) {
     __syncthreads();  // the previous chunk's waves are done with the LDS copy
     stage_from_C<SC, VEC>(C, n, L, n_pad, sA);
@@ -233,11 +233,30 @@ __device__ __forceinline__ void direct_chunk(const BInst& B, const DevState* st,
   }
 }
 
+// Split screen for the current codebook: chosen (split != 0) and its row
+// layout fits the workgroup's LDS.
+template <int LP>
+__device__ __forceinline__ bool split_fits(int n) {
+  const int n_pad = (n + 31) & ~31;
+  return n_pad * Bf16x3Screen<LP>::S * Bf16x3Screen<LP>::ESZ <= kBatchLds;
+}
+
 // Persistent: workgroups take chunks (instance, first slot, slot count) from
-// the queue until none is left.
+// the queue until none is left.  Two builds, each with its own queue:
+//   SPLIT = false: codebooks of at most kDirectN codevectors (direct search)
+//     and, unless ``split``, every other codebook with the FP32 screen;
+//   SPLIT = true (launched only when ``split``): the codebooks whose split
+//     BF16 screen layout fits the workgroup's LDS.
+// With ``split`` each build skips the other's chunks, so every chunk is
+// allocated once per round.  The split screen is FP32-accurate with the same
+// exact certificate as the FP32 screen: the allocation and partials are the
+// same whichever build takes a chunk.  (One kernel holding both screens spills
+// registers; two keep each at the single-run kernel's register use.)
+template <bool SPLIT>
 __global__ __launch_bounds__(kT, 2) void b_assign_kernel(const BInst* __restrict__ inst,
                                                          const int32_t* __restrict__ chunks,
-                                                         int nchunks, unsigned* __restrict__ qctr) {
+                                                         int nchunks, unsigned* __restrict__ qctr,
+                                                         int split) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int s_c;
   int staged = -1;
@@ -251,7 +270,23 @@ __global__ __launch_bounds__(kT, 2) void b_assign_kernel(const BInst* __restrict
     const BInst& B = inst[i];
     const DevState* st = B.st;
     if (st->done) continue;
-    if (st->n <= kDirectN) {
+    const int n = st->n;
+    const bool direct = n <= kDirectN;
+    const bool sp = split && !direct && (B.LP == 16 ? split_fits<16>(n) : split_fits<64>(n));
+    if (sp != SPLIT) continue;  // the other build's chunk
+    if constexpr (SPLIT) {
+      if (B.LP == 16) {
+        if (B.vec)
+          alloc_chunk<Bf16x3Screen<16>, true>(B, st, b0, cnt, i, &staged, smem);
+        else
+          alloc_chunk<Bf16x3Screen<16>, false>(B, st, b0, cnt, i, &staged, smem);
+      } else {
+        if (B.vec)
+          alloc_chunk<Bf16x3Screen<64>, true>(B, st, b0, cnt, i, &staged, smem);
+        else
+          alloc_chunk<Bf16x3Screen<64>, false>(B, st, b0, cnt, i, &staged, smem);
+      }
+    } else if (direct) {
       if (B.LP == 16) {
         if (B.vec)
           direct_chunk<16, true, true>(B, st, b0, cnt, i, &staged, smem);
@@ -263,52 +298,97 @@ __global__ __launch_bounds__(kT, 2) void b_assign_kernel(const BInst* __restrict
         else
           direct_chunk<64, false, false>(B, st, b0, cnt, i, &staged, smem);
       }
-      continue;
-    }
-    if (B.LP == 16) {
-      if (B.vec)
-        alloc_chunk<Fp32Screen<16>, true>(B, st, b0, cnt, i, &staged, smem);
-      else
-        alloc_chunk<Fp32Screen<16>, false>(B, st, b0, cnt, i, &staged, smem);
     } else {
-      if (B.vec)
-        alloc_chunk<Fp32Screen<64>, true>(B, st, b0, cnt, i, &staged, smem);
-      else
-        alloc_chunk<Fp32Screen<64>, false>(B, st, b0, cnt, i, &staged, smem);
+      if (B.LP == 16) {
+        if (B.vec)
+          alloc_chunk<Fp32Screen<16>, true>(B, st, b0, cnt, i, &staged, smem);
+        else
+          alloc_chunk<Fp32Screen<16>, false>(B, st, b0, cnt, i, &staged, smem);
+      } else {
+        if (B.vec)
+          alloc_chunk<Fp32Screen<64>, true>(B, st, b0, cnt, i, &staged, smem);
+        else
+          alloc_chunk<Fp32Screen<64>, false>(B, st, b0, cnt, i, &staged, smem);
+      }
     }
   }
 }
 
 // ----------------------------------------------------------------- update --
-__global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ inst, int n_inst,
-                                                   const int64_t* __restrict__ pre, Tabs tb) {
-  extern __shared__ unsigned long long sacc[];
-  __shared__ int32_t slist[afp::kSel];
-  __shared__ int32_t snsel;
-  const int64_t* acc_pre = pre + (int64_t)kPreAcc * (n_inst + 1);
-  if ((int64_t)blockIdx.x >= acc_pre[n_inst]) return;
-  const int i = tb.b2i[tb.off[kPreAcc] + blockIdx.x];
-  const BInst& B = inst[i];
-  const int64_t local = (int64_t)blockIdx.x - acc_pre[i];
+// The round's finish work list: the cells of every instance still running
+// (st[i].done clear) below the pending state's n_src, at least cell 0 (which
+// commits the state), compacted; b_fin walks it.  One workgroup of 1024
+// threads, run after the decisions (b_acc) are made.  st, pend: the
+// instances' states, contiguous.  list[item] = instance, first[i] = its first
+// item, *total = the number of items.
+__global__ __launch_bounds__(1024) void b_list_kernel(const DevState* __restrict__ st,
+                                                     const DevState* __restrict__ pend,
+                                                     const BInst* __restrict__ inst, int n_inst,
+                                                     int32_t* __restrict__ list,
+                                                     int32_t* __restrict__ first,
+                                                     int32_t* __restrict__ total) {
+  __shared__ int32_t ssum[1024];
+  __shared__ int32_t sbase;
+  const int t = threadIdx.x;
+  if (t == 0) sbase = 0;
+  for (int i0 = 0; i0 < n_inst; i0 += 1024) {
+    const int i = i0 + t;
+    int c = 0;
+    if (i < n_inst) {
+      const int done = st[i].done, n_src = pend[i].n_src, N = inst[i].N;
+      if (!done) c = max(1, min(N, n_src));
+    }
+    ssum[t] = c;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
+      const int v = t >= off ? ssum[t - off] : 0;
+      __syncthreads();
+      ssum[t] += v;
+      __syncthreads();
+    }
+    const int f = sbase + ssum[t] - c;
+    if (i < n_inst) {
+      first[i] = f;
+      for (int u = 0; u < c; ++u) list[f + u] = i;
+    }
+    __syncthreads();  // every thread has read sbase
+    if (t == 1023) sbase = f + c;
+    __syncthreads();
+  }
+  if (t == 0) *total = sbase;
+}
+
+// One workgroup's share of instance B's update: its decision (local 0),
+// then the fixed-point cell sums of row chunk x cell slice ``local``.
+__device__ __forceinline__ void acc_item(const BInst& B, int64_t local, unsigned long long* sacc,
+                                         int32_t* slist, int32_t& snsel) {
   const Ctl ctl{B.st, B.pend, B.dpart, (B.M + 31) / 32, B.Dtrace, B.Atrace};
   int N = B.N;
   if (B.st->done) return;
   if (local == 0) (void)afp::acc_decide(ctl, true, &N);  // the instance's decision
   if (forced_stop(B.st)) return;  // the level ends here: no update follows
   N = B.st->n;
+  // Slices of cps cells the current codebook needs (the launch has the final
+  // codebook's): the workgroups of the others have nothing to add, and one
+  // slice streams the rows instead of gathering them per slice.  The
+  // partials keep the planned layout (cells of slice q from q cps).
+  const int nsl = max(1, (N + B.cps - 1) / B.cps);
+  const int64_t chunk = local / B.nslices;
+  const int slice = (int)(local % B.nslices);
+  if (slice >= nsl) return;
+  const int64_t blk = chunk * nsl + slice;
   const int s = B.shift[0], tf = B.shift[1];
   const int L = B.L;
 #define LBG_BACC1(GG, VV, FF)                                                                 \
   do {                                                                                     \
-    if (B.nslices > 1)                                                                     \
-      afp::acc_body<GG, VV, 1, true, 8, kT, FF>(B.X, B.M, L, B.idx, N, B.N, B.cps,          \
-                                                B.nslices, B.rows_per_chunk, s, B.part,    \
-                                                B.pcnt, local, sacc, slist, snsel, B.lo,   \
-                                                tf);                                       \
+    if (nsl > 1)                                                                           \
+      afp::acc_body<GG, VV, 1, true, 8, kT, FF>(B.X, B.M, L, B.idx, N, B.N, B.cps, nsl,     \
+                                                B.rows_per_chunk, s, B.part, B.pcnt, blk,  \
+                                                sacc, slist, snsel, B.lo, tf);             \
     else                                                                                   \
-      afp::acc_body<GG, VV, 1, false, afp::kUnrollSel, kT, FF>(                                  \
-          B.X, B.M, L, B.idx, N, B.N, B.cps, B.nslices, B.rows_per_chunk, s, B.part,         \
-          B.pcnt, local, sacc, slist, snsel, B.lo, tf);                                     \
+      afp::acc_body<GG, VV, 1, false, afp::kUnrollSel, kT, FF>(                            \
+          B.X, B.M, L, B.idx, N, B.N, B.cps, 1, B.rows_per_chunk, s, B.part, B.pcnt, blk,   \
+          sacc, slist, snsel, B.lo, tf);                                                   \
   } while (0)
 #define LBG_BACC(GG, VV)        \
   do {                          \
@@ -349,23 +429,25 @@ __global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ ins
 #undef LBG_BACC1
 }
 
-// Block 0 also rearms the allocation queue for the next round (the round's
-// allocation has completed before this launch starts).
-__global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ inst, int n_inst,
-                                                   const int64_t* __restrict__ pre, Tabs tb,
-                                                   unsigned* __restrict__ qctr,
-                                                   unsigned* __restrict__ ndone) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *qctr = 0u;
-  const int64_t* fin_pre = pre + (int64_t)kPreFin * (n_inst + 1);
-  if ((int64_t)blockIdx.x >= fin_pre[n_inst]) return;
-  const int i = tb.b2i[tb.off[kPreFin] + blockIdx.x];
-  const BInst& B = inst[i];
-  const int k = (int)((int64_t)blockIdx.x - fin_pre[i]);
-  // A cell beyond the codebook this round updates or splits has nothing to
-  // do in any case (and a finished run does nothing at all); only cell 0
-  // commits the state.  Such workgroups leave before loading partials.
-  if (B.st->done) return;  // finished in an earlier round: nothing left to commit
-  if (k != 0 && k >= B.pend->n_src) return;
+// One workgroup per (instance, row chunk, cell slice) of every instance; the
+// workgroups of finished instances leave at once.  (A persistent form over a
+// compacted list of the running instances' workgroups measured slower: the
+// list costs a launch and the loop more registers.)
+__global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ inst, int n_inst,
+                                                   const int64_t* __restrict__ pre, Tabs tb) {
+  extern __shared__ unsigned long long sacc[];
+  __shared__ int32_t slist[afp::kSel];
+  __shared__ int32_t snsel;
+  const int64_t* acc_pre = pre + (int64_t)kPreAcc * (n_inst + 1);
+  if ((int64_t)blockIdx.x >= acc_pre[n_inst]) return;
+  const int i = tb.b2i[tb.off[kPreAcc] + blockIdx.x];
+  acc_item(inst[i], (int64_t)blockIdx.x - acc_pre[i], sacc, slist, snsel);
+}
+
+// Cell k of instance B: centroid, or split, or nothing; cell 0 commits the
+// state.  (The work list holds only cells below the pending n_src of
+// instances still running.)
+__device__ __forceinline__ void fin_item(const BInst& B, int k, unsigned* __restrict__ ndone) {
   const Ctl ctl{B.st, B.pend, B.dpart, (B.M + 31) / 32, B.Dtrace, B.Atrace};
   const CbPair cbp{{B.Cb[0], B.Cb[1]}};
   int N = B.N;
@@ -375,6 +457,27 @@ __global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ ins
         return afp::fin_state(ctl, cbp, k, k == 0, B.L, &N, c_old, dst, ndone);
       },
       B.lo, B.shift[1]);
+}
+
+// Persistent over the round's finish list (b_list_kernel).  Block 0
+// also rearms the allocation queues (qctr[0] and qctr[2]) for the next round
+// (the round's allocation has completed before this launch starts).
+__global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ inst,
+                                                   const int32_t* __restrict__ list,
+                                                   const int32_t* __restrict__ first,
+                                                   const int32_t* __restrict__ total,
+                                                   unsigned* __restrict__ qctr,
+                                                   unsigned* __restrict__ ndone) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    qctr[0] = 0u;
+    qctr[2] = 0u;
+  }
+  const int T = *total;
+  for (int item = blockIdx.x; item < T; item += gridDim.x) {
+    __syncthreads();  // the previous item is done with the LDS
+    const int i = list[item];
+    fin_item(inst[i], item - first[i], ndone);
+  }
 }
 
 // ------------------------------------------------------------- set-up, end --
@@ -469,11 +572,14 @@ struct BatchWs {
   int64_t* pre;     // kNumPre x (n + 1)
   DevState* st;     // n
   DevState* pend;   // n
-  unsigned* ctr;    // [0] allocation queue, [1] finished instances
+  unsigned* ctr;    // [0] allocation queue, [1] finished instances, [2] split queue
   unsigned long long* nfb;  // n
   int32_t* b2i;             // block -> instance tables
   int64_t b2i_n;
   int32_t* chunks;          // allocation chunks (instance, first slot, slots)
+  int32_t* fin_list;        // the round's finish work list (b_list_kernel)
+  int32_t* fin_first;       // n
+  int32_t* list_total;      // its item count
   int64_t tot[kNumPre];     // blocks (items) of each family
   std::vector<InstPlan> plans;
 };
@@ -509,7 +615,7 @@ void plan_batch(Carver& c, const lbg_instance* in, int n, BatchWs* w) {
   w->pre = c.take<int64_t>((size_t)kNumPre * (n + 1));
   w->st = c.take<DevState>((size_t)n);
   w->pend = c.take<DevState>((size_t)n);
-  w->ctr = c.take<unsigned>(2);
+  w->ctr = c.take<unsigned>(3);
   w->nfb = c.take<unsigned long long>((size_t)n);
   w->plans.resize((size_t)n);
   for (int i = 0; i < n; ++i) {
@@ -540,6 +646,9 @@ void plan_batch(Carver& c, const lbg_instance* in, int n, BatchWs* w) {
     if (k != kPreItem) w->b2i_n += w->tot[k];
   w->b2i = c.take<int32_t>((size_t)w->b2i_n);
   w->chunks = c.take<int32_t>((size_t)(3 * w->tot[kPreItem]));
+  w->fin_list = c.take<int32_t>((size_t)w->tot[kPreFin]);
+  w->fin_first = c.take<int32_t>((size_t)n);
+  w->list_total = c.take<int32_t>(1);
 }
 
 // Allocation chunks of at most ``grab`` slots, never spanning two instances,
@@ -581,21 +690,39 @@ struct Launch {
   size_t acc_lds;
   const int32_t* chunks;    // device chunk table for the current grab
   int nchunks;
+  const DevState* st;       // the instances' states (contiguous)
+  const DevState* pend;
+  int32_t* fin_list;        // finish work list (b_list_kernel)
+  int32_t* fin_first;
+  int32_t* list_total;
 };
+
+// Workgroups of the persistent finish launch: enough to fill the GPU several
+// times over, never more than the cells a round can have.
+constexpr int64_t kFinGrid = 2048;
 
 // ev (nullable): events recorded before the allocation, between it and the
 // update, and after the update.
-int launch_round(const Launch& l, int grid, hipStream_t s, hipEvent_t* ev = nullptr) {
+int launch_round(const Launch& l, int grid, int split, hipStream_t s,
+                 hipEvent_t* ev = nullptr) {
   if (ev) LBG_TRY_HIP(hipEventRecord(ev[0], s));
-  hipLaunchKernelGGL(b_assign_kernel, dim3((unsigned)grid), dim3(kT), kBatchLds, s, l.inst,
-                     l.chunks, l.nchunks, l.ctr);
+  hipLaunchKernelGGL(b_assign_kernel<false>, dim3((unsigned)grid), dim3(kT), kBatchLds, s, l.inst,
+                     l.chunks, l.nchunks, l.ctr, split);
   LBG_TRY_HIP(hipGetLastError());
+  if (split) {
+    hipLaunchKernelGGL(b_assign_kernel<true>, dim3((unsigned)grid), dim3(kT), kBatchLds, s,
+                       l.inst, l.chunks, l.nchunks, l.ctr + 2, split);
+    LBG_TRY_HIP(hipGetLastError());
+  }
   if (ev) LBG_TRY_HIP(hipEventRecord(ev[1], s));
   hipLaunchKernelGGL(b_acc_kernel, dim3((unsigned)l.blocks[kPreAcc]), dim3(kT), l.acc_lds, s,
                      l.inst, l.n, l.pre, l.tb);
   LBG_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(b_fin_kernel, dim3((unsigned)l.blocks[kPreFin]), dim3(kT), 0, s, l.inst,
-                     l.n, l.pre, l.tb, l.ctr, l.ctr + 1);
+  hipLaunchKernelGGL(b_list_kernel, dim3(1), dim3(1024), 0, s, l.st, l.pend, l.inst, l.n,
+                     l.fin_list, l.fin_first, l.list_total);
+  LBG_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(b_fin_kernel, dim3((unsigned)std::min(l.blocks[kPreFin], kFinGrid)), dim3(kT),
+                     0, s, l.inst, l.fin_list, l.fin_first, l.list_total, l.ctr, l.ctr + 1);
   LBG_TRY_HIP(hipGetLastError());
   if (ev) LBG_TRY_HIP(hipEventRecord(ev[2], s));
   return LBG_OK;
@@ -615,22 +742,29 @@ struct RoundEvents {
   }
 };
 
-// Autotuner: candidate (grab, grid) pairs timed on the allocation at every
-// instance's final codebook size; the fastest is cached per workload.
+// Autotuner: candidate (screen, grab, grid) triples timed on the allocation at
+// every instance's final codebook size; the fastest is cached per workload.
+// The screens give the same allocation, so only their speed is compared.
 struct TuneKey {
   int n;
   int64_t sumM, work, sumN;
+  int screen;  // the screens the caller allowed
   bool operator<(const TuneKey& o) const {
-    return std::tie(n, sumM, work, sumN) < std::tie(o.n, o.sumM, o.work, o.sumN);
+    return std::tie(n, sumM, work, sumN, screen) < std::tie(o.n, o.sumM, o.work, o.sumN, o.screen);
   }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, std::pair<int, int>> g_tune;
+struct TuneVal {
+  int grab, grid, split;
+};
+std::map<TuneKey, TuneVal> g_tune;
 
 int autotune(Launch l, const std::vector<InstPlan>& plans, int32_t* chunk_host,
-             int32_t* chunk_dev, hipStream_t s, int* grab_out, int* grid_out, double* ms_out) {
+             int32_t* chunk_dev, hipStream_t s, int split_req, TuneVal* out, double* ms_out) {
   static const int grabs[] = {1, 2, 4, 8, 16};
   static const int grids[] = {256, 512};
+  // split_req: 0 = try both screens, 1 = FP32 screen only, 2 = split only
+  const int sp_lo = split_req == 2 ? 1 : 0, sp_hi = split_req == 1 ? 0 : 1;
   hipLaunchKernelGGL(b_tune_setup_kernel, dim3((unsigned)l.blocks[kPreFin]), dim3(kT), 0, s,
                      l.inst, l.n, l.pre, l.tb);
   LBG_TRY_HIP(hipGetLastError());
@@ -638,7 +772,7 @@ int autotune(Launch l, const std::vector<InstPlan>& plans, int32_t* chunk_host,
   LBG_TRY_HIP(hipEventCreate(&e0));
   LBG_TRY_HIP(hipEventCreate(&e1));
   float best = 1e30f;
-  int bg = 4, bgrid = 512;
+  int bg = 4, bgrid = 512, bsp = sp_lo;
   double total = 0.0;
   int rc = LBG_OK;
   for (int g : grabs) {
@@ -651,14 +785,20 @@ int autotune(Launch l, const std::vector<InstPlan>& plans, int32_t* chunk_host,
       rc = hip_fail(ec, "autotune");
       break;
     }
+    for (int sp = sp_lo; sp <= sp_hi; ++sp)
     for (int gr : grids) {
       float ms_min = 1e30f;
       for (int rep = 0; rep < 3 && rc == LBG_OK; ++rep) {
-        hipError_t e = hipMemsetAsync(l.ctr, 0, sizeof(unsigned), s);
+        hipError_t e = hipMemsetAsync(l.ctr, 0, 3 * sizeof(unsigned), s);
         if (e == hipSuccess) e = hipEventRecord(e0, s);
         if (e == hipSuccess) {
-          hipLaunchKernelGGL(b_assign_kernel, dim3((unsigned)gr), dim3(kT), kBatchLds, s, l.inst,
-                             l.chunks, l.nchunks, l.ctr);
+          hipLaunchKernelGGL(b_assign_kernel<false>, dim3((unsigned)gr), dim3(kT), kBatchLds, s,
+                             l.inst, l.chunks, l.nchunks, l.ctr, sp);
+          e = hipGetLastError();
+        }
+        if (e == hipSuccess && sp) {
+          hipLaunchKernelGGL(b_assign_kernel<true>, dim3((unsigned)gr), dim3(kT), kBatchLds, s,
+                             l.inst, l.chunks, l.nchunks, l.ctr + 2, sp);
           e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipEventRecord(e1, s);
@@ -676,13 +816,15 @@ int autotune(Launch l, const std::vector<InstPlan>& plans, int32_t* chunk_host,
         best = ms_min;
         bg = g;
         bgrid = gr;
+        bsp = sp;
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  *grab_out = bg;
-  *grid_out = bgrid;
+  out->grab = bg;
+  out->grid = bgrid;
+  out->split = bsp;
   *ms_out = total;
   return rc;
 }
@@ -692,7 +834,7 @@ struct BGraph {
   bool used = false;
   const void* ws = nullptr;
   hipStream_t stream = nullptr;
-  int n = 0, grab = 0, grid = 0;
+  int n = 0, grab = 0, grid = 0, split = 0;
   int64_t blocks[kNumPre] = {};
   size_t acc_lds = 0;
   int nchunks = 0;
@@ -703,11 +845,11 @@ std::mutex g_bgraph_mu;
 BGraph g_bgraph[4];
 uint64_t g_bstamp = 0;
 
-int get_graph(const Launch& l, const void* ws, int grab, int grid, hipStream_t s,
+int get_graph(const Launch& l, const void* ws, int grab, int grid, int split, hipStream_t s,
               hipGraphExec_t* out) {
   for (auto& e : g_bgraph)
     if (e.used && e.ws == ws && e.stream == s && e.n == l.n && e.grab == grab &&
-        e.grid == grid && e.acc_lds == l.acc_lds && e.nchunks == l.nchunks &&
+        e.grid == grid && e.split == split && e.acc_lds == l.acc_lds && e.nchunks == l.nchunks &&
         memcmp(e.blocks, l.blocks, sizeof(e.blocks)) == 0) {
       e.stamp = ++g_bstamp;
       *out = e.exec;
@@ -726,7 +868,7 @@ int get_graph(const Launch& l, const void* ws, int grab, int grid, hipStream_t s
   hipGraph_t g = nullptr;
   LBG_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   int rc = LBG_OK;
-  for (int r = 0; r < kRoundsPerGraph && rc == LBG_OK; ++r) rc = launch_round(l, grid, s);
+  for (int r = 0; r < kRoundsPerGraph && rc == LBG_OK; ++r) rc = launch_round(l, grid, split, s);
   const hipError_t e = hipStreamEndCapture(s, &g);
   if (rc != LBG_OK) {
     if (g) (void)hipGraphDestroy(g);
@@ -743,6 +885,7 @@ int get_graph(const Launch& l, const void* ws, int grab, int grid, hipStream_t s
   slot->n = l.n;
   slot->grab = grab;
   slot->grid = grid;
+  slot->split = split;
   memcpy(slot->blocks, l.blocks, sizeof(slot->blocks));
   slot->acc_lds = l.acc_lds;
   slot->nchunks = l.nchunks;
@@ -838,6 +981,7 @@ extern "C" void lbg_batch_config_default(lbg_batch_config* cfg) {
   cfg->grid = 0;
   cfg->graph = 1;
   cfg->rounds_per_poll = kRoundsPerGraph;
+  cfg->screen = 0;
 }
 
 extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const lbg_params* p,
@@ -867,6 +1011,10 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
   }
   if (cfg->grab < 0 || cfg->grid < 0 || cfg->rounds_per_poll < 0) {
     set_error("lbg_train_batched: negative configuration value");
+    return LBG_EINVAL;
+  }
+  if (cfg->screen < 0 || cfg->screen > 2) {
+    set_error("lbg_train_batched: screen must be 0 (autotuned), 1 (FP32) or 2 (split BF16)");
     return LBG_EINVAL;
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -990,13 +1138,18 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
     }
   }
   int32_t* hchunk = reinterpret_cast<int32_t*>(host + b_inst + b_pre + b_st + 64 + b_tab);
-  Launch l{w.inst, n, w.pre, tb, {}, w.ctr, acc_lds, w.chunks, 0};
+  Launch l{w.inst, n, w.pre, tb, {}, w.ctr, acc_lds, w.chunks, 0,
+           w.st, w.pend, w.fin_list, w.fin_first, w.list_total};
   for (int k = 0; k < kNumPre; ++k) l.blocks[k] = tot[k];
 
   static const hipError_t lds_ok = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&b_assign_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-      kBatchLds);
+      reinterpret_cast<const void*>(&b_assign_kernel<false>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLds);
+  static const hipError_t lds_ok2 = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&b_assign_kernel<true>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLds);
   LBG_TRY_HIP(lds_ok);
+  LBG_TRY_HIP(lds_ok2);
 
   LBG_TRY_HIP(hipMemcpyAsync(w.inst, hi, b_inst + 0, hipMemcpyHostToDevice, s));
   LBG_TRY_HIP(hipMemcpyAsync(w.pre, hp, b_pre, hipMemcpyHostToDevice, s));
@@ -1004,24 +1157,25 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
 
   // autotune (before the states are set: it uses them as scratch)
   int grab = cfg->grab, grid = cfg->grid;
+  int split = cfg->screen == 2 ? 1 : 0;
   bool tuned = false;
   double ms_tune = 0.0;
-  if (grab == 0 || grid == 0) {
-    const TuneKey key{n, sumM, work, sumN};
+  if (grab == 0 || grid == 0 || cfg->screen == 0) {
+    const TuneKey key{n, sumM, work, sumN, cfg->screen};
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
+    TuneVal tv;
     if (it != g_tune.end()) {
-      if (grab == 0) grab = it->second.first;
-      if (grid == 0) grid = it->second.second;
+      tv = it->second;
     } else {
-      int tg = 0, tgrid = 0;
       LBG_TRY_HIP(hipMemsetAsync(w.st, 0, b_st, s));
-      LBG_TRY(autotune(l, w.plans, hchunk, w.chunks, s, &tg, &tgrid, &ms_tune));
-      g_tune[key] = {tg, tgrid};
+      LBG_TRY(autotune(l, w.plans, hchunk, w.chunks, s, cfg->screen, &tv, &ms_tune));
+      g_tune[key] = tv;
       tuned = true;
-      if (grab == 0) grab = tg;
-      if (grid == 0) grid = tgrid;
     }
+    if (grab == 0) grab = tv.grab;
+    if (grid == 0) grid = tv.grid;
+    if (cfg->screen == 0) split = tv.split;
   }
 
   // the allocation chunks for the chosen grab
@@ -1032,7 +1186,7 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
   // set-up: states, counters, centroids and first split, fixed-point shifts
   LBG_TRY_HIP(hipMemcpyAsync(w.st, hs, b_st, hipMemcpyHostToDevice, s));
   LBG_TRY_HIP(hipMemcpyAsync(w.pend, hs, b_st, hipMemcpyHostToDevice, s));
-  LBG_TRY_HIP(hipMemsetAsync(w.ctr, 0, 2 * sizeof(unsigned), s));
+  LBG_TRY_HIP(hipMemsetAsync(w.ctr, 0, 3 * sizeof(unsigned), s));
   LBG_TRY_HIP(hipMemsetAsync(w.nfb, 0, sizeof(unsigned long long) * (size_t)n, s));
   hipLaunchKernelGGL(b_colsum_kernel, dim3((unsigned)tot[kPreCol]), dim3(kT), 0, s, w.inst, n,
                      w.pre, tb);
@@ -1066,7 +1220,7 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
   hipGraphExec_t gexec = nullptr;
   if (use_graph) {
     glk.lock();
-    LBG_TRY(get_graph(l, ws, grab, grid, s, &gexec));
+    LBG_TRY(get_graph(l, ws, grab, grid, split, s, &gexec));
   }
   RoundEvents rev;
   if (timing) LBG_TRY(rev.make(per_poll));
@@ -1076,7 +1230,7 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
       LBG_TRY_HIP(hipGraphLaunch(gexec, s));
     } else {
       for (int r = 0; r < per_poll; ++r)
-        LBG_TRY(launch_round(l, grid, s, timing ? &rev.ev[(size_t)r * 3] : nullptr));
+        LBG_TRY(launch_round(l, grid, split, s, timing ? &rev.ev[(size_t)r * 3] : nullptr));
     }
     rounds += per_poll;
     LBG_TRY_HIP(hipMemcpyAsync(ndone_host, w.ctr + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
@@ -1137,6 +1291,7 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
     stats->ms_tune = ms_tune;
     stats->ms_assign = ms_assign;
     stats->ms_update = ms_update;
+    stats->screen = split ? 2 : 1;
   }
   return status;
 }

@@ -78,20 +78,26 @@ def test_batched_equals_single_runs(P):
         _same(P, got, X, N, f"case {case}")
 
 
-@pytest.mark.parametrize("grab,grid,graph", [(1, 256, False), (16, 512, True), (3, 97, True)])
-def test_batched_configuration_does_not_change_results(P, grab, grid, graph):
-    data = _data(CASES[:6])
+# screen 1: FP32 screen; 2: split BF16 screen where its codebook layout fits
+# (both exact, so the allocations, and everything after them, are the same)
+@pytest.mark.parametrize("grab,grid,graph,screen", [(1, 256, False, 1), (16, 512, True, 2),
+                                                    (3, 97, True, 2), (4, 256, False, 2)])
+def test_batched_configuration_does_not_change_results(P, grab, grid, graph, screen):
+    data = _data(CASES)
     ref, _ = P.train_batched([dev(X) for X, _ in data], [N for _, N in data], grab=1, grid=512,
-                             graph=False)
+                             graph=False, screen=1)
     # graphs are captured on non-default streams only
     side = torch.cuda.Stream()
     Xs = [dev(X) for X, _ in data]
     torch.cuda.synchronize()
     with torch.cuda.stream(side):
-        got, st = P.train_batched(Xs, [N for _, N in data], grab=grab, grid=grid, graph=graph)
-        got2, _ = P.train_batched(Xs, [N for _, N in data], grab=grab, grid=grid, graph=graph)
+        got, st = P.train_batched(Xs, [N for _, N in data], grab=grab, grid=grid, graph=graph,
+                                  screen=screen)
+        got2, _ = P.train_batched(Xs, [N for _, N in data], grab=grab, grid=grid, graph=graph,
+                                  screen=screen)
     side.synchronize()
     assert st["grab"] == grab and st["grid"] == grid and st["graph"] == (1 if graph else 0)
+    assert st["screen"] == screen
     for a, b in zip(got, got2):  # a second call replays the cached graph
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[2] == b[2]
     for a, b in zip(ref, got):
