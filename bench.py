@@ -756,7 +756,7 @@ def main():
                              "fallback_rows_per_step": tot2["fallback"] // args.steps,
                              "D": last2[2]}
         out["speedup_vs_fp32_exact"] = (tot["dist"] / el) / (tot2["dist"] / el2)
-        out["bf16_errors"] = bf16_errors(P, X, Xd, last2[0], last[0], last[2], last2[2])
+        out["bf16_errors"] = bf16_errors(P, X, Xd, last2[0], last[0], last[2], last2[2], C0d, iters)
     if not args.no_extras and not args.precision:
         out["config1"] = config1_line(P, max(3, args.steps // 2), 2, stream)
     if not args.no_cpu_baseline:
@@ -769,10 +769,12 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bf16_errors(P, X, Xd, C_exact, C_bf16, D_bf16, D_exact):
+def bf16_errors(P, X, Xd, C_exact, C_bf16, D_bf16, D_exact, C0d=None, iters=10):
     """Errors of the BF16 form: per step (the exact run's final codebook into
     one BF16 and one exact allocation + update; allocations against the FP64
-    oracle on the 65,536-row subsample) and after the 10 iterations."""
+    oracle on the 65,536-row subsample), along the BF16 run (every one of its
+    steps against the exact step from the same codebook) and after the 10
+    iterations."""
     import torch
     import oracle
     M = X.shape[0]
@@ -799,6 +801,22 @@ def bf16_errors(P, X, Xd, C_exact, C_bf16, D_bf16, D_exact):
 
     r1 = rel_rows(Cb1, Cf1)
     r10 = rel_rows(C_bf16, C_exact)
+    # along the BF16 trajectory: step t of the BF16 run (allocation in BF16,
+    # exact update) against the exact step from the same codebook C_t
+    along = []
+    if C0d is not None:
+        Ct = C0d.clone()
+        for _ in range(iters):
+            ib_t, _ = P.assign(Xd, Ct, P.BF16_RESCORE)
+            if_t, _ = P.assign(Xd, Ct, P.FP32)
+            Cb_t, _ = P.update(Xd, ib_t, Ct)
+            Cf_t, _ = P.update(Xd, if_t, Ct)
+            r = rel_rows(Cb_t, Cf_t)
+            along.append({"codebook_rel_max": float(r.max()),
+                          "codebook_rel_median": float(np.median(r)),
+                          "allocation_mismatch_rate_vs_exact":
+                              float((ib_t != if_t).float().mean().item())})
+            Ct = Cb_t
     return {
         "per_step": {
             "subsample_rows": int(rows.size),
@@ -807,6 +825,11 @@ def bf16_errors(P, X, Xd, C_exact, C_bf16, D_bf16, D_exact):
             "codebook_rel_vs_exact_update_max": float(r1.max()),
             "codebook_rel_vs_exact_update_median": float(np.median(r1)),
             "D_rel_vs_exact": abs(D_b - D_f) / D_f,
+        },
+        "per_step_along_bf16_run": {
+            "steps": along,
+            "codebook_rel_max_over_steps": max((a["codebook_rel_max"] for a in along),
+                                               default=None),
         },
         "after_10_iterations": {
             "codebook_rel_vs_exact_run_max": float(r10.max()),
