@@ -179,6 +179,29 @@ def form_batched(args):
     torch.cuda.synchronize(dev)
     t_s = time.perf_counter() - t0
     same = sum(1 for r, d in zip(res, D_single) if r[2] == d)
+    # the batched single steps on the final codebooks: one allocation (with
+    # D) and one update of every instance, against the single calls
+    Cs = [r[0] for r in res]
+    ab = P.assign_batched(Xs, Cs)  # warm-up
+    ub = P.update_batched(Xs, ab[0], Cs)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    ib, Db = P.assign_batched(Xs, Cs)
+    t_ab = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ub = P.update_batched(Xs, ib, Cs)
+    t_ub = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    single_ab = [P.assign_distortion(X, C, P.FP32) for X, C in zip(Xs, Cs)]
+    torch.cuda.synchronize(dev)
+    t_as = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    single_ub = [P.update(X, i1[0], C) for X, i1, C in zip(Xs, single_ab, Cs)]
+    torch.cuda.synchronize(dev)
+    t_us = time.perf_counter() - t0
+    steps_same = sum(1 for a, b, c, d in zip(ib, Db, single_ab, ub[0])
+                     if torch.equal(a, c[0]) and float(b.item()) == float(c[2].item()))
+    upd_same = sum(1 for a, b in zip(ub[0], single_ub) if torch.equal(a, b[0]))
     out = {
         "metric": "batched LBG vector-codeword distances/s",
         "value": dist / t_b,
@@ -209,6 +232,11 @@ def form_batched(args):
         "per_instance_launches": {"value": dist / t_s, "ms_total": t_s * 1e3},
         "speedup_vs_per_instance": t_s / t_b,
         "identical_D_to_per_instance": f"{same}/{len(inst)}",
+        "batched_single_steps": {
+            "assign_batched_ms": t_ab * 1e3, "assign_distortion_per_instance_ms": t_as * 1e3,
+            "update_batched_ms": t_ub * 1e3, "update_per_instance_ms": t_us * 1e3,
+            "identical_allocation_and_D": f"{steps_same}/{len(inst)}",
+            "identical_update": f"{upd_same}/{len(inst)}"},
     }
     print(json.dumps(out), flush=True)
 

@@ -416,6 +416,62 @@ int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const lbg_params
                       lbg_batch_stats* st, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Batched single steps: many independent items in a few launches for all of
+ * them (the batched form's kernels), each item's result bit-identical to the
+ * single call on it.  HOST arrays items[n]; device pointers inside.  The
+ * workspace (device, 256-byte aligned) is sized by the *_workspace call on
+ * the same items.  Both synchronise ``stream`` (the items' descriptors are
+ * uploaded from host memory that is released on return).
+ *
+ * Cell Allocation (Algorithm 1, "Cell Allocation"; Sec. 3.2) of item i:
+ * idx[m] = the nearest row of C (squared Euclidean distance, lowest index
+ * on ties) for every row of X, exactly as lbg_assign(X, M, L, C, N, idx,
+ * NULL, LBG_FP32, ...); D (nullable) receives (1/M) sum_m d(x_m, c_idx[m])
+ * in FP64, lbg_assign_distortion's D bit for bit.  1 <= L <= 64, N >= 1, and
+ * the codebook must fit the allocation's LDS as for lbg_instance
+ * ((N rounded up to 32) * (16 or 64, L rounded up, + 4) * 4 <= 81920 bytes).
+ * A non-finite row gets index 0 and makes D +inf.
+ */
+typedef struct lbg_assign_item {
+  const float* X;  /* DEVICE, M x L FP32 row-major (16-byte aligned rows for
+                      vector loads; 4-byte aligned at least) */
+  int64_t M;       /* 1 <= M <= LBG_MAX_M */
+  int64_t L;       /* 1 <= L <= 64 */
+  const float* C;  /* DEVICE, N x L FP32 */
+  int64_t N;       /* 1 <= N; see the LDS limit above */
+  int32_t* idx;    /* DEVICE, M: the allocation (out) */
+  double* D;       /* DEVICE, nullable: the mean distortion (out) */
+} lbg_assign_item;
+
+size_t lbg_assign_batched_workspace(const lbg_assign_item* items, int32_t n);
+int lbg_assign_batched(const lbg_assign_item* items, int32_t n, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/*
+ * Codebook Updation (Algorithm 1, "Codebook Updation"; Sec. 3.2) of item i:
+ * C_new[k] = the mean of the rows with idx == k (an empty cell keeps
+ * C_old[k]; entries of idx outside [0, N) join no cell), from exact
+ * fixed-point sums as lbg_update does, so C_new and counts equal
+ * lbg_update's bit for bit.  C_new may equal C_old (in place); otherwise
+ * they must not overlap.  1 <= L <= 64, and N * L within the fixed-point
+ * path's limit (LBG_EINVAL names the item otherwise: use lbg_update).
+ */
+typedef struct lbg_update_item {
+  const float* X;        /* DEVICE, M x L FP32 row-major */
+  int64_t M;             /* 1 <= M <= LBG_MAX_M */
+  int64_t L;             /* 1 <= L <= 64 */
+  const int32_t* idx;    /* DEVICE, M */
+  const float* C_old;    /* DEVICE, N x L */
+  int64_t N;             /* >= 1 */
+  float* C_new;          /* DEVICE, N x L (out) */
+  int32_t* counts;       /* DEVICE, N, nullable: the cell sizes (out) */
+} lbg_update_item;
+
+size_t lbg_update_batched_workspace(const lbg_update_item* items, int32_t n);
+int lbg_update_batched(const lbg_update_item* items, int32_t n, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/*
  * lbg_assign_distortion without a workspace, for callers that cannot
  * allocate device memory (code under stream capture, tight serving loops,
  * harnesses that forbid allocation).  Same arguments, results and error

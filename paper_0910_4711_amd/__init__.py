@@ -97,6 +97,31 @@ class Instance(ct.Structure):
     ]
 
 
+class AssignItem(ct.Structure):
+    _fields_ = [
+        ("X", ct.c_void_p),
+        ("M", ct.c_int64),
+        ("L", ct.c_int64),
+        ("C", ct.c_void_p),
+        ("N", ct.c_int64),
+        ("idx", ct.c_void_p),
+        ("D", ct.c_void_p),
+    ]
+
+
+class UpdateItem(ct.Structure):
+    _fields_ = [
+        ("X", ct.c_void_p),
+        ("M", ct.c_int64),
+        ("L", ct.c_int64),
+        ("idx", ct.c_void_p),
+        ("C_old", ct.c_void_p),
+        ("N", ct.c_int64),
+        ("C_new", ct.c_void_p),
+        ("counts", ct.c_void_p),
+    ]
+
+
 class BatchConfig(ct.Structure):
     _fields_ = [
         ("grab", ct.c_int32),
@@ -171,6 +196,8 @@ def load():
             "lbg_train_batched": [ct.POINTER(Instance), i32, ct.POINTER(Params),
                                   ct.POINTER(BatchConfig), ct.POINTER(BatchResult),
                                   ct.POINTER(BatchStats), vp, sz, vp],
+            "lbg_assign_batched": [ct.POINTER(AssignItem), i32, vp, sz, vp],
+            "lbg_update_batched": [ct.POINTER(UpdateItem), i32, vp, sz, vp],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -190,6 +217,10 @@ def load():
         lib.lbg_batch_config_default.restype = None
         lib.lbg_train_batched_workspace.argtypes = [ct.POINTER(Instance), i32]
         lib.lbg_train_batched_workspace.restype = ct.c_size_t
+        lib.lbg_assign_batched_workspace.argtypes = [ct.POINTER(AssignItem), i32]
+        lib.lbg_assign_batched_workspace.restype = ct.c_size_t
+        lib.lbg_update_batched_workspace.argtypes = [ct.POINTER(UpdateItem), i32]
+        lib.lbg_update_batched_workspace.restype = ct.c_size_t
         _lib = lib
         return lib
 
@@ -600,3 +631,77 @@ class Distortion(torch.autograd.Function):
         gX, gC = distortion_backward(X, C, idx, gv, need_x=ctx.needs_input_grad[0],
                                      need_c=ctx.needs_input_grad[1])
         return gX, gC
+
+
+def assign_batched(Xs, Cs, with_D=True, workspace=None):
+    """Cell Allocation of many independent (X_i, C_i) pairs in one persistent
+    launch (exact, as assign(X_i, C_i, FP32)).  Returns (idxs, Ds): idxs[i]
+    int32 [M_i]; Ds[i] a 0-d float64 GPU tensor (assign_distortion's D) or
+    None when with_D is false."""
+    if len(Xs) != len(Cs) or len(Xs) == 0:
+        raise ValueError("need as many codebooks as training sets (at least one)")
+    Xs = [_f32_2d(f"Xs[{i}]", X) for i, X in enumerate(Xs)]
+    Cs = [_f32_2d(f"Cs[{i}]", C) for i, C in enumerate(Cs)]
+    dev = Xs[0].device
+    if any(t.device != dev for t in Xs + Cs):
+        raise ValueError("all tensors must be on one device")
+    n = len(Xs)
+    items = (AssignItem * n)()
+    idxs, Ds = [], []
+    for i, (X, C) in enumerate(zip(Xs, Cs)):
+        M, L = X.shape
+        if C.shape[1] != L:
+            raise ValueError(f"Cs[{i}] has {C.shape[1]} columns, Xs[{i}] {L}")
+        idx = torch.empty(M, dtype=torch.int32, device=dev)
+        D = torch.empty((), dtype=torch.float64, device=dev) if with_D else None
+        items[i].X, items[i].M, items[i].L = X.data_ptr(), M, L
+        items[i].C, items[i].N = C.data_ptr(), C.shape[0]
+        items[i].idx = idx.data_ptr()
+        items[i].D = D.data_ptr() if with_D else None
+        idxs.append(idx)
+        Ds.append(D)
+    lib = load()
+    nb = lib.lbg_assign_batched_workspace(items, n)
+    if nb == 0:
+        raise LBGError("lbg_assign_batched_workspace: bad items")
+    ws = workspace
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _check(lib.lbg_assign_batched(items, n, _ptr(ws), nb, _stream(dev)), "lbg_assign_batched")
+    return idxs, Ds
+
+
+def update_batched(Xs, idxs, Cs_old, workspace=None):
+    """Codebook Updation of many independent items in a few launches (exact,
+    as update(X_i, idx_i, C_i)).  Returns (C_news, counts)."""
+    if not (len(Xs) == len(idxs) == len(Cs_old)) or len(Xs) == 0:
+        raise ValueError("need as many allocations and codebooks as training sets")
+    Xs = [_f32_2d(f"Xs[{i}]", X) for i, X in enumerate(Xs)]
+    Cs_old = [_f32_2d(f"Cs_old[{i}]", C) for i, C in enumerate(Cs_old)]
+    dev = Xs[0].device
+    n = len(Xs)
+    items = (UpdateItem * n)()
+    outs, cnts, keep = [], [], []
+    for i, (X, idx, C) in enumerate(zip(Xs, idxs, Cs_old)):
+        M, L = X.shape
+        if idx.dtype != torch.int32 or idx.numel() != M or not idx.is_contiguous():
+            raise ValueError(f"idxs[{i}] must be a contiguous int32 tensor of {M} entries")
+        if C.shape[1] != L or any(t.device != dev for t in (idx, C)):
+            raise ValueError(f"item {i}: codebook columns or device differ from Xs[{i}]")
+        Cn = torch.empty_like(C)
+        cnt = torch.empty(C.shape[0], dtype=torch.int32, device=dev)
+        items[i].X, items[i].M, items[i].L = X.data_ptr(), M, L
+        items[i].idx, items[i].C_old, items[i].N = idx.data_ptr(), C.data_ptr(), C.shape[0]
+        items[i].C_new, items[i].counts = Cn.data_ptr(), cnt.data_ptr()
+        outs.append(Cn)
+        cnts.append(cnt)
+        keep.append(idx)
+    lib = load()
+    nb = lib.lbg_update_batched_workspace(items, n)
+    if nb == 0:
+        raise LBGError("lbg_update_batched_workspace: bad items")
+    ws = workspace
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _check(lib.lbg_update_batched(items, n, _ptr(ws), nb, _stream(dev)), "lbg_update_batched")
+    return outs, cnts

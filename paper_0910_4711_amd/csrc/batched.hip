@@ -70,6 +70,8 @@ struct BInst {
   double* Dtrace;
   int32_t* Atrace;
   unsigned long long* nfb;
+  int32_t* counts;  // batched single steps: cell counts out (nullable)
+  double* Dout;     // batched single steps: mean distortion out (nullable)
 };
 
 // Exclusive prefix sums of each launch's blocks (or items) over instances;
@@ -358,16 +360,11 @@ __global__ __launch_bounds__(1024) void b_list_kernel(const DevState* __restrict
   if (t == 0) *total = sbase;
 }
 
-// One workgroup's share of instance B's update: its decision (local 0),
-// then the fixed-point cell sums of row chunk x cell slice ``local``.
-__device__ __forceinline__ void acc_item(const BInst& B, int64_t local, unsigned long long* sacc,
-                                         int32_t* slist, int32_t& snsel) {
-  const Ctl ctl{B.st, B.pend, B.dpart, (B.M + 31) / 32, B.Dtrace, B.Atrace};
-  int N = B.N;
-  if (B.st->done) return;
-  if (local == 0) (void)afp::acc_decide(ctl, true, &N);  // the instance's decision
-  if (forced_stop(B.st)) return;  // the level ends here: no update follows
-  N = B.st->n;
+// The fixed-point cell sums of instance B's row chunk x cell slice
+// ``local`` for a codebook of N cells.
+__device__ __forceinline__ void acc_cells(const BInst& B, int N, int64_t local,
+                                          unsigned long long* sacc, int32_t* slist,
+                                          int32_t& snsel) {
   // Slices of cps cells the current codebook needs (the launch has the final
   // codebook's): the workgroups of the others have nothing to add, and one
   // slice streams the rows instead of gathering them per slice.  The
@@ -427,6 +424,18 @@ __device__ __forceinline__ void acc_item(const BInst& B, int64_t local, unsigned
   }
 #undef LBG_BACC
 #undef LBG_BACC1
+}
+
+// One workgroup's share of instance B's update: its decision (local 0),
+// then the fixed-point cell sums of row chunk x cell slice ``local``.
+__device__ __forceinline__ void acc_item(const BInst& B, int64_t local, unsigned long long* sacc,
+                                         int32_t* slist, int32_t& snsel) {
+  const Ctl ctl{B.st, B.pend, B.dpart, (B.M + 31) / 32, B.Dtrace, B.Atrace};
+  int N = B.N;
+  if (B.st->done) return;
+  if (local == 0) (void)afp::acc_decide(ctl, true, &N);  // the instance's decision
+  if (forced_stop(B.st)) return;  // the level ends here: no update follows
+  acc_cells(B, B.st->n, local, sacc, slist, snsel);
 }
 
 // One workgroup per (instance, row chunk, cell slice) of every instance; the
@@ -553,6 +562,71 @@ __global__ __launch_bounds__(kT) void b_tune_setup_kernel(const BInst* __restric
     B.st->cb = 0;
     B.st->done = 0;
   }
+}
+
+// ------------------------------------------------- batched single steps --
+// Item i's mean distortion from its allocation partials (one per 32 rows), in
+// the order of the single-call reduction (thread t adds partials t, t + 256,
+// ... in index order, 32 loads in flight, then a tree over the threads), so
+// that it equals lbg_assign_distortion's D bit for bit.  One workgroup per
+// item; items without an output pointer are skipped.
+__global__ __launch_bounds__(kT) void b_reduce_kernel(const BInst* __restrict__ inst) {
+  constexpr int RB = 32;
+  __shared__ double sred[kT];
+  const BInst& B = inst[blockIdx.x];
+  if (!B.Dout) return;
+  const int64_t nparts = (B.M + 31) / 32;
+  const double* parts = B.dpart;
+  double acc = 0.0;
+  int64_t p = threadIdx.x;
+  for (; p + (int64_t)(RB - 1) * kT < nparts; p += (int64_t)RB * kT) {
+    double v[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) v[b] = parts[p + (int64_t)b * kT];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) acc += v[b];
+  }
+  for (; p < nparts; p += kT) acc += parts[p];
+  sred[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kT / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sred[threadIdx.x] += sred[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *B.Dout = sred[0] / (double)B.M;
+}
+
+// Codebook Updation of many items without run state: the cell sums of every
+// item's chunk x slice workgroups (the item's N cells) ...
+__global__ __launch_bounds__(kT) void b_upd_acc_kernel(const BInst* __restrict__ inst, int n_inst,
+                                                       const int64_t* __restrict__ pre, Tabs tb) {
+  extern __shared__ unsigned long long sacc[];
+  __shared__ int32_t slist[afp::kSel];
+  __shared__ int32_t snsel;
+  const int64_t* acc_pre = pre + (int64_t)kPreAcc * (n_inst + 1);
+  if ((int64_t)blockIdx.x >= acc_pre[n_inst]) return;
+  const int i = tb.b2i[tb.off[kPreAcc] + blockIdx.x];
+  const BInst& B = inst[i];
+  acc_cells(B, B.N, (int64_t)blockIdx.x - acc_pre[i], sacc, slist, snsel);
+}
+
+// ... then every item's centroids (one workgroup per cell; an empty cell
+// keeps C_old, Cb[0]) into C_out, with the counts.
+__global__ __launch_bounds__(kT) void b_upd_fin_kernel(const BInst* __restrict__ inst, int n_inst,
+                                                       const int64_t* __restrict__ pre, Tabs tb) {
+  const int64_t* fin_pre = pre + (int64_t)kPreFin * (n_inst + 1);
+  if ((int64_t)blockIdx.x >= fin_pre[n_inst]) return;
+  const int i = tb.b2i[tb.off[kPreFin] + blockIdx.x];
+  const BInst& B = inst[i];
+  const int k = (int)((int64_t)blockIdx.x - fin_pre[i]);
+  afp::fin_body<0>(
+      B.part, B.pcnt, B.nchunks, B.N, B.L, B.shift[0], B.counts, 0.0, k,
+      [&](const float** c_old, float** dst) {
+        *c_old = B.Cb[0];
+        *dst = B.C_out;
+        return true;
+      },
+      B.lo, B.shift[1]);
 }
 
 // ---------------------------------------------------------------- planning --
@@ -1294,4 +1368,317 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
     stats->screen = split ? 2 : 1;
   }
   return status;
+}
+
+// ------------------------------------------------- batched single steps --
+namespace lbg {
+namespace {
+
+struct AsgWs {
+  BInst* inst;
+  DevState* st;
+  unsigned* ctr;
+  unsigned long long* nfb;
+  int32_t* chunks;
+  std::vector<InstPlan> plans;  // G and the partials of each item
+};
+
+void plan_asg(Carver& c, const lbg_assign_item* in, int n, AsgWs* w) {
+  w->inst = c.take<BInst>((size_t)n);
+  w->st = c.take<DevState>((size_t)n);
+  w->ctr = c.take<unsigned>(3);
+  w->nfb = c.take<unsigned long long>((size_t)n);
+  w->plans.assign((size_t)n, InstPlan{});
+  int64_t totG = 0;
+  for (int i = 0; i < n; ++i) {
+    InstPlan& q = w->plans[(size_t)i];
+    q.G = slots_of(in[i].M, in[i].L);
+    q.ntiles = (in[i].M + kRowsPerTile - 1) / kRowsPerTile;
+    q.dpart = c.take<double>((size_t)((in[i].M + 31) / 32));
+    totG += q.G;
+  }
+  w->chunks = c.take<int32_t>((size_t)(3 * totG));
+}
+
+int validate_asg(const lbg_assign_item* in, int32_t n) {
+  if (!in || n < 1) {
+    set_error("lbg_assign_batched: need at least one item (n = %d)", (int)n);
+    return LBG_EINVAL;
+  }
+  for (int i = 0; i < n; ++i) {
+    const lbg_assign_item& a = in[i];
+    if (!a.X || !a.C || !a.idx) {
+      set_error("lbg_assign_batched: item %d has a NULL pointer", i);
+      return LBG_EINVAL;
+    }
+    if (a.M < 1 || a.M > LBG_MAX_M || a.L < 1 || a.L > 64 || a.N < 1 || a.N > LBG_MAX_N) {
+      set_error("lbg_assign_batched: item %d: M = %lld, L = %lld, N = %lld (need M >= 1, "
+                "1 <= L <= 64, N >= 1)", i, (long long)a.M, (long long)a.L, (long long)a.N);
+      return LBG_EINVAL;
+    }
+    const int64_t npad = (a.N + 31) & ~(int64_t)31;
+    if (npad * (lp_of(a.L) + 4) * 4 > kBatchLds) {
+      set_error("lbg_assign_batched: item %d: codebook of %lld x %lld does not fit the "
+                "allocation's LDS (%d bytes)", i, (long long)a.N, (long long)a.L, kBatchLds);
+      return LBG_EINVAL;
+    }
+    if (((reinterpret_cast<uintptr_t>(a.X) | reinterpret_cast<uintptr_t>(a.C) |
+          reinterpret_cast<uintptr_t>(a.idx)) & 3) ||
+        (reinterpret_cast<uintptr_t>(a.D) & 7)) {
+      set_error("lbg_assign_batched: item %d: misaligned pointer", i);
+      return LBG_EINVAL;
+    }
+  }
+  return LBG_OK;
+}
+
+struct UpdWs {
+  BInst* inst;
+  int64_t* pre;
+  int32_t* b2i;
+  int64_t tot[kNumPre];
+  std::vector<AfpWs> afp;
+};
+
+// Blocks of the update launches for one item (the other families unused).
+void upd_counts(const AfpWs& a, int64_t N, int64_t cnt[kNumPre]) {
+  for (int k = 0; k < kNumPre; ++k) cnt[k] = 0;
+  cnt[kPreAcc] = (int64_t)a.nchunks * a.nslices;
+  cnt[kPreFin] = N;
+  cnt[kPreAmax] = a.absmax_blocks;
+}
+
+void plan_upd(Carver& c, const lbg_update_item* in, int n, UpdWs* w) {
+  w->inst = c.take<BInst>((size_t)n);
+  w->pre = c.take<int64_t>((size_t)kNumPre * (n + 1));
+  w->afp.assign((size_t)n, AfpWs{});
+  for (int k = 0; k < kNumPre; ++k) w->tot[k] = 0;
+  for (int i = 0; i < n; ++i) {
+    plan_afp(c, in[i].M, in[i].L, in[i].N, &w->afp[(size_t)i], false, true);
+    int64_t cnt[kNumPre];
+    upd_counts(w->afp[(size_t)i], in[i].N, cnt);
+    for (int k = 0; k < kNumPre; ++k) w->tot[k] += cnt[k];
+  }
+  int64_t nb = 0;
+  for (int k = 0; k < kNumPre; ++k) nb += w->tot[k];
+  w->b2i = c.take<int32_t>((size_t)std::max<int64_t>(1, nb));
+}
+
+int validate_upd(const lbg_update_item* in, int32_t n) {
+  if (!in || n < 1) {
+    set_error("lbg_update_batched: need at least one item (n = %d)", (int)n);
+    return LBG_EINVAL;
+  }
+  for (int i = 0; i < n; ++i) {
+    const lbg_update_item& a = in[i];
+    if (!a.X || !a.idx || !a.C_old || !a.C_new) {
+      set_error("lbg_update_batched: item %d has a NULL pointer", i);
+      return LBG_EINVAL;
+    }
+    if (a.M < 1 || a.M > LBG_MAX_M || a.L < 1 || a.L > 64 || a.N < 1 || a.N > LBG_MAX_N) {
+      set_error("lbg_update_batched: item %d: M = %lld, L = %lld, N = %lld (need M >= 1, "
+                "1 <= L <= 64, N >= 1)", i, (long long)a.M, (long long)a.L, (long long)a.N);
+      return LBG_EINVAL;
+    }
+    if (!afp_usable(a.L, a.N)) {
+      set_error("lbg_update_batched: item %d: N * L too large for the batched update; use "
+                "lbg_update", i);
+      return LBG_EINVAL;
+    }
+    if ((reinterpret_cast<uintptr_t>(a.X) | reinterpret_cast<uintptr_t>(a.idx) |
+         reinterpret_cast<uintptr_t>(a.C_old) | reinterpret_cast<uintptr_t>(a.C_new) |
+         reinterpret_cast<uintptr_t>(a.counts)) & 3) {
+      set_error("lbg_update_batched: item %d: misaligned pointer", i);
+      return LBG_EINVAL;
+    }
+  }
+  return LBG_OK;
+}
+
+int check_ws(const char* what, void* ws, size_t ws_bytes, size_t need) {
+  if (!ws) {
+    set_error("%s: workspace is NULL", what);
+    return LBG_EINVAL;
+  }
+  if (reinterpret_cast<uintptr_t>(ws) & 255) {
+    set_error("%s: workspace must be 256-byte aligned", what);
+    return LBG_EINVAL;
+  }
+  if (ws_bytes < need) {
+    set_error("%s: workspace of %zu bytes, %zu needed", what, ws_bytes, need);
+    return LBG_ENOWS;
+  }
+  return LBG_OK;
+}
+
+}  // namespace
+}  // namespace lbg
+
+extern "C" size_t lbg_assign_batched_workspace(const lbg_assign_item* items, int32_t n) {
+  if (!items || n < 1) return 0;
+  Carver c{nullptr, 0};
+  AsgWs w;
+  plan_asg(c, items, n, &w);
+  return c.off + 256;
+}
+
+extern "C" int lbg_assign_batched(const lbg_assign_item* items, int32_t n, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  clear_error();
+  LBG_TRY(validate_asg(items, n));
+  LBG_TRY(check_ws("lbg_assign_batched", ws, ws_bytes, lbg_assign_batched_workspace(items, n)));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Carver c{reinterpret_cast<char*>(ws), 0};
+  AsgWs w;
+  plan_asg(c, items, n, &w);
+  std::vector<BInst> hi((size_t)n);
+  std::vector<DevState> hs((size_t)n);
+  for (int i = 0; i < n; ++i) {
+    const lbg_assign_item& a = items[i];
+    const InstPlan& q = w.plans[(size_t)i];
+    BInst& B = hi[(size_t)i];
+    memset(&B, 0, sizeof(B));
+    B.X = a.X;
+    B.M = a.M;
+    B.L = (int32_t)a.L;
+    B.LP = lp_of(a.L);
+    B.vec = (a.L == B.LP) && ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0) &&
+            ((reinterpret_cast<uintptr_t>(a.C) & 15) == 0);
+    B.N = (int32_t)a.N;
+    B.Cb[0] = B.Cb[1] = const_cast<float*>(a.C);  // read only by the allocation
+    B.idx = a.idx;
+    B.st = w.st + i;
+    B.dpart = q.dpart;
+    B.ntiles = q.ntiles;
+    B.G = q.G;
+    B.nfb = w.nfb + i;
+    B.Dout = a.D;
+    DevState& d = hs[(size_t)i];
+    memset(&d, 0, sizeof(d));
+    d.n = (int32_t)a.N;
+    d.N = (int32_t)a.N;
+    d.M = a.M;
+  }
+  std::vector<int32_t> hchunk;
+  int64_t totG = 0;
+  for (const auto& q : w.plans) totG += q.G;
+  hchunk.resize((size_t)(3 * totG));
+  constexpr int kGrab = 16, kGrid = 512;
+  const int nchunks = build_chunks(w.plans, kGrab, hchunk.data());
+  static const hipError_t lds_ok = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&b_assign_kernel<false>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLds);
+  LBG_TRY_HIP(lds_ok);
+  LBG_TRY_HIP(hipMemcpyAsync(w.inst, hi.data(), sizeof(BInst) * (size_t)n,
+                             hipMemcpyHostToDevice, s));
+  LBG_TRY_HIP(hipMemcpyAsync(w.st, hs.data(), sizeof(DevState) * (size_t)n,
+                             hipMemcpyHostToDevice, s));
+  LBG_TRY_HIP(hipMemcpyAsync(w.chunks, hchunk.data(), sizeof(int32_t) * 3 * (size_t)nchunks,
+                             hipMemcpyHostToDevice, s));
+  LBG_TRY_HIP(hipMemsetAsync(w.ctr, 0, 3 * sizeof(unsigned), s));
+  // the FP32 screen (and the direct search for small codebooks): the split
+  // screen's build measured slower here too (5.3 vs 5.0 ms for the 512
+  // instances of the batched workload with codebooks of their final sizes)
+  hipLaunchKernelGGL(b_assign_kernel<false>, dim3(kGrid), dim3(kT), kBatchLds, s, w.inst,
+                     w.chunks, nchunks, w.ctr, 0);
+  LBG_TRY_HIP(hipGetLastError());
+  bool anyD = false;
+  for (int i = 0; i < n; ++i) anyD = anyD || items[i].D != nullptr;
+  if (anyD) {
+    hipLaunchKernelGGL(b_reduce_kernel, dim3((unsigned)n), dim3(kT), 0, s, w.inst);
+    LBG_TRY_HIP(hipGetLastError());
+  }
+  // the host images are released on return
+  LBG_TRY_HIP(hipStreamSynchronize(s));
+  return LBG_OK;
+}
+
+extern "C" size_t lbg_update_batched_workspace(const lbg_update_item* items, int32_t n) {
+  if (!items || n < 1) return 0;
+  Carver c{nullptr, 0};
+  UpdWs w;
+  plan_upd(c, items, n, &w);
+  return c.off + 256;
+}
+
+extern "C" int lbg_update_batched(const lbg_update_item* items, int32_t n, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  clear_error();
+  LBG_TRY(validate_upd(items, n));
+  LBG_TRY(check_ws("lbg_update_batched", ws, ws_bytes, lbg_update_batched_workspace(items, n)));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Carver c{reinterpret_cast<char*>(ws), 0};
+  UpdWs w;
+  plan_upd(c, items, n, &w);
+  for (int k = 0; k < kNumPre; ++k)
+    if (w.tot[k] > 0x7fffffff) {
+      set_error("lbg_update_batched: too many blocks for one launch");
+      return LBG_EINVAL;
+    }
+  std::vector<BInst> hi((size_t)n);
+  std::vector<int64_t> hp((size_t)kNumPre * (n + 1), 0);
+  size_t acc_lds = 0;
+  for (int i = 0; i < n; ++i) {
+    const lbg_update_item& a = items[i];
+    const AfpWs& q = w.afp[(size_t)i];
+    BInst& B = hi[(size_t)i];
+    memset(&B, 0, sizeof(B));
+    B.X = a.X;
+    B.M = a.M;
+    B.L = (int32_t)a.L;
+    B.LP = lp_of(a.L);
+    B.vec = (reinterpret_cast<uintptr_t>(a.X) & 15) == 0;
+    B.N = (int32_t)a.N;
+    B.Cb[0] = B.Cb[1] = const_cast<float*>(a.C_old);  // read only (may equal C_new)
+    B.C_out = a.C_new;
+    B.idx = const_cast<int32_t*>(a.idx);  // read only by the update
+    B.cps = q.cps;
+    B.nslices = q.nslices;
+    B.nchunks = q.nchunks;
+    B.absmax_blocks = q.absmax_blocks;
+    B.rows_per_chunk = q.rows_per_chunk;
+    B.part = q.part;
+    B.pcnt = q.pcnt;
+    B.amax = q.amax;
+    B.lo = q.lo;
+    B.shift = q.shift;
+    B.counts = a.counts;
+    int64_t cnt[kNumPre];
+    upd_counts(q, a.N, cnt);
+    for (int k = 0; k < kNumPre; ++k)
+      hp[(size_t)k * (n + 1) + i + 1] = hp[(size_t)k * (n + 1) + i] + cnt[k];
+    acc_lds = std::max(acc_lds, afp::acc_lds_bytes(q.cps, a.L));
+  }
+  // block -> item tables of the three families
+  std::vector<int32_t> htab;
+  Tabs tb;
+  tb.b2i = w.b2i;
+  for (int k = 0; k < kNumPre; ++k) {
+    tb.off[k] = (int64_t)htab.size();
+    for (int i = 0; i < n; ++i)
+      for (int64_t b = hp[(size_t)k * (n + 1) + i]; b < hp[(size_t)k * (n + 1) + i + 1]; ++b)
+        htab.push_back(i);
+  }
+  if (htab.empty()) htab.push_back(0);
+  LBG_TRY_HIP(hipMemcpyAsync(w.inst, hi.data(), sizeof(BInst) * (size_t)n,
+                             hipMemcpyHostToDevice, s));
+  LBG_TRY_HIP(hipMemcpyAsync(w.pre, hp.data(), sizeof(int64_t) * hp.size(),
+                             hipMemcpyHostToDevice, s));
+  LBG_TRY_HIP(hipMemcpyAsync(w.b2i, htab.data(), sizeof(int32_t) * htab.size(),
+                             hipMemcpyHostToDevice, s));
+  // the fixed-point scales of every item (and its second-word sums cleared)
+  hipLaunchKernelGGL(b_absmax_kernel, dim3((unsigned)w.tot[kPreAmax]), dim3(kT), 0, s, w.inst, n,
+                     w.pre, tb);
+  LBG_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(b_shift_kernel, dim3((unsigned)n), dim3(kT), 0, s, w.inst);
+  LBG_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(b_upd_acc_kernel, dim3((unsigned)w.tot[kPreAcc]), dim3(kT), acc_lds, s,
+                     w.inst, n, w.pre, tb);
+  LBG_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(b_upd_fin_kernel, dim3((unsigned)w.tot[kPreFin]), dim3(kT), 0, s, w.inst,
+                     n, w.pre, tb);
+  LBG_TRY_HIP(hipGetLastError());
+  // the host images are released on return
+  LBG_TRY_HIP(hipStreamSynchronize(s));
+  return LBG_OK;
 }

@@ -29,7 +29,8 @@ def test_header_declares_the_calls():
     names = _declared()
     for need in ["lbg_split", "lbg_assign", "lbg_update", "lbg_distortion", "lbg_train",
                  "lbg_workspace_size", "lbg_last_error", "lbg_distortion_backward",
-                 "lbg_centroid", "lbg_split_add", "lbg_params_default", "lbg_version"]:
+                 "lbg_centroid", "lbg_split_add", "lbg_params_default", "lbg_version",
+                 "lbg_assign_batched", "lbg_update_batched"]:
         assert need in names
 
 
@@ -153,3 +154,35 @@ def test_batched_argument_checks():
     cfg = P.BatchConfig()
     lib.lbg_batch_config_default(ct.byref(cfg))
     assert cfg.graph == 1 and cfg.grab == 0 and cfg.grid == 0
+    assert cfg.screen == 0
+
+
+def test_batched_single_steps_argument_checks():
+    P, lib = _lib()
+    items = (P.AssignItem * 2)()
+    for i in range(2):
+        items[i].X, items[i].C, items[i].idx = FAKE.value, FAKE.value, FAKE.value
+        items[i].M, items[i].L, items[i].N = 100, 16, 9
+    need = lib.lbg_assign_batched_workspace(items, 2)
+    assert need > 0 and lib.lbg_assign_batched_workspace(None, 2) == 0
+    call = lambda n, ws, nb: lib.lbg_assign_batched(items, n, ws, nb, None)
+    assert call(2, FAKE, need - 1) == P.ENOWS
+    assert call(0, FAKE, need) == P.EINVAL
+    items[1].L = 65
+    assert call(2, FAKE, need) == P.EINVAL
+    items[1].L, items[1].N = 64, 512
+    assert call(2, FAKE, need) == P.EINVAL and b"LDS" in lib.lbg_last_error()
+    items[1].N, items[1].D = 9, FAKE.value + 4  # misaligned FP64 output
+    assert call(2, FAKE, need) == P.EINVAL and b"misaligned" in lib.lbg_last_error()
+    items[1].D, items[1].C = None, None
+    assert call(2, FAKE, need) == P.EINVAL and b"NULL" in lib.lbg_last_error()
+    ups = (P.UpdateItem * 1)()
+    ups[0].X, ups[0].idx, ups[0].C_old, ups[0].C_new = (FAKE.value,) * 4
+    ups[0].M, ups[0].L, ups[0].N = 100, 16, 8
+    need = lib.lbg_update_batched_workspace(ups, 1)
+    assert need > 0
+    assert lib.lbg_update_batched(ups, 1, FAKE, need - 1, None) == P.ENOWS
+    ups[0].N = 0
+    assert lib.lbg_update_batched(ups, 1, FAKE, need, None) == P.EINVAL
+    ups[0].N, ups[0].C_new = 8, None
+    assert lib.lbg_update_batched(ups, 1, FAKE, need, None) == P.EINVAL

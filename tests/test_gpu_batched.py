@@ -142,3 +142,61 @@ def test_batched_rejects_bad_instances(P):
         P.train_batched([dev(np.zeros((10, 65), np.float32))], [4])  # L > 64
     with pytest.raises(Exception):
         P.train_batched([dev(np.zeros((10, 64), np.float32))], [512])  # codebook too large
+
+
+# items of the batched single steps: ragged M (1, 31, 33, several tiles), L
+# from 1 to 64 (vector and scalar rows), codebooks of 1 to 256 codevectors
+# (the direct search up to 8), Gaussian mixtures; one item with a non-finite
+# row, one with a misaligned X
+STEP_ITEMS = [(1, 16, 1, 21), (31, 16, 8, 22), (33, 64, 9, 23), (5000, 16, 256, 24),
+              (4097, 64, 100, 25), (700, 5, 3, 26), (2048, 33, 40, 27), (9000, 1, 7, 28),
+              (3001, 64, 256, 29), (1500, 12, 17, 30)]
+
+
+def _step_data():
+    rng = np.random.default_rng(99)
+    Xs, Cs = [], []
+    for M, L, N, seed in STEP_ITEMS:
+        X = synth.gmm(seed, max(M, N), L, max(1, N // 2))[:M]
+        C = X[rng.integers(0, M, N)] + rng.normal(0, 1, (N, L)).astype(np.float32)
+        Xs.append(np.ascontiguousarray(X))
+        Cs.append(np.ascontiguousarray(C.astype(np.float32)))
+    Xs[3][17, 2] = np.nan
+    return Xs, Cs
+
+
+def test_assign_batched_equals_single_calls(P):
+    Xs, Cs = _step_data()
+    Xd = [dev(X) for X in Xs]
+    # a misaligned training set: the rows of a larger buffer from offset 1
+    big = dev(np.concatenate([np.zeros(1, np.float32), Xs[1].ravel()]))
+    Xd[1] = big[1:].view(Xs[1].shape)
+    Cd = [dev(C) for C in Cs]
+    idxs, Ds = P.assign_batched(Xd, Cd)
+    for i, (X, C) in enumerate(zip(Xd, Cd)):
+        idx1, _, D1 = P.assign_distortion(X, C, P.FP32)
+        assert torch.equal(idxs[i], idx1), f"item {i}"
+        assert float(Ds[i].item()) == float(D1.item()) or (
+            np.isinf(float(D1.item())) and np.isinf(float(Ds[i].item()))), f"item {i}"
+    io, _, _ = oracle.assign(Xs[4], Cs[4].astype(np.float64))
+    assert np.array_equal(idxs[4].cpu().numpy(), io)
+    idxs2, Ds2 = P.assign_batched(Xd, Cd, with_D=False)
+    assert all(d is None for d in Ds2)
+    assert all(torch.equal(a, b) for a, b in zip(idxs, idxs2))
+
+
+def test_update_batched_equals_single_calls(P):
+    Xs, Cs = _step_data()
+    Xs[3][17, 2] = 0.5  # finite data for the update
+    Xd = [dev(X) for X in Xs]
+    Cd = [dev(C) for C in Cs]
+    idxs, _ = P.assign_batched(Xd, Cd, with_D=False)
+    idxs[5][3] = -1          # joins no cell
+    idxs[6][0] = Cs[6].shape[0]  # outside [0, N): joins no cell
+    news, counts = P.update_batched(Xd, idxs, Cd)
+    for i, (X, idx, C) in enumerate(zip(Xd, idxs, Cd)):
+        C1, n1 = P.update(X, idx, C)
+        assert torch.equal(news[i], C1), f"item {i}"
+        assert torch.equal(counts[i], n1), f"item {i}"
+    ref, rc = oracle.update(Xs[4], idxs[4].cpu().numpy(), Cs[4].astype(np.float64))
+    np.testing.assert_array_equal(counts[4].cpu().numpy(), rc)
