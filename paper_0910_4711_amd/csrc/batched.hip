@@ -247,8 +247,10 @@ __device__ __forceinline__ bool split_fits(int n) {
 // the queue until none is left.  Two builds, each with its own queue:
 //   SPLIT = false: codebooks of at most kDirectN codevectors (direct search)
 //     and, unless ``split``, every other codebook with the FP32 screen;
-//   SPLIT = true (launched only when ``split``): the codebooks whose split
-//     BF16 screen layout fits the workgroup's LDS.
+//   SPLIT = true (launched only when ``split``): the instances with rows of
+//     exactly 64 aligned floats whose split BF16 screen layout fits the
+//     workgroup's LDS (others keep the FP32 screen: shorter rows' tiles are
+//     cheap either way, and a build for several row forms spills registers).
 // With ``split`` each build skips the other's chunks, so every chunk is
 // allocated once per round.  The split screen is FP32-accurate with the same
 // exact certificate as the FP32 screen: the allocation and partials are the
@@ -274,20 +276,10 @@ __global__ __launch_bounds__(kT, 2) void b_assign_kernel(const BInst* __restrict
     if (st->done) continue;
     const int n = st->n;
     const bool direct = n <= kDirectN;
-    const bool sp = split && !direct && (B.LP == 16 ? split_fits<16>(n) : split_fits<64>(n));
+    const bool sp = split && !direct && B.LP == 64 && B.vec && split_fits<64>(n);
     if (sp != SPLIT) continue;  // the other build's chunk
     if constexpr (SPLIT) {
-      if (B.LP == 16) {
-        if (B.vec)
-          alloc_chunk<Bf16x3Screen<16>, true>(B, st, b0, cnt, i, &staged, smem);
-        else
-          alloc_chunk<Bf16x3Screen<16>, false>(B, st, b0, cnt, i, &staged, smem);
-      } else {
-        if (B.vec)
-          alloc_chunk<Bf16x3Screen<64>, true>(B, st, b0, cnt, i, &staged, smem);
-        else
-          alloc_chunk<Bf16x3Screen<64>, false>(B, st, b0, cnt, i, &staged, smem);
-      }
+      alloc_chunk<Bf16x3Screen<64>, true>(B, st, b0, cnt, i, &staged, smem);
     } else if (direct) {
       if (B.LP == 16) {
         if (B.vec)
