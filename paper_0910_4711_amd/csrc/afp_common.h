@@ -106,7 +106,12 @@ __device__ __forceinline__ void absmax_body(const float* __restrict__ X, int64_t
 // 2^t), so coordinates down to 2^-(s+t) count exactly and the update keeps
 // about 2^-(s+t) of max|x| (2^-80 of it at M = 2^22) where one word kept
 // 2^-s; shift[2] = 1 when every coordinate is exact in BF16 (the
-// allocation's split screen then skips the products of vanishing parts).
+// allocation's split screen then skips the products of vanishing parts);
+// shift[3] = 1 when every coordinate is a multiple of 2^-g for some g <= s
+// with |x| 2^g M < 2^31 (shift[4] = g, the coarsest such grid): every cell
+// sum at scale 2^g is then an integer below 2^31 in magnitude, which 32-bit
+// words hold exactly, and times 2^(s-g) it is the sum at scale 2^s (for
+// example 8-bit pixels: g = 0, sums below 2^8 M).
 __device__ __forceinline__ void shift_body(const uint32_t* __restrict__ part, int nparts,
                                            int64_t M, int* __restrict__ shift) {
   __shared__ uint32_t s[kT];
@@ -140,6 +145,10 @@ __device__ __forceinline__ void shift_body(const uint32_t* __restrict__ part, in
     shift[0] = sh;
     shift[1] = (sf[0] != 0u && (int)sf[0] - 256 > sh) ? min(52, 63 - b) : 0;
     shift[2] = sr[0] == 0u;
+    const int g = sf[0] == 0u ? 0 : (int)sf[0] - 256;
+    const bool narrow = g <= sh && e + g + b <= 31;
+    shift[3] = narrow ? 1 : 0;
+    shift[4] = narrow ? g : 0;
   }
 }
 
@@ -599,6 +608,83 @@ __device__ __forceinline__ void accd_body(const float* __restrict__ X, int64_t M
   }
 }
 
+// The 32-bit form of the dimension slices, for data whose cell sums fit 32
+// bits at the scale 2^g (shift[3], see shift_body): a slice is 32 dimensions,
+// one 128-byte line of a row of 64 floats, so no two blocks read the same
+// line (16-dimension slices of 8-byte sums share each line between two
+// blocks, which fetch it twice when they drift apart).  A group of eight
+// lanes takes one row's slice, a 16-byte word per lane; x 2^g is an integer
+// below 2^31 in magnitude, so it converts exactly to int32 and the LDS sums
+// add in 32-bit two's complement without overflow.  Lane gl's dimension
+// 4 gl + e goes to word 8 e + gl of its cell's row, so that the eight lanes
+// of a group add into consecutive words; rows of sums are 33 words apart.
+// The partials are int32 [chunk][cell][L].
+constexpr int kDn = 32;  // dimensions per 32-bit slice
+
+inline size_t accn_lds_bytes(int64_t N) {
+  return (size_t)(N + 1) * (kDn + 1) * 4 + (size_t)(N + 1) * 4;
+}
+
+template <bool VEC>
+__device__ __forceinline__ void accn_body(const float* __restrict__ X, int64_t M, int L,
+                                          const int32_t* __restrict__ idx, int N, int ns,
+                                          int64_t rows_per_chunk, int chunk, int q, int g,
+                                          int32_t* __restrict__ part, int32_t* __restrict__ pcnt,
+                                          uint32_t* sacc) {
+  constexpr int LS = kDn + 1;
+  constexpr int NG = kDsThreads / 8;
+  int32_t* scnt = reinterpret_cast<int32_t*>(sacc + (size_t)(N + 1) * LS);
+  const int t = threadIdx.x;
+  for (int e = t; e < (N + 1) * LS; e += kDsThreads) sacc[e] = 0u;
+  if (q == 0)
+    for (int e = t; e <= N; e += kDsThreads) scnt[e] = 0;
+  __syncthreads();
+  const int gr = t >> 3, gl = t & 7;
+  const int d0 = kDn * q + 4 * gl;  // this lane's four dimensions
+  const int64_t r0 = (int64_t)chunk * rows_per_chunk;
+  const int64_t r1 = min(M, r0 + rows_per_chunk);
+  for (int64_t b = r0 + gr; b < r1; b += (int64_t)NG * kDsRows) {
+    int k[kDsRows];
+    float v[kDsRows][4];
+#pragma unroll
+    for (int u = 0; u < kDsRows; ++u) {
+      const int64_t m = b + (int64_t)u * NG;
+      const bool on = m < r1;
+      const int64_t mm = on ? m : r0;  // a row of this chunk
+      const int kv = idx[mm];
+      k[u] = (on && (unsigned)kv < (unsigned)N) ? kv : N;  // N: the spare row
+      if constexpr (VEC) {
+        const float4 x = *reinterpret_cast<const float4*>(X + mm * L + d0);
+        v[u][0] = x.x;
+        v[u][1] = x.y;
+        v[u][2] = x.z;
+        v[u][3] = x.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[u][e] = X[mm * L + d0 + e];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kDsRows; ++u) {
+      uint32_t* row = sacc + __umul24(k[u], LS) + gl;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        atomicAdd(&row[8 * e], (uint32_t)(int32_t)__builtin_amdgcn_ldexpf(v[u][e], g));
+      if (q == 0 && gl == 0) atomicAdd(&scnt[k[u]], 1);
+    }
+  }
+  __syncthreads();
+  int32_t* dst = part + (int64_t)chunk * ns * L + kDn * q;
+  for (int e = t; e < N * kDn; e += kDsThreads) {
+    const int kk = e / kDn, d = e - kk * kDn;
+    dst[(int64_t)kk * L + d] = (int32_t)sacc[kk * LS + 8 * (d & 3) + (d >> 2)];
+  }
+  if (q == 0) {
+    int32_t* cdst = pcnt + (int64_t)chunk * ns;
+    for (int e = t; e < N; e += kDsThreads) cdst[e] = scnt[e];
+  }
+}
+
 // Under device control: acts on the pending state for cell ``k`` (a split
 // of codevector k, or nothing); the block with ``lead`` commits the state.
 // Returns true when cell k is to be updated, with N, C_old and out set.
@@ -649,15 +735,19 @@ __device__ __forceinline__ bool fin_state(const Ctl& ctl, const CbPair& cbp, int
 //   With second words (tfine > 0, see shift_body) cell k's residual sums
 // lo[k L + d] are read and cleared before ``gate`` (whatever the decision,
 // so the next accumulation starts from zero) and enter as lo 2^-(s+tfine).
-template <int MODE, class Gate>
+//   P32: the partials are the int32 sums of the 32-bit slices at scale
+// 2^(s-up) (see accn_body); their 64-bit total times 2^up is the sum at 2^s.
+template <int MODE, bool P32 = false, class Gate>
 __device__ __forceinline__ void fin_body(const unsigned long long* __restrict__ part,
                                          const int32_t* __restrict__ pcnt, int nchunks, int ns,
                                          int L, int s, int32_t* __restrict__ counts, double g2,
                                          int k, Gate&& gate, unsigned long long* lo = nullptr,
-                                         int tfine = 0) {
-  constexpr int U = 16;  // partials in flight per thread
+                                         int tfine = 0, int up = 0) {
+  constexpr int U = 16;  // 8-byte partial words in flight per thread
+  // dimensions per word: the 32-bit partials (L even) are read in pairs
+  constexpr int W = P32 ? 2 : 1;
   constexpr int UC = 8;  // counts in flight per thread
-  __shared__ unsigned long long red[kT];
+  __shared__ unsigned long long red[W][kT];
   __shared__ long long scount;
   __shared__ long long slo[kT];
   const int t = threadIdx.x;
@@ -667,15 +757,16 @@ __device__ __forceinline__ void fin_body(const unsigned long long* __restrict__ 
     slo[t] = (long long)*p;
     *p = 0ull;
   }
+  const int LW = L / W;  // words per cell row
   int G2 = 1;
-  while (G2 < L && G2 < kT) G2 <<= 1;
+  while (G2 < LW && G2 < kT) G2 <<= 1;
   const int Q = kT / G2;
   const int q = t / G2;
-  auto load_u = [&](int d, int chs, unsigned long long (&v)[U]) {
+  auto load_u = [&](int dw, int chs, unsigned long long (&v)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int ch = chs + q + Q * u;
-      v[u] = (d < L && ch < nchunks) ? part[((int64_t)ch * ns + k) * L + d] : 0ull;
+      v[u] = (dw < LW && ch < nchunks) ? part[((int64_t)ch * ns + k) * LW + dw] : 0ull;
     }
   };
   auto load_c = [&](int chs, int (&v)[UC]) {
@@ -704,37 +795,50 @@ __device__ __forceinline__ void fin_body(const unsigned long long* __restrict__ 
     for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
     if (t == 0) scount = c;
   }
-  for (int d0 = 0; d0 < L; d0 += G2) {
-    const int d = d0 + t % G2;
-    if (d0 > 0) load_u(d, 0, a);
-    unsigned long long acc = 0;
+  for (int dw0 = 0; dw0 < LW; dw0 += G2) {
+    const int dw = dw0 + t % G2;
+    if (dw0 > 0) load_u(dw, 0, a);
+    unsigned long long acc[W] = {};
     for (int chs = Q * U;; chs += Q * U) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) acc += a[u];
+      for (int u = 0; u < U; ++u) {
+        if constexpr (P32) {  // two int32 sums, sign-extended (little-endian: dim 2 dw first)
+          acc[0] += (unsigned long long)(long long)(int32_t)(uint32_t)a[u];
+          acc[W - 1] += (unsigned long long)(long long)(int32_t)(uint32_t)(a[u] >> 32);
+        } else {
+          acc[0] += a[u];
+        }
+      }
       if (chs >= nchunks) break;
-      load_u(d, chs, a);
+      load_u(dw, chs, a);
     }
-    red[t] = acc;
+#pragma unroll
+    for (int w = 0; w < W; ++w) red[w][t] = acc[w];
     __syncthreads();
     const long long cnt = scount;
-    if (d0 == 0 && counts && t == 0) counts[k] = (int32_t)cnt;
-    if (t < G2 && d < L) {
-      const int64_t e = (int64_t)k * L + d;
-      if (cnt == 0) {
-        if (MODE == 0) {
-          if (out != C_old) out[e] = C_old[e];
+    if (dw0 == 0 && counts && t == 0) counts[k] = (int32_t)cnt;
+    if (t < G2 && dw < LW) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int d = dw * W + w;
+        const int64_t e = (int64_t)k * L + d;
+        if (cnt == 0) {
+          if (MODE == 0) {
+            if (out != C_old) out[e] = C_old[e];
+          } else {
+            out[e] = 0.0f;
+          }
         } else {
-          out[e] = 0.0f;
-        }
-      } else {
-        unsigned long long sum = 0;
-        for (int qi = 0; qi < Q; ++qi) sum += red[qi * G2 + t];
-        const long long S = (long long)sum;
-        const double low = fine ? ldexp((double)slo[d], -(s + tfine)) : 0.0;
-        if (MODE == 0) {
-          out[e] = (float)((ldexp((double)S, -s) + low) / (double)cnt);
-        } else {
-          out[e] = (float)(g2 * (grad_diff(C_old[e], cnt, S, s) - low));
+          unsigned long long sum = 0;
+          for (int qi = 0; qi < Q; ++qi) sum += red[w][qi * G2 + t];
+          if constexpr (P32) sum <<= up;
+          const long long S = (long long)sum;
+          const double low = fine ? ldexp((double)slo[d], -(s + tfine)) : 0.0;
+          if (MODE == 0) {
+            out[e] = (float)((ldexp((double)S, -s) + low) / (double)cnt);
+          } else {
+            out[e] = (float)(g2 * (grad_diff(C_old[e], cnt, S, s) - low));
+          }
         }
       }
     }

@@ -541,10 +541,10 @@ int lbg_train(const float* X, int64_t M, int64_t L, int64_t N, const lbg_params*
   int on_grid = 0;
   if (w.up.use_afp) {
     LBG_TRY(launch_afp_shift(X, M, L, w.up.afp, s));
-    int flags[3] = {0, 0, 0};
+    int flags[5] = {0, 0, 0, 0, 0};
     LBG_TRY_HIP(hipMemcpyAsync(flags, w.up.afp.shift, sizeof(flags), hipMemcpyDeviceToHost, s));
     LBG_TRY_HIP(hipStreamSynchronize(s));
-    on_grid = flags[1] == 0 ? 1 : 0;
+    on_grid = flags[1] != 0 ? 0 : (flags[3] ? 2 : 1);
   }
   auto assign_and_D = [&](double* Dh) -> int {
     LBG_TRY(tm.begin(Timer::kAssign, s));

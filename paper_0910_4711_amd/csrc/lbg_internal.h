@@ -127,13 +127,19 @@ struct AfpWs {
   unsigned long long* part;  // [nchunks][N][L] integer partial sums
   int32_t* pcnt;             // [nchunks][N] partial counts
   uint32_t* amax;            // [3 absmax_blocks] block maxima of |x|, fine bits, BF16 rest
-  int* shift;                // [3] fixed-point shift s, second-word shift t (0: none),
-                             // every coordinate exact in BF16
+  int* shift;                // [5] fixed-point shift s, second-word shift t (0: none),
+                             // every coordinate exact in BF16, 32-bit sums possible and
+                             // their shift g
   unsigned long long* lo;    // [N][L] second-word sums (kept zero between updates)
   int64_t nlo;
   int cps, nslices, nchunks, absmax_blocks;
   int dslices;  // > 0: accumulation by this many 16-dimension slices (all cells per block)
   int64_t rows_per_chunk;
+  // > 0: the 32-bit accumulation by this many 32-dimension slices is
+  // possible (when shift[3] says so), in nch_n chunks of rpc_n rows, its
+  // partials int32 [nch_n][N][L] in the bytes of ``part``
+  int nds_n, nch_n;
+  int64_t rpc_n;
 };
 bool afp_usable(int64_t L, int64_t N);
 // dslices: the single-run kernels may accumulate by dimension slices
@@ -141,11 +147,14 @@ void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices
               bool many = false);
 int launch_afp_shift(const float* X, int64_t M, int64_t L, const AfpWs& w, hipStream_t s);
 // The finishing kernel of the update (centroids or gradient from the partials).
+// p32: the partials are those of the 32-bit slices.
 int launch_fin(const float* X, int64_t M, int64_t L, const float* C_old, int64_t N,
                float* C_out, int32_t* counts, int mode, double g2, const AfpWs& w,
-               hipStream_t s, Ctl ctl, CbPair cbp);
+               hipStream_t s, Ctl ctl, CbPair cbp, bool p32 = false);
 // on_grid: 1 when the caller knows every coordinate lies on the 2^-s grid
-// (shift[1] == 0: one-word kernels), else the kernels read that on the device.
+// (shift[1] == 0: one-word kernels), 2 when shift[3] is also set (the 32-bit
+// dimension slices where planned), else 0: the kernels read that on the
+// device.
 int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const float* C_old,
                int64_t N, float* C_out, int32_t* counts, int mode, double g2, const AfpWs& w,
                hipStream_t s, Ctl ctl = Ctl{nullptr, nullptr, nullptr, 0, nullptr, nullptr, nullptr},

@@ -66,7 +66,8 @@ struct Batch {
   int32_t* idx;
   const TrainWs* w;
   int64_t nparts;
-  int on_grid;  // 1: the training set lies on the update's 2^-s grid
+  int on_grid;  // 1: the training set lies on the update's 2^-s grid; 2: its
+                // cell sums also fit 32 bits (shift[3])
 };
 
 // One iteration is two pieces: the allocation, then the update, whose
@@ -246,12 +247,12 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
   // Whether the training set lies on the update's 2^-s grid (set-up pass):
   // read once, so that the accumulation runs its one-word kernel (the
   // kernel that decides on the device is larger and measured slower).
-  int flags[3] = {0, 0, 0};
+  int flags[5] = {0, 0, 0, 0, 0};
   LBG_TRY_HIP(hipMemcpyAsync(flags, w.up.afp.shift, sizeof(flags), hipMemcpyDeviceToHost, s));
   LBG_TRY_HIP(hipStreamSynchronize(s));
   const bool timed = p->timing != 0 && st != nullptr;
   Batch b{X, M, L, N, p->precision, p->split_mode, p->eps_split, p->delta, idx_out, &w,
-          assign_num_parts(M, L, N, p->precision), flags[1] == 0 ? 1 : 0};
+          assign_num_parts(M, L, N, p->precision), flags[1] != 0 ? 0 : (flags[3] ? 2 : 1)};
   const bool use_graph = s != nullptr && p->graph != 0;
 
   GraphEntry* ge = nullptr;

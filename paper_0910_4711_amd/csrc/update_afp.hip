@@ -112,8 +112,28 @@ __global__ __launch_bounds__(kDsThreads) void accd_kernel(
                           lo, 0);
 }
 
+// The 32-bit dimension slices (see accn_body): one 1024-thread block per
+// (chunk, slice), for data whose sums fit 32 bits at scale 2^shift[4].
+template <bool VEC>
+__global__ __launch_bounds__(kDsThreads) void accn_kernel(
+    const float* __restrict__ X, int64_t M, int L, const int32_t* __restrict__ idx, int N,
+    int nch, int nds, int64_t rows_per_chunk, const int* __restrict__ shift_p,
+    int32_t* __restrict__ part, int32_t* __restrict__ pcnt, Ctl ctl) {
+  extern __shared__ uint32_t saccn[];
+  const int ns = N;
+  if (ctl.st) {
+    if (ctl.st->done) return;
+    if (blockIdx.x == 0) (void)acc_decide(ctl, true, &N);
+    if (forced_stop(ctl.st)) return;  // the level ends here: no update follows
+    N = ctl.st->n;
+  }
+  int chunk, q;
+  accd_block(blockIdx.x, nch, nds, &chunk, &q);
+  accn_body<VEC>(X, M, L, idx, N, ns, rows_per_chunk, chunk, q, shift_p[4], part, pcnt, saccn);
+}
+
 // One block per cell.
-template <int MODE>
+template <int MODE, bool P32>
 __global__ __launch_bounds__(kT) void fin_kernel(
     const unsigned long long* __restrict__ part, const int32_t* __restrict__ pcnt, int nchunks,
     int N, int L, const int* __restrict__ shift_p, const float* __restrict__ C_old,
@@ -121,14 +141,14 @@ __global__ __launch_bounds__(kT) void fin_kernel(
     unsigned long long* __restrict__ lo, Ctl ctl, CbPair cbp) {
   const int k = blockIdx.x;
   const int s = shift_p[0];
-  fin_body<MODE>(
+  fin_body<MODE, P32>(
       part, pcnt, nchunks, N, L, s, counts, g2, k,
       [&](const float** c_old, float** dst) {
         *c_old = C_old;
         *dst = out;
         return !ctl.st || fin_state(ctl, cbp, k, k == 0, L, &N, c_old, dst);
       },
-      lo, shift_p[1]);
+      lo, shift_p[1], P32 ? s - shift_p[4] : 0);
 }
 
 template <int G, int VW, int DPL>
@@ -181,11 +201,21 @@ void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices
   }
   w->nchunks = (int)nch;
   w->rows_per_chunk = (M + nch - 1) / nch;
+  // the 32-bit slices: half as many slices of twice the width, twice the
+  // chunks (the same blocks), their int32 partials in the same bytes
+  w->nds_n = 0;
+  w->nch_n = 0;
+  w->rpc_n = 0;
+  if (w->dslices && L % kDn == 0 && accn_lds_bytes(N) <= (size_t)kAccdLdsMax) {
+    w->nds_n = (int)(L / kDn);
+    w->nch_n = (int)(nch * w->dslices / w->nds_n);
+    w->rpc_n = (M + w->nch_n - 1) / w->nch_n;
+  }
   w->absmax_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (M * L + 4095) / 4096));
   w->part = c.take<unsigned long long>((size_t)(nch * N * L));
-  w->pcnt = c.take<int32_t>((size_t)(nch * N));
+  w->pcnt = c.take<int32_t>((size_t)(std::max<int64_t>(nch, w->nch_n) * N));
   w->amax = c.take<uint32_t>((size_t)(3 * w->absmax_blocks));
-  w->shift = c.take<int>(3);
+  w->shift = c.take<int>(5);
   w->lo = c.take<unsigned long long>((size_t)(N * L));
   w->nlo = N * L;
 }
@@ -208,6 +238,24 @@ int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const f
                int64_t N, float* C_out, int32_t* counts, int mode, double g2, const AfpWs& w,
                hipStream_t s, Ctl ctl, CbPair cbp, int on_grid) {
   const bool vec = (L % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  if (w.dslices && w.nds_n && on_grid == 2) {
+    const dim3 grid((unsigned)(w.nch_n * w.nds_n));
+    const size_t lds = accn_lds_bytes(N);
+    int32_t* part32 = reinterpret_cast<int32_t*>(w.part);
+#define LBG_ACCN(VV)                                                                            \
+    {                                                                                           \
+      static const hipError_t a = hipFuncSetAttribute(                                          \
+          reinterpret_cast<const void*>(&accn_kernel<VV>),                                      \
+          hipFuncAttributeMaxDynamicSharedMemorySize, kAccdLdsMax);                              \
+      LBG_TRY_HIP(a);                                                                           \
+      hipLaunchKernelGGL((accn_kernel<VV>), grid, dim3(kDsThreads), lds, s, X, M, (int)L, idx,  \
+                         (int)N, w.nch_n, w.nds_n, w.rpc_n, w.shift, part32, w.pcnt, ctl);      \
+    }
+    if (vec) LBG_ACCN(true) else LBG_ACCN(false)
+#undef LBG_ACCN
+    LBG_TRY_HIP(hipGetLastError());
+    return launch_fin(X, M, L, C_old, N, C_out, counts, mode, g2, w, s, ctl, cbp, true);
+  }
   if (w.dslices) {
     const dim3 grid((unsigned)(w.nchunks * w.dslices));
     const size_t lds = accd_lds_bytes(N);
@@ -221,7 +269,7 @@ int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const f
                          idx, (int)N, w.nchunks, w.dslices, w.rows_per_chunk, w.shift, w.part,  \
                          w.pcnt, w.lo, ctl);                                                    \
     }
-    if (on_grid != 1) {
+    if (on_grid == 0) {
       if (vec) LBG_ACCD(true, true) else LBG_ACCD(true, false)
     } else {
       if (vec) LBG_ACCD(false, true) else LBG_ACCD(false, false)
@@ -247,7 +295,7 @@ int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const f
 #define LBG_ACC(GG, VV, DD)                                                                     \
   if (G == GG && VW == VV && DPL == DD) {                                                       \
     launch_acc<GG, VV, DD>(grid, lds, s, X, M, Li, idx, n, w.cps, w.nslices, w.rows_per_chunk, \
-                           w.shift, w.part, w.pcnt, w.lo, ctl, on_grid != 1);                   \
+                           w.shift, w.part, w.pcnt, w.lo, ctl, on_grid == 0);                   \
   } else
   LBG_ACC(1, 4, 1) LBG_ACC(2, 4, 1) LBG_ACC(4, 4, 1) LBG_ACC(8, 4, 1) LBG_ACC(16, 4, 1)
   LBG_ACC(32, 4, 1) LBG_ACC(64, 4, 1)
@@ -264,16 +312,20 @@ int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const f
 
 int launch_fin(const float* X, int64_t M, int64_t L, const float* C_old, int64_t N,
                float* C_out, int32_t* counts, int mode, double g2, const AfpWs& w,
-               hipStream_t s, Ctl ctl, CbPair cbp) {
+               hipStream_t s, Ctl ctl, CbPair cbp, bool p32) {
   (void)X;
   (void)M;
   const int n = (int)N, Li = (int)L;
-  if (mode == 0)
-    hipLaunchKernelGGL(fin_kernel<0>, dim3((unsigned)N), dim3(kT), 0, s, w.part, w.pcnt,
-                       w.nchunks, n, Li, w.shift, C_old, C_out, counts, g2, w.lo, ctl, cbp);
-  else
-    hipLaunchKernelGGL(fin_kernel<1>, dim3((unsigned)N), dim3(kT), 0, s, w.part, w.pcnt,
-                       w.nchunks, n, Li, w.shift, C_old, C_out, counts, g2, w.lo, ctl, cbp);
+  const int nch = p32 ? w.nch_n : w.nchunks;
+#define LBG_FIN(MM, PP)                                                                         \
+  hipLaunchKernelGGL((fin_kernel<MM, PP>), dim3((unsigned)N), dim3(kT), 0, s, w.part, w.pcnt,  \
+                     nch, n, Li, w.shift, C_old, C_out, counts, g2, w.lo, ctl, cbp)
+  if (mode == 0) {
+    if (p32) LBG_FIN(0, true); else LBG_FIN(0, false);
+  } else {
+    if (p32) LBG_FIN(1, true); else LBG_FIN(1, false);
+  }
+#undef LBG_FIN
   LBG_TRY_HIP(hipGetLastError());
   return LBG_OK;
 }

@@ -530,3 +530,65 @@ def test_update_dimension_slices_misaligned(P):
         C_new, counts = P.update(Xd, dev(idx), dev(C_old))
         np.testing.assert_array_equal(host(counts), cnt)
         np.testing.assert_array_equal(host(C_new), want.astype(np.float32))
+
+
+def _grid_bits(X, M):
+    """(e, g, b) of the update's 32-bit condition, from the data alone:
+    max|x| < 2^e, every coordinate a multiple of 2^-g (g as small as
+    possible), M < 2^b.  The cell sums fit 32 bits when e + g + b <= 31."""
+    a = np.abs(X[X != 0].astype(np.float64))
+    e = int(np.frexp(a.max())[1])
+    m, E = np.frexp(a)
+    sig = (m * 2.0 ** 53).astype(np.uint64)
+    tz = np.zeros(sig.shape, np.int64)
+    s = sig.copy()
+    while np.any(s & np.uint64(1) == 0):
+        z = (s & np.uint64(1)) == 0
+        tz += z
+        s = np.where(z, s >> np.uint64(1), s)
+    g = int((-(E - 53 + tz)).max())
+    return e, g, int(M).bit_length()
+
+
+# Whole Lloyd iterations from a given codebook on data whose cell sums do or
+# do not fit 32 bits: the update then sums 32-dimension slices in 32-bit
+# words, or 16-dimension slices in 64-bit words; either way the sums are
+# exact and the runs equal the oracle's (FP32 codebook storage) bit for bit.
+# Signed integers at the limit e + g + b = 31 and one bit past it, eighths
+# (g = 3) at L = 96 (three 32-bit slices), multiples of 4 (g = -2) at L = 32
+# (one slice), and X offset by one float (scalar loads).
+@pytest.mark.parametrize("case", ["limit", "past_limit", "eighths", "fours", "misaligned"])
+def test_train_32bit_slices_match_oracle(P, case):
+    rng = np.random.default_rng({"limit": 31, "past_limit": 32, "eighths": 33, "fours": 34,
+                                 "misaligned": 35}[case])
+    if case in ("limit", "past_limit", "misaligned"):
+        M, L, N = 4096, 64, 256
+        top = 2 ** 18 - 1 if case != "past_limit" else 2 ** 19 - 1
+        X = np.rint(_gmm(21, M, L, 12) * (top / 4.0))
+        X = np.clip(X, -top, top)
+        X[0, 0], X[1, 1] = top, -top
+        X = X.astype(np.float32)
+        want = case != "past_limit"
+    elif case == "eighths":
+        M, L, N = 3001, 96, 256
+        X = (np.rint(_gmm(22, M, L, 10) * 800.0) / 8.0).astype(np.float32)
+        want = True
+    else:
+        M, L, N = 5000, 32, 512
+        X = (np.rint(_gmm(23, M, L, 16) * 50.0) * 4.0).astype(np.float32)
+        want = True
+    e, g, b = _grid_bits(X, M)
+    assert (e + g + b <= 31) == want, (e, g, b)
+    C0 = X[rng.permutation(M)[:N]] + rng.normal(size=(N, L)).astype(np.float32)
+    ref = oracle.train(X, N, C_init=C0.astype(np.float64), fixed_iters=4, store_fp32=True)
+    Xd = dev(X)
+    if case == "misaligned":
+        flat = torch.empty(M * L + 1, dtype=torch.float32, device="cuda")
+        Xd = flat[1:].view(M, L)
+        Xd.copy_(dev(X))
+        assert Xd.data_ptr() % 16 != 0
+    C, idx, D, st = P.train(Xd, N, C_init=dev(C0), fixed_iters=4)
+    assert st["level_iters"] == [4]
+    np.testing.assert_array_equal(host(idx), ref["idx"])
+    np.testing.assert_array_equal(host(C), ref["C"].astype(np.float32))
+    assert abs(D - ref["D"]) <= 1e-12 * ref["D"]
