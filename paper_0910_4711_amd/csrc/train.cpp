@@ -7,6 +7,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "lbg_internal.h"
@@ -96,11 +97,12 @@ inline hipEvent_t event_after(hipEvent_t (*ev)[3][2], int i, int piece) {
   return piece == 0 ? ev[i][0][1] : ev[i][1][1];
 }
 
-// ``iters`` (at most kBatchIters) iterations launched directly.
+// ``iters`` (at most kBatchIters) iterations launched directly; skip0: the
+// first iteration's allocation is already enqueued.
 int enqueue_batch(const Batch& b, hipStream_t s, hipEvent_t (*ev)[3][2],
-                  int iters = kBatchIters) {
+                  int iters = kBatchIters, bool skip0 = false) {
   for (int i = 0; i < iters; ++i)
-    for (int piece = 0; piece < kPieces; ++piece) {
+    for (int piece = (i == 0 && skip0) ? 1 : 0; piece < kPieces; ++piece) {
       if (ev && event_before(ev, i, piece))
         LBG_TRY_HIP(hipEventRecord(event_before(ev, i, piece), s));
       LBG_TRY(enqueue_piece(b, piece, s));
@@ -224,15 +226,26 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
     hs.n_forced = 1;
     hs.forced[0] = 0;
   }
-  // pinned host block: action trace, then the state
-  int32_t* acts =
-      reinterpret_cast<int32_t*>(pinned_block(2 * sizeof(DevState) + kTraceCap * 4));
-  if (!acts) {
+  // pinned host block: action trace, two state copies, the set-up flags,
+  // the statistics words, the distortion trace.  Every readback lands in
+  // pinned memory, so that the copies stay asynchronous (a copy into
+  // pageable memory costs a host round trip of 20-30 us each).
+  static_assert(sizeof(DevState) % 8 == 0, "state alignment");
+  const size_t off_state = (size_t)kTraceCap * 4;
+  const size_t off_flags = off_state + 2 * sizeof(DevState);
+  const size_t off_words = off_flags + 8 * sizeof(int);
+  const size_t off_trace = off_words + 4 * sizeof(unsigned long long);
+  char* pbase = reinterpret_cast<char*>(pinned_block(off_trace + (size_t)kTraceCap * 8));
+  if (!pbase) {
     set_error("could not allocate pinned host memory");
     return LBG_EHIP;
   }
-  DevState* pins[2] = {reinterpret_cast<DevState*>(acts + kTraceCap),
-                       reinterpret_cast<DevState*>(acts + kTraceCap) + 1};
+  int32_t* acts = reinterpret_cast<int32_t*>(pbase);
+  DevState* pins[2] = {reinterpret_cast<DevState*>(pbase + off_state),
+                       reinterpret_cast<DevState*>(pbase + off_state) + 1};
+  int* flags = reinterpret_cast<int*>(pbase + off_flags);
+  unsigned long long* words = reinterpret_cast<unsigned long long*>(pbase + off_words);
+  double* dtrace = reinterpret_cast<double*>(pbase + off_trace);
   DevState* pin = pins[0];
   memcpy(pin, &hs, sizeof(hs));
   if (fused_setup) {
@@ -247,13 +260,31 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
   // Whether the training set lies on the update's 2^-s grid (set-up pass):
   // read once, so that the accumulation runs its one-word kernel (the
   // kernel that decides on the device is larger and measured slower).
-  int flags[5] = {0, 0, 0, 0, 0};
-  LBG_TRY_HIP(hipMemcpyAsync(flags, w.up.afp.shift, sizeof(flags), hipMemcpyDeviceToHost, s));
-  LBG_TRY_HIP(hipStreamSynchronize(s));
+  // Untimed direct launches: the first allocation (which does not depend on
+  // the flags) is enqueued before the host waits for them, so that the
+  // device does not idle through that round trip.
   const bool timed = p->timing != 0 && st != nullptr;
-  Batch b{X, M, L, N, p->precision, p->split_mode, p->eps_split, p->delta, idx_out, &w,
-          assign_num_parts(M, L, N, p->precision), flags[1] != 0 ? 0 : (flags[3] ? 2 : 1)};
   const bool use_graph = s != nullptr && p->graph != 0;
+  Batch b{X, M, L, N, p->precision, p->split_mode, p->eps_split, p->delta, idx_out, &w,
+          assign_num_parts(M, L, N, p->precision), 0};
+  LBG_TRY_HIP(hipMemcpyAsync(flags, w.up.afp.shift, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+  bool skip0 = false;
+  if (!timed && !use_graph) {
+    hipEvent_t fev = nullptr;
+    LBG_TRY_HIP(hipEventCreateWithFlags(&fev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(fev, s);
+    int rc0 = e == hipSuccess ? enqueue_piece(b, 0, s) : hip_fail(e, "hipEventRecord");
+    if (rc0 == LBG_OK) {
+      skip0 = true;
+      e = hipEventSynchronize(fev);
+      if (e != hipSuccess) rc0 = hip_fail(e, "hipEventSynchronize");
+    }
+    (void)hipEventDestroy(fev);
+    if (rc0 != LBG_OK) return rc0;
+  } else {
+    LBG_TRY_HIP(hipStreamSynchronize(s));
+  }
+  b.on_grid = flags[1] != 0 ? 0 : (flags[3] ? 2 : 1);
 
   GraphEntry* ge = nullptr;
   std::unique_lock<std::mutex> lk(g_cache_mu, std::defer_lock);
@@ -321,22 +352,52 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
         }
   }
 
+  // When every level's update count is forced (fixed_iters, or a forced
+  // list covering every level) the run takes exactly sum(count + 1)
+  // iterations whatever its distortions (fewer only if one is not finite):
+  // the host then enqueues no iteration beyond that, so no launches that
+  // return at once trail the run.  -1: no such bound.
+  int64_t left = -1;
+  {
+    int levels = 1;
+    for (int64_t n = hs.n; n < N; n *= 2) ++levels;
+    int64_t sum = 0;
+    int it = hs.it;
+    for (int l = 0; l < levels && sum >= 0; ++l) {
+      int f = hs.fixed_iters > 0 ? hs.fixed_iters : -1;
+      if (l < hs.n_forced && l < 32) f = hs.forced[l];
+      sum = f < 0 ? -1 : sum + std::max(f - it, 0) + 1;
+      it = 0;
+    }
+    left = sum;
+  }
   double ms[3] = {0.0, 0.0, 0.0};
   int32_t prev_assign = 0;
   int rc = LBG_OK;
   int iters = kBatchIters;  // of the next untimed direct batch
+  int64_t enqueued = 0;     // iterations enqueued directly so far
   auto launch_batch = [&]() -> int {
     if (ge) {
       const hipError_t e = hipGraphLaunch(ge->exec, s);
       return e == hipSuccess ? LBG_OK : hip_fail(e, "hipGraphLaunch");
     }
-    return timed ? enqueue_batch(b, s, local_ev) : enqueue_batch(b, s, nullptr, iters);
+    int k = timed ? kBatchIters : iters;
+    if (left >= 0) {
+      k = (int)std::min<int64_t>(k, left);
+      left -= k;
+    }
+    enqueued += k;
+    if (k == 0) return LBG_OK;
+    const bool sk = skip0;
+    skip0 = false;
+    return timed ? enqueue_batch(b, s, local_ev, k) : enqueue_batch(b, s, nullptr, k, sk);
   };
   if (!timed) {
     // The next batch is enqueued before this batch's state is read back (its
     // kernels return at once when the run has finished in this batch), so
     // the device does not wait for the host between batches.
     hipEvent_t read[2] = {nullptr, nullptr};
+    int64_t before_read[2] = {0, 0};  // iterations enqueued ahead of each readback
     for (auto& e : read)
       if (rc == LBG_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
         rc = hip_fail(hipGetLastError(), "hipEventCreate");
@@ -348,6 +409,7 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
         rc = hip_fail(hipGetLastError(), "state readback");
         break;
       }
+      before_read[cur] = enqueued;
       rc = launch_batch();
       if (rc < 0) break;
       if (hipEventSynchronize(read[cur]) != hipSuccess) {
@@ -358,6 +420,8 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
         pin = pins[cur];
         break;
       }
+      // not done after every bounded iteration (not expected): go on unbounded
+      if (left == 0 && before_read[cur] == enqueued) left = -1;
       if (pins[cur]->n >= N) iters = kTailIters;
     }
     for (auto& e : read)
@@ -385,6 +449,7 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
     }
     prev_assign = pin->n_assign;
     if (pin->done) break;
+    if (left == 0) left = -1;  // not done after every bounded iteration (not expected)
   }
   if (lk.owns_lock()) lk.unlock();
   destroy_local();
@@ -393,20 +458,24 @@ int train_device(const float* X, int64_t M, int64_t L, int64_t N, const lbg_para
   LBG_TRY_HIP(hipMemcpyAsync(C_out, w.Cb[pin->cb], (size_t)(N * L) * sizeof(float),
                              hipMemcpyDeviceToDevice, s));
   if (st) {
-    unsigned long long nf = 0, rs[2] = {0, 0};
+    unsigned long long* rs = words;  // empty cells, near-tie rows
+    unsigned long long* nf = words + 2;
+    rs[0] = rs[1] = *nf = 0;
     // statistics of the final allocation (before the one synchronisation)
     if (pin->status != LBG_EINVAL) {
       LBG_TRY(launch_run_stats(X, M, L, w.Cb[pin->cb], N, idx_out, p->stats_ties != 0,
                                w.cellcnt, w.runstat, s));
-      LBG_TRY_HIP(hipMemcpyAsync(rs, w.runstat, sizeof(rs), hipMemcpyDeviceToHost, s));
+      LBG_TRY_HIP(hipMemcpyAsync(rs, w.runstat, 2 * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, s));
     }
-    LBG_TRY_HIP(hipMemcpyAsync(&nf, w.as.nfb, sizeof(nf), hipMemcpyDeviceToHost, s));
+    LBG_TRY_HIP(hipMemcpyAsync(nf, w.as.nfb, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     const int nD = std::min(pin->n_assign, std::min(st->D_cap, kTraceCap));
     if (st->D_trace && nD > 0)
-      LBG_TRY_HIP(hipMemcpyAsync(st->D_trace, w.Dtrace, (size_t)nD * sizeof(double),
+      LBG_TRY_HIP(hipMemcpyAsync(dtrace, w.Dtrace, (size_t)nD * sizeof(double),
                                  hipMemcpyDeviceToHost, s));
     LBG_TRY_HIP(hipStreamSynchronize(s));
-    st->fallback_rows = (int64_t)nf;
+    if (st->D_trace && nD > 0) memcpy(st->D_trace, dtrace, (size_t)nD * sizeof(double));
+    st->fallback_rows = (int64_t)*nf;
     st->n_D = pin->n_assign;
     st->total_assigns = pin->n_assign;
     st->total_updates = pin->n_update;
