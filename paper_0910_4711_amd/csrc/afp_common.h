@@ -523,6 +523,9 @@ constexpr int kDsThreads = 1024;
 // the device-side stop decision, about 3 KiB).
 constexpr int kAccdLdsMax = 163840 - 8192;
 
+// Dynamic LDS of the batched form's 16-dimension slices (see plan_afp).
+constexpr int kBdsLdsMax = 40960;
+
 inline size_t accd_lds_bytes(int64_t N) {
   return (size_t)(N + 1) * (kDs + 1) * 8 + (size_t)(N + 1) * 4;
 }
@@ -540,7 +543,7 @@ __device__ __forceinline__ void accd_block(int blk, int nch, int nds, int* chunk
   }
 }
 
-template <bool FINE, bool VEC>
+template <bool FINE, bool VEC, int NT = kDsThreads>
 __device__ __forceinline__ void accd_body(const float* __restrict__ X, int64_t M, int L,
                                           const int32_t* __restrict__ idx, int N, int ns,
                                           int64_t rows_per_chunk, int chunk, int q, int s,
@@ -549,14 +552,14 @@ __device__ __forceinline__ void accd_body(const float* __restrict__ X, int64_t M
                                           unsigned long long* sacc,
                                           unsigned long long* __restrict__ lo, int tfine) {
   constexpr int LS = kDs + 1;
-  constexpr int NG = kDsThreads / 4;
+  constexpr int NG = NT / 4;
   const double p2s = ldexp(1.0, s);
   const double p2t = ldexp(1.0, tfine);
   int32_t* scnt = reinterpret_cast<int32_t*>(sacc + (size_t)(N + 1) * LS);
   const int t = threadIdx.x;
-  for (int e = t; e < (N + 1) * LS; e += kDsThreads) sacc[e] = 0ull;
+  for (int e = t; e < (N + 1) * LS; e += NT) sacc[e] = 0ull;
   if (q == 0)
-    for (int e = t; e <= N; e += kDsThreads) scnt[e] = 0;
+    for (int e = t; e <= N; e += NT) scnt[e] = 0;
   __syncthreads();
   const int g = t >> 2, gl = t & 3;
   const int d0 = kDs * q + 4 * gl;  // this lane's four dimensions
@@ -602,13 +605,13 @@ __device__ __forceinline__ void accd_body(const float* __restrict__ X, int64_t M
   }
   __syncthreads();
   unsigned long long* dst = part + (int64_t)chunk * ns * L + kDs * q;
-  for (int e = t; e < N * kDs; e += kDsThreads) {
+  for (int e = t; e < N * kDs; e += NT) {
     const int kk = e / kDs, d = e - kk * kDs;
     dst[(int64_t)kk * L + d] = sacc[kk * LS + d];
   }
   if (q == 0) {
     int32_t* cdst = pcnt + (int64_t)chunk * ns;
-    for (int e = t; e < N; e += kDsThreads) cdst[e] = scnt[e];
+    for (int e = t; e < N; e += NT) cdst[e] = scnt[e];
   }
 }
 

@@ -60,6 +60,7 @@ struct BInst {
   int64_t ntiles;  // row tiles of kRowsPerTile
   int32_t G;       // allocation slots: the single-run kernel's grid
   int32_t cps, nslices, nchunks, absmax_blocks, cnwg;
+  int32_t bds;  // > 0: the update runs this many 16-dimension slices (b_accd_kernel)
   int64_t rows_per_chunk, crpb;
   unsigned long long* part;
   int32_t* pcnt;
@@ -78,7 +79,7 @@ struct BInst {
 // for every family but the allocation items also a block -> instance table
 // (offset tab_off[family] into one int32 array), so that a block finds its
 // instance with one load.
-enum { kPreItem, kPreAcc, kPreFin, kPreCol, kPreColFin, kPreAmax, kNumPre };
+enum { kPreItem, kPreAcc, kPreFin, kPreCol, kPreColFin, kPreAmax, kPreAccD, kNumPre };
 
 struct Tabs {
   const int32_t* b2i;         // block -> instance, all families
@@ -445,6 +446,45 @@ __global__ __launch_bounds__(kT) void b_acc_kernel(const BInst* __restrict__ ins
   acc_item(inst[i], (int64_t)blockIdx.x - acc_pre[i], sacc, slist, snsel);
 }
 
+// The update of the instances planned with 16-dimension slices (all their
+// cells' sums for 16 dimensions in at most 40 KiB of LDS): one workgroup
+// per (instance, row chunk, slice), each adding a 64-byte slice of every row
+// of its chunk, no filtering by cell; the instance's decision in its
+// workgroup 0.  Its own kernel, so that its registers and LDS (four
+// workgroups per CU) are not those of the cell-slice path.
+__global__ __launch_bounds__(kT) void b_accd_kernel(const BInst* __restrict__ inst, int n_inst,
+                                                    const int64_t* __restrict__ pre, Tabs tb) {
+  extern __shared__ unsigned long long sacc[];
+  const int64_t* p = pre + (int64_t)kPreAccD * (n_inst + 1);
+  if ((int64_t)blockIdx.x >= p[n_inst]) return;
+  const int i = tb.b2i[tb.off[kPreAccD] + blockIdx.x];
+  const BInst& B = inst[i];
+  const int64_t local = (int64_t)blockIdx.x - p[i];
+  const Ctl ctl{B.st, B.pend, B.dpart, (B.M + 31) / 32, B.Dtrace, B.Atrace};
+  int N = B.N;
+  if (B.st->done) return;
+  if (local == 0) (void)afp::acc_decide(ctl, true, &N);  // the instance's decision
+  if (forced_stop(B.st)) return;  // the level ends here: no update follows
+  const int n = B.st->n;
+  const int chunk = (int)(local / B.bds), q = (int)(local % B.bds);
+  const int s = B.shift[0], tf = B.shift[1];
+#define LBG_BACCD(FF, VV)                                                                   \
+  afp::accd_body<FF, VV, kT>(B.X, B.M, B.L, B.idx, n, B.N, B.rows_per_chunk, chunk, q, s,  \
+                             B.part, B.pcnt, sacc, B.lo, tf)
+  if (B.vec) {
+    if (tf > 0)
+      LBG_BACCD(true, true);
+    else
+      LBG_BACCD(false, true);
+  } else {
+    if (tf > 0)
+      LBG_BACCD(true, false);
+    else
+      LBG_BACCD(false, false);
+  }
+#undef LBG_BACCD
+}
+
 // Cell k of instance B: centroid, or split, or nothing; cell 0 commits the
 // state.  (The work list holds only cells below the pending n_src of
 // instances still running.)
@@ -602,6 +642,38 @@ __global__ __launch_bounds__(kT) void b_upd_acc_kernel(const BInst* __restrict__
   acc_cells(B, B.N, (int64_t)blockIdx.x - acc_pre[i], sacc, slist, snsel);
 }
 
+// ... or, for the items planned with 16-dimension slices, one workgroup per
+// (item, row chunk, slice), as b_accd_kernel without run state.
+__global__ __launch_bounds__(kT) void b_upd_accd_kernel(const BInst* __restrict__ inst,
+                                                        int n_inst,
+                                                        const int64_t* __restrict__ pre,
+                                                        Tabs tb) {
+  extern __shared__ unsigned long long sacc[];
+  const int64_t* p = pre + (int64_t)kPreAccD * (n_inst + 1);
+  if ((int64_t)blockIdx.x >= p[n_inst]) return;
+  const int i = tb.b2i[tb.off[kPreAccD] + blockIdx.x];
+  const BInst& B = inst[i];
+  const int64_t local = (int64_t)blockIdx.x - p[i];
+  const int chunk = (int)(local / B.bds), q = (int)(local % B.bds);
+  const int s = B.shift[0], tf = B.shift[1];
+#define LBG_BUACCD(FF, VV)                                                                  \
+  afp::accd_body<FF, VV, kT>(B.X, B.M, B.L, B.idx, B.N, B.N, B.rows_per_chunk, chunk, q, s, \
+                             B.part, B.pcnt, sacc, B.lo, tf)
+  const bool vec = B.vec && (B.L & 3) == 0;
+  if (vec) {
+    if (tf > 0)
+      LBG_BUACCD(true, true);
+    else
+      LBG_BUACCD(false, true);
+  } else {
+    if (tf > 0)
+      LBG_BUACCD(true, false);
+    else
+      LBG_BUACCD(false, false);
+  }
+#undef LBG_BUACCD
+}
+
 // ... then every item's centroids (one workgroup per cell; an empty cell
 // keeps C_old, Cb[0]) into C_out, with the counts.
 __global__ __launch_bounds__(kT) void b_upd_fin_kernel(const BInst* __restrict__ inst, int n_inst,
@@ -653,11 +725,12 @@ struct BatchWs {
 // Blocks (allocation items) of each launch family for one instance.
 void family_counts(const InstPlan& q, int64_t N, int64_t L, int64_t cnt[kNumPre]) {
   cnt[kPreItem] = q.G;
-  cnt[kPreAcc] = (int64_t)q.afp.nchunks * q.afp.nslices;
+  cnt[kPreAcc] = q.afp.bds ? 0 : (int64_t)q.afp.nchunks * q.afp.nslices;
   cnt[kPreFin] = N;
   cnt[kPreCol] = q.cnwg;
   cnt[kPreColFin] = L;
   cnt[kPreAmax] = q.afp.absmax_blocks;
+  cnt[kPreAccD] = q.afp.bds ? (int64_t)q.afp.nchunks * q.afp.bds : 0;
 }
 
 int lp_of(int64_t L) { return L <= 16 ? 16 : 64; }
@@ -699,7 +772,7 @@ void plan_batch(Carver& c, const lbg_instance* in, int n, BatchWs* w) {
     q.cpart = c.take<double>((size_t)(q.cnwg * L));
     q.Dtrace = c.take<double>(kBatchTrace);
     q.Atrace = c.take<int32_t>(kBatchTrace);
-    plan_afp(c, M, L, N, &q.afp, false, true);
+    plan_afp(c, M, L, N, &q.afp, false, true, true);
   }
   for (int k = 0; k < kNumPre; ++k) w->tot[k] = 0;
   for (int i = 0; i < n; ++i) {
@@ -753,7 +826,7 @@ struct Launch {
   Tabs tb;
   int64_t blocks[kNumPre];  // totals
   unsigned* ctr;
-  size_t acc_lds;
+  size_t acc_lds, accd_lds;
   const int32_t* chunks;    // device chunk table for the current grab
   int nchunks;
   const DevState* st;       // the instances' states (contiguous)
@@ -781,9 +854,16 @@ int launch_round(const Launch& l, int grid, int split, hipStream_t s,
     LBG_TRY_HIP(hipGetLastError());
   }
   if (ev) LBG_TRY_HIP(hipEventRecord(ev[1], s));
-  hipLaunchKernelGGL(b_acc_kernel, dim3((unsigned)l.blocks[kPreAcc]), dim3(kT), l.acc_lds, s,
-                     l.inst, l.n, l.pre, l.tb);
-  LBG_TRY_HIP(hipGetLastError());
+  if (l.blocks[kPreAccD] > 0) {
+    hipLaunchKernelGGL(b_accd_kernel, dim3((unsigned)l.blocks[kPreAccD]), dim3(kT), l.accd_lds,
+                       s, l.inst, l.n, l.pre, l.tb);
+    LBG_TRY_HIP(hipGetLastError());
+  }
+  if (l.blocks[kPreAcc] > 0) {
+    hipLaunchKernelGGL(b_acc_kernel, dim3((unsigned)l.blocks[kPreAcc]), dim3(kT), l.acc_lds, s,
+                       l.inst, l.n, l.pre, l.tb);
+    LBG_TRY_HIP(hipGetLastError());
+  }
   hipLaunchKernelGGL(b_list_kernel, dim3(1), dim3(1024), 0, s, l.st, l.pend, l.inst, l.n,
                      l.fin_list, l.fin_first, l.list_total);
   LBG_TRY_HIP(hipGetLastError());
@@ -902,7 +982,7 @@ struct BGraph {
   hipStream_t stream = nullptr;
   int n = 0, grab = 0, grid = 0, split = 0;
   int64_t blocks[kNumPre] = {};
-  size_t acc_lds = 0;
+  size_t acc_lds = 0, accd_lds = 0;
   int nchunks = 0;
   hipGraphExec_t exec = nullptr;
   uint64_t stamp = 0;
@@ -915,7 +995,8 @@ int get_graph(const Launch& l, const void* ws, int grab, int grid, int split, hi
               hipGraphExec_t* out) {
   for (auto& e : g_bgraph)
     if (e.used && e.ws == ws && e.stream == s && e.n == l.n && e.grab == grab &&
-        e.grid == grid && e.split == split && e.acc_lds == l.acc_lds && e.nchunks == l.nchunks &&
+        e.grid == grid && e.split == split && e.acc_lds == l.acc_lds && e.accd_lds == l.accd_lds &&
+        e.nchunks == l.nchunks &&
         memcmp(e.blocks, l.blocks, sizeof(e.blocks)) == 0) {
       e.stamp = ++g_bstamp;
       *out = e.exec;
@@ -954,6 +1035,7 @@ int get_graph(const Launch& l, const void* ws, int grab, int grid, int split, hi
   slot->split = split;
   memcpy(slot->blocks, l.blocks, sizeof(slot->blocks));
   slot->acc_lds = l.acc_lds;
+  slot->accd_lds = l.accd_lds;
   slot->nchunks = l.nchunks;
   slot->exec = ex;
   slot->stamp = ++g_bstamp;
@@ -1109,7 +1191,7 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
     hp[(int64_t)k * (n + 1)] = 0;
     tot[k] = 0;
   }
-  size_t acc_lds = 0;
+  size_t acc_lds = 0, accd_lds = 0;
   int64_t work = 0, sumM = 0, sumN = 0;
   for (int i = 0; i < n; ++i) {
     const lbg_instance& a = inst[i];
@@ -1133,6 +1215,7 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
     B.G = q.G;
     B.cps = q.afp.cps;
     B.nslices = q.afp.nslices;
+    B.bds = q.afp.bds;
     B.nchunks = q.afp.nchunks;
     B.absmax_blocks = q.afp.absmax_blocks;
     B.cnwg = q.cnwg;
@@ -1153,7 +1236,10 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
       tot[k] += cnt[k];
       hp[(int64_t)k * (n + 1) + i + 1] = tot[k];
     }
-    acc_lds = std::max(acc_lds, afp::acc_lds_bytes(q.afp.cps, a.L));
+    if (q.afp.bds)
+      accd_lds = std::max(accd_lds, afp::accd_lds_bytes(a.N));
+    else
+      acc_lds = std::max(acc_lds, afp::acc_lds_bytes(q.afp.cps, a.L));
     work += a.M * a.N * a.L;
     sumM += a.M;
     sumN += a.N;
@@ -1204,7 +1290,7 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
     }
   }
   int32_t* hchunk = reinterpret_cast<int32_t*>(host + b_inst + b_pre + b_st + 64 + b_tab);
-  Launch l{w.inst, n, w.pre, tb, {}, w.ctr, acc_lds, w.chunks, 0,
+  Launch l{w.inst, n, w.pre, tb, {}, w.ctr, acc_lds, accd_lds, w.chunks, 0,
            w.st, w.pend, w.fin_list, w.fin_first, w.list_total};
   for (int k = 0; k < kNumPre; ++k) l.blocks[k] = tot[k];
 
@@ -1435,7 +1521,8 @@ struct UpdWs {
 // Blocks of the update launches for one item (the other families unused).
 void upd_counts(const AfpWs& a, int64_t N, int64_t cnt[kNumPre]) {
   for (int k = 0; k < kNumPre; ++k) cnt[k] = 0;
-  cnt[kPreAcc] = (int64_t)a.nchunks * a.nslices;
+  cnt[kPreAcc] = a.bds ? 0 : (int64_t)a.nchunks * a.nslices;
+  cnt[kPreAccD] = a.bds ? (int64_t)a.nchunks * a.bds : 0;
   cnt[kPreFin] = N;
   cnt[kPreAmax] = a.absmax_blocks;
 }
@@ -1446,7 +1533,7 @@ void plan_upd(Carver& c, const lbg_update_item* in, int n, UpdWs* w) {
   w->afp.assign((size_t)n, AfpWs{});
   for (int k = 0; k < kNumPre; ++k) w->tot[k] = 0;
   for (int i = 0; i < n; ++i) {
-    plan_afp(c, in[i].M, in[i].L, in[i].N, &w->afp[(size_t)i], false, true);
+    plan_afp(c, in[i].M, in[i].L, in[i].N, &w->afp[(size_t)i], false, true, true);
     int64_t cnt[kNumPre];
     upd_counts(w->afp[(size_t)i], in[i].N, cnt);
     for (int k = 0; k < kNumPre; ++k) w->tot[k] += cnt[k];
@@ -1609,7 +1696,7 @@ extern "C" int lbg_update_batched(const lbg_update_item* items, int32_t n, void*
     }
   std::vector<BInst> hi((size_t)n);
   std::vector<int64_t> hp((size_t)kNumPre * (n + 1), 0);
-  size_t acc_lds = 0;
+  size_t acc_lds = 0, accd_lds = 0;
   for (int i = 0; i < n; ++i) {
     const lbg_update_item& a = items[i];
     const AfpWs& q = w.afp[(size_t)i];
@@ -1626,6 +1713,7 @@ extern "C" int lbg_update_batched(const lbg_update_item* items, int32_t n, void*
     B.idx = const_cast<int32_t*>(a.idx);  // read only by the update
     B.cps = q.cps;
     B.nslices = q.nslices;
+    B.bds = q.bds;
     B.nchunks = q.nchunks;
     B.absmax_blocks = q.absmax_blocks;
     B.rows_per_chunk = q.rows_per_chunk;
@@ -1639,9 +1727,12 @@ extern "C" int lbg_update_batched(const lbg_update_item* items, int32_t n, void*
     upd_counts(q, a.N, cnt);
     for (int k = 0; k < kNumPre; ++k)
       hp[(size_t)k * (n + 1) + i + 1] = hp[(size_t)k * (n + 1) + i] + cnt[k];
-    acc_lds = std::max(acc_lds, afp::acc_lds_bytes(q.cps, a.L));
+    if (q.bds)
+      accd_lds = std::max(accd_lds, afp::accd_lds_bytes(a.N));
+    else
+      acc_lds = std::max(acc_lds, afp::acc_lds_bytes(q.cps, a.L));
   }
-  // block -> item tables of the three families
+  // block -> item tables of the families
   std::vector<int32_t> htab;
   Tabs tb;
   tb.b2i = w.b2i;
@@ -1664,9 +1755,16 @@ extern "C" int lbg_update_batched(const lbg_update_item* items, int32_t n, void*
   LBG_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(b_shift_kernel, dim3((unsigned)n), dim3(kT), 0, s, w.inst);
   LBG_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(b_upd_acc_kernel, dim3((unsigned)w.tot[kPreAcc]), dim3(kT), acc_lds, s,
-                     w.inst, n, w.pre, tb);
-  LBG_TRY_HIP(hipGetLastError());
+  if (w.tot[kPreAccD] > 0) {
+    hipLaunchKernelGGL(b_upd_accd_kernel, dim3((unsigned)w.tot[kPreAccD]), dim3(kT), accd_lds, s,
+                       w.inst, n, w.pre, tb);
+    LBG_TRY_HIP(hipGetLastError());
+  }
+  if (w.tot[kPreAcc] > 0) {
+    hipLaunchKernelGGL(b_upd_acc_kernel, dim3((unsigned)w.tot[kPreAcc]), dim3(kT), acc_lds, s,
+                       w.inst, n, w.pre, tb);
+    LBG_TRY_HIP(hipGetLastError());
+  }
   hipLaunchKernelGGL(b_upd_fin_kernel, dim3((unsigned)w.tot[kPreFin]), dim3(kT), 0, s, w.inst,
                      n, w.pre, tb);
   LBG_TRY_HIP(hipGetLastError());

@@ -140,11 +140,15 @@ struct AfpWs {
   // partials int32 [nch_n][N][L] in the bytes of ``part``
   int nds_n, nch_n;
   int64_t rpc_n;
+  // > 0: one of many instances whose update runs this many 16-dimension
+  // slices with all cells in LDS (batched form)
+  int bds;
 };
 bool afp_usable(int64_t L, int64_t N);
 // dslices: the single-run kernels may accumulate by dimension slices
+// bds_ok (with many): the batched form may run 16-dimension slices.
 void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices = true,
-              bool many = false);
+              bool many = false, bool bds_ok = false);
 int launch_afp_shift(const float* X, int64_t M, int64_t L, const AfpWs& w, hipStream_t s);
 // The finishing kernel of the update (centroids or gradient from the partials).
 // p32: the partials are those of the 32-bit slices.

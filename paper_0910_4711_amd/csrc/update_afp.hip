@@ -175,7 +175,8 @@ void launch_acc(dim3 grid, size_t lds, hipStream_t st, const float* X, int64_t M
 
 }  // namespace
 
-void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices, bool many) {
+void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices, bool many,
+              bool bds_ok) {
   w->cps = (int)std::min<int64_t>(std::min<int64_t>(N, 8192), kLdsBytes / (8 * (L + 1) + 4) - 1);
   w->nslices = (int)((N + w->cps - 1) / w->cps);
   // Dimension slices instead of several cell slices when all cells fit one
@@ -201,6 +202,11 @@ void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices
   }
   w->nchunks = (int)nch;
   w->rows_per_chunk = (M + nch - 1) / nch;
+  // batched form: 16-dimension slices with every cell in at most 40 KiB of
+  // LDS, so that four 256-thread workgroups share a CU
+  w->bds = (many && bds_ok && L % kDs == 0 && accd_lds_bytes(N) <= (size_t)kBdsLdsMax)
+               ? (int)(L / kDs)
+               : 0;
   // the 32-bit slices: half as many slices of twice the width, twice the
   // chunks (the same blocks), their int32 partials in the same bytes
   w->nds_n = 0;
