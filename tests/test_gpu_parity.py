@@ -358,10 +358,11 @@ def test_train_wide_codebook_matches_oracle(P):
     assert abs(D - ref["D"]) <= 1e-12 * ref["D"]
 
 
-@pytest.mark.parametrize("M,L,N", [(2000, 200, 16), (2048, 256, 1024)])
+@pytest.mark.parametrize("M,L,N", [(2000, 200, 16), (2048, 256, 1024), (3000, 160, 64)])
 def test_train_host_loop_matches_oracle(P, M, L, N):
     # L > 128 runs the host-controlled loop (FP64 allocation); at L = 256,
-    # N = 1024 its updates sum the cells through the sorted allocation.
+    # N = 1024 its updates sum the cells through the sorted allocation; at
+    # L = 160, N = 64 through five 32-dimension slices of 32-bit sums.
     # Integer-valued data: every sum is exact, so the run equals the oracle's
     # with FP32 codebook storage
     X = np.rint(_gmm(L + N, M, L, 12)).astype(np.float32)
