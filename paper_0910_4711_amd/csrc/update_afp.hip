@@ -21,10 +21,14 @@
 //   absmax    per block: largest |x| (as float bits; max is order-free) and
 //             the largest fine bits (the finest binary digit any coordinate
 //             needs); the blocks also clear the second-word array
-//   shift     one block: s and t from the block maxima
+//   shift     one block: s and t from the block maxima (and whether the
+//             sums fit 32 bits at a coarser grid 2^-g, see shift_body)
 //   acc       one block per (row chunk, cell slice): LDS int64 sums and
 //             counts for the cells of its slice over the rows of its chunk;
-//             dense partials per chunk
+//             dense partials per chunk.  accd: one block per (row chunk,
+//             16-dimension slice) with every cell in LDS; accn: the same
+//             with 32-dimension slices of int32 sums at scale 2^g, whose
+//             totals fin shifts to scale 2^s
 //   fin       one block per cell: partials of all chunks added (integers),
 //             centroid = sum * 2^-s / count (FP64, rounded to FP32); an empty
 //             cell keeps its codevector.  For the gradient, (count * c_k - sum)
