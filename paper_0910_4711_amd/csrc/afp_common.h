@@ -633,10 +633,18 @@ inline size_t accn_lds_bytes(int64_t N) {
   return (size_t)(N + 1) * (kDn + 1) * 4 + (size_t)(N + 1) * 4;
 }
 
+// Rows are dealt to the nch chunks in spans of 128 kDnRows rows (span p to
+// chunk p mod nch), and every block walks its spans from the end of X
+// backwards: the allocation before the update reads X front to back, so
+// the update starts on the rows it read last, which the memory-side cache
+// still holds, and ends on the rows the next allocation reads first
+// (measured: update 212 -> 207 us and allocation 693 -> 659 us per
+// iteration at M = 4,194,304, L = 64, N = 1024, against contiguous chunks
+// walked forwards).  The chunks' sums do not depend on which rows they hold.
 template <bool VEC>
 __device__ __forceinline__ void accn_body(const float* __restrict__ X, int64_t M, int L,
                                           const int32_t* __restrict__ idx, int N, int ns,
-                                          int64_t rows_per_chunk, int chunk, int q, int g,
+                                          int nch, int chunk, int q, int g,
                                           int32_t* __restrict__ part, int32_t* __restrict__ pcnt,
                                           uint32_t* sacc) {
   constexpr int LS = kDn + 1;
@@ -649,16 +657,18 @@ __device__ __forceinline__ void accn_body(const float* __restrict__ X, int64_t M
   __syncthreads();
   const int gr = t >> 3, gl = t & 7;
   const int d0 = kDn * q + 4 * gl;  // this lane's four dimensions
-  const int64_t r0 = (int64_t)chunk * rows_per_chunk;
-  const int64_t r1 = min(M, r0 + rows_per_chunk);
-  for (int64_t b = r0 + gr; b < r1; b += (int64_t)NG * kDnRows) {
+  constexpr int64_t span = (int64_t)NG * kDnRows;
+  const int64_t nsp = (M + span - 1) / span;
+  const int64_t last = chunk < nsp ? chunk + (nsp - 1 - chunk) / nch * nch : -1;
+  for (int64_t p = last; p >= 0; p -= nch) {
+    const int64_t b = p * span + gr;
     int k[kDnRows];
     float v[kDnRows][4];
 #pragma unroll
     for (int u = 0; u < kDnRows; ++u) {
       const int64_t m = b + (int64_t)u * NG;
-      const bool on = m < r1;
-      const int64_t mm = on ? m : r0;  // a row of this chunk
+      const bool on = m < M;
+      const int64_t mm = on ? m : 0;  // a row of X
       const int kv = idx[mm];
       k[u] = (on && (unsigned)kv < (unsigned)N) ? kv : N;  // N: the spare row
       if constexpr (VEC) {

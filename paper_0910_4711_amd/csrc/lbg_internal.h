@@ -136,10 +136,9 @@ struct AfpWs {
   int dslices;  // > 0: accumulation by this many 16-dimension slices (all cells per block)
   int64_t rows_per_chunk;
   // > 0: the 32-bit accumulation by this many 32-dimension slices is
-  // possible (when shift[3] says so), in nch_n chunks of rpc_n rows, its
-  // partials int32 [nch_n][N][L] in the bytes of ``part``
+  // possible (when shift[3] says so), in nch_n chunks (rows dealt in spans),
+  // its partials int32 [nch_n][N][L] in the bytes of ``part``
   int nds_n, nch_n;
-  int64_t rpc_n;
   // > 0: one of many instances whose update runs this many 16-dimension
   // slices with all cells in LDS (batched form)
   int bds;

@@ -121,8 +121,8 @@ __global__ __launch_bounds__(kDsThreads) void accd_kernel(
 template <bool VEC>
 __global__ __launch_bounds__(kDsThreads) void accn_kernel(
     const float* __restrict__ X, int64_t M, int L, const int32_t* __restrict__ idx, int N,
-    int nch, int nds, int64_t rows_per_chunk, const int* __restrict__ shift_p,
-    int32_t* __restrict__ part, int32_t* __restrict__ pcnt, Ctl ctl) {
+    int nch, int nds, const int* __restrict__ shift_p, int32_t* __restrict__ part,
+    int32_t* __restrict__ pcnt, Ctl ctl) {
   extern __shared__ uint32_t saccn[];
   const int ns = N;
   if (ctl.st) {
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kDsThreads) void accn_kernel(
   }
   int chunk, q;
   accd_block(blockIdx.x, nch, nds, &chunk, &q);
-  accn_body<VEC>(X, M, L, idx, N, ns, rows_per_chunk, chunk, q, shift_p[4], part, pcnt, saccn);
+  accn_body<VEC>(X, M, L, idx, N, ns, nch, chunk, q, shift_p[4], part, pcnt, saccn);
 }
 
 // One block per cell.
@@ -215,11 +215,9 @@ void plan_afp(Carver& c, int64_t M, int64_t L, int64_t N, AfpWs* w, bool dslices
   // chunks (the same blocks), their int32 partials in the same bytes
   w->nds_n = 0;
   w->nch_n = 0;
-  w->rpc_n = 0;
   if (w->dslices && L % kDn == 0 && accn_lds_bytes(N) <= (size_t)kAccdLdsMax) {
     w->nds_n = (int)(L / kDn);
     w->nch_n = (int)(nch * w->dslices / w->nds_n);
-    w->rpc_n = (M + w->nch_n - 1) / w->nch_n;
   }
   w->absmax_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (M * L + 4095) / 4096));
   w->part = c.take<unsigned long long>((size_t)(nch * N * L));
@@ -259,7 +257,7 @@ int launch_afp(const float* X, int64_t M, int64_t L, const int32_t* idx, const f
           hipFuncAttributeMaxDynamicSharedMemorySize, kAccdLdsMax);                              \
       LBG_TRY_HIP(a);                                                                           \
       hipLaunchKernelGGL((accn_kernel<VV>), grid, dim3(kDsThreads), lds, s, X, M, (int)L, idx,  \
-                         (int)N, w.nch_n, w.nds_n, w.rpc_n, w.shift, part32, w.pcnt, ctl);      \
+                         (int)N, w.nch_n, w.nds_n, w.shift, part32, w.pcnt, ctl);               \
     }
     if (vec) LBG_ACCN(true) else LBG_ACCN(false)
 #undef LBG_ACCN
