@@ -457,9 +457,13 @@ __global__ __launch_bounds__(kT) void b_accd_kernel(const BInst* __restrict__ in
   extern __shared__ unsigned long long sacc[];
   const int64_t* p = pre + (int64_t)kPreAccD * (n_inst + 1);
   if ((int64_t)blockIdx.x >= p[n_inst]) return;
-  const int i = tb.b2i[tb.off[kPreAccD] + blockIdx.x];
+  // the last instances first: the allocation before took the instances in
+  // order, so their rows are the ones the memory-side cache still holds
+  // (and the next allocation starts on the rows read last here)
+  const int64_t bx = p[n_inst] - 1 - (int64_t)blockIdx.x;
+  const int i = tb.b2i[tb.off[kPreAccD] + bx];
   const BInst& B = inst[i];
-  const int64_t local = (int64_t)blockIdx.x - p[i];
+  const int64_t local = bx - p[i];
   const Ctl ctl{B.st, B.pend, B.dpart, (B.M + 31) / 32, B.Dtrace, B.Atrace};
   int N = B.N;
   if (B.st->done) return;
