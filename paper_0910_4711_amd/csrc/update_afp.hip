@@ -109,11 +109,11 @@ __global__ __launch_bounds__(kDsThreads) void accd_kernel(
   accd_block(blockIdx.x, nch, nds, &chunk, &q);
   const int s = shift_p[0], tf = shift_p[1];
   if (GENERIC && tf > 0)
-    accd_body<true, VEC>(X, M, L, idx, N, ns, rows_per_chunk, chunk, q, s, part, pcnt, sacc, lo,
-                         tf);
+    accd_body<true, VEC, kDsThreads, true>(X, M, L, idx, N, ns, rows_per_chunk, chunk, q, s,
+                                           part, pcnt, sacc, lo, tf, nch);
   else
-    accd_body<false, VEC>(X, M, L, idx, N, ns, rows_per_chunk, chunk, q, s, part, pcnt, sacc,
-                          lo, 0);
+    accd_body<false, VEC, kDsThreads, true>(X, M, L, idx, N, ns, rows_per_chunk, chunk, q, s,
+                                            part, pcnt, sacc, lo, 0, nch);
 }
 
 // The 32-bit dimension slices (see accn_body): one 1024-thread block per
