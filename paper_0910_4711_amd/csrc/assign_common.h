@@ -1478,7 +1478,11 @@ __global__ __launch_bounds__(64 * W, W == 4 ? SC::OCC : 1) void assign_kernel(
 // Launch shape of the allocation for a codebook of n_pad rows: waves per
 // workgroup, workgroups, codebook rows per LDS chunk and LDS bytes.  A
 // codebook that does not fit the LDS of OCC workgroups per CU but fits one
-// workgroup's kWideLds bytes runs resident in eight-wave workgroups.
+// workgroup's kWideLds bytes runs resident in eight-wave workgroups.  A
+// split-screen codebook larger still is staged in chunks of nearly all of a
+// CU's LDS into eight-wave workgroups too: each staged chunk then serves 256
+// vectors instead of 128 (at M = 4,194,304, L = 64, N = 1024: 2,096 ->
+// 1,875 us per allocation).
 struct Shape {
   int waves;
   int64_t grid;
@@ -1496,6 +1500,11 @@ inline Shape shape_of(int64_t M, int n_pad) {
     sh.grid = std::min<int64_t>((M + 255) / 256, 256);
     sh.cr = n_pad;
     sh.lds = full;
+  } else if (CR < n_pad && SC::SPLIT) {
+    sh.waves = 8;
+    sh.grid = std::min<int64_t>((M + 255) / 256, 256);
+    sh.cr = (int)(((size_t)(kWideLds - 8192) / ((size_t)SC::S * SC::ESZ)) & ~(size_t)31);
+    sh.lds = (size_t)sh.cr * SC::S * SC::ESZ;
   } else {
     sh.waves = 4;
     sh.grid = std::min<int64_t>((M + kRowsPerTile - 1) / kRowsPerTile, persist_blocks<SC>());
