@@ -134,6 +134,29 @@ def test_batched_many_instances(P):
         _same(P, res[k], X, N, f"instance {k}")
 
 
+def test_batched_more_instances_than_one_list_workgroup(P):
+    # 1100 small instances: the round's finish list and next allocation queue
+    # are built 1024 instances at a time, and the instances stop at different
+    # rounds, so the queue of running instances shrinks unevenly across both
+    # batches
+    rng = np.random.default_rng(77)
+    inst = []
+    for k in range(1100):
+        M = int(rng.integers(1, 400))
+        L = int(rng.choice([3, 16, 64]))
+        N = int(rng.choice([1, 2, 4, 8, 16, 32]))
+        inst.append((synth.gmm(1000 + k, M, L, max(1, min(N, 8))), N))
+    Xs = [dev(X) for X, _ in inst]
+    res, st = P.train_batched(Xs, [N for _, N in inst], grab=2, grid=256)
+    assert st["rounds"] > 1
+    for k in list(range(0, 1100, 37)) + [1023, 1024, 1099]:
+        X, N = inst[k]
+        _same(P, res[k], X, N, f"instance {k}")
+    got, _ = P.train_batched(Xs, [N for _, N in inst], grab=1, grid=512)
+    for a, b in zip(res, got):
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and a[2] == b[2]
+
+
 def test_batched_rejects_bad_instances(P):
     X = dev(np.zeros((100, 16), np.float32))
     with pytest.raises(Exception):
