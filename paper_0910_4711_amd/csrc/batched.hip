@@ -245,10 +245,7 @@ __device__ __forceinline__ bool split_fits(int n) {
 }
 
 // Persistent: workgroups take chunks (instance, first slot, slot count) from
-// the queue until none is left.  The queue holds ``*qn`` chunks when qn is
-// set (training: the chunks of the instances still running, compacted by
-// the previous round's b_list_kernel), else ``nchunks``.  Two builds, each
-// with its own queue:
+// the queue until none is left.  Two builds, each with its own queue:
 //   SPLIT = false: codebooks of at most kDirectN codevectors (direct search)
 //     and, unless ``split``, every other codebook with the FP32 screen;
 //   SPLIT = true (launched only when ``split``): the instances with rows of
@@ -263,20 +260,17 @@ __device__ __forceinline__ bool split_fits(int n) {
 template <bool SPLIT>
 __global__ __launch_bounds__(kT, 2) void b_assign_kernel(const BInst* __restrict__ inst,
                                                          const int32_t* __restrict__ chunks,
-                                                         int nchunks,
-                                                         const int32_t* __restrict__ qn,
-                                                         unsigned* __restrict__ qctr,
+                                                         int nchunks, unsigned* __restrict__ qctr,
                                                          int split) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int s_c;
   int staged = -1;
-  const int nch = qn ? *qn : nchunks;
   for (;;) {
     __syncthreads();  // s_c of the previous access has been read
     if (threadIdx.x == 0) s_c = (int)atomicAdd(qctr, 1u);
     __syncthreads();
     const int c = s_c;
-    if (c >= nch) break;
+    if (c >= nchunks) break;
     const int i = chunks[3 * c], b0 = chunks[3 * c + 1], cnt = chunks[3 * c + 2];
     const BInst& B = inst[i];
     const DevState* st = B.st;
@@ -316,105 +310,47 @@ __global__ __launch_bounds__(kT, 2) void b_assign_kernel(const BInst* __restrict
 }
 
 // ----------------------------------------------------------------- update --
-// Inclusive sum over the 1024 threads of a workgroup (64-lane waves);
-// swave: 16 words of LDS.  Every thread of the workgroup must call it.
-__device__ __forceinline__ unsigned long long block_scan(unsigned long long v,
-                                                         unsigned long long* swave) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int off = 1; off < 64; off <<= 1) {
-    const unsigned long long u = __shfl_up(v, off, 64);
-    if (lane >= off) v += u;
-  }
-  if (lane == 63) swave[w] = v;
-  __syncthreads();
-  unsigned long long pre = 0;
-  for (int k = 0; k < w; ++k) pre += swave[k];
-  __syncthreads();  // swave is free again
-  return v + pre;
-}
-
 // The round's finish work list: the cells of every instance still running
 // (st[i].done clear) below the pending state's n_src, at least cell 0 (which
 // commits the state), compacted; b_fin walks it.  One workgroup of 1024
 // threads, run after the decisions (b_acc) are made.  st, pend: the
 // instances' states, contiguous.  list[item] = instance, first[i] = its first
 // item, *total = the number of items.
-// It also writes the next round's allocation queue: the chunks of the
-// instances that still run after this round's commit (st and pend both not
-// done), in instance order, as build_chunks lays them out (instance i's
-// chunk u covers slots u * grab .. min(G_i, (u + 1) * grab) - 1), into
-// ``qlist``, their number into *qn.  (Taking every chunk and skipping the
-// finished instances' had cost the allocation about 100 us a round once most
-// instances had finished: every skipped chunk is an atomic and three
-// dependent loads.  Halving the grab for the last rounds' few instances
-// gained less than the extra pass over the states cost.)
 __global__ __launch_bounds__(1024) void b_list_kernel(const DevState* __restrict__ st,
                                                      const DevState* __restrict__ pend,
                                                      const BInst* __restrict__ inst, int n_inst,
                                                      int32_t* __restrict__ list,
                                                      int32_t* __restrict__ first,
-                                                     int32_t* __restrict__ total, int grab,
-                                                     int32_t* __restrict__ qlist,
-                                                     int32_t* __restrict__ qn) {
-  // both scans at once: finish items in the low word, chunks in the high one
-  __shared__ unsigned long long ssum[1024];
-  __shared__ unsigned long long swave[16];
-  __shared__ int32_t sG[1024];
-  __shared__ int32_t sbase, qbase;
+                                                     int32_t* __restrict__ total) {
+  __shared__ int32_t ssum[1024];
+  __shared__ int32_t sbase;
   const int t = threadIdx.x;
-  const int g = grab;
-  if (t == 0) {
-    sbase = 0;
-    qbase = 0;
-  }
+  if (t == 0) sbase = 0;
   for (int i0 = 0; i0 < n_inst; i0 += 1024) {
     const int i = i0 + t;
-    int c = 0, a = 0;
+    int c = 0;
     if (i < n_inst) {
-      const int done = st[i].done, n_src = pend[i].n_src, N = inst[i].N, G = inst[i].G;
-      if (!done) {
-        c = max(1, min(N, n_src));
-        if (!pend[i].done) a = (G + g - 1) / g;
-      }
-      sG[t] = G;
+      const int done = st[i].done, n_src = pend[i].n_src, N = inst[i].N;
+      if (!done) c = max(1, min(N, n_src));
     }
-    const unsigned long long incl =
-        block_scan(((unsigned long long)(unsigned)a << 32) | (unsigned)c, swave);
-    ssum[t] = incl;
-    const int f = sbase + (int)(unsigned)incl - c;
+    ssum[t] = c;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
+      const int v = t >= off ? ssum[t - off] : 0;
+      __syncthreads();
+      ssum[t] += v;
+      __syncthreads();
+    }
+    const int f = sbase + ssum[t] - c;
     if (i < n_inst) {
       first[i] = f;
       for (int u = 0; u < c; ++u) list[f + u] = i;
     }
-    __syncthreads();  // ssum and sG complete
-    // this batch's chunks, spread over the threads: entry v belongs to the
-    // first instance whose inclusive chunk count exceeds v
-    const int Q = (int)(ssum[1023] >> 32), qb = qbase;
-    for (int v = t; v < Q; v += 1024) {
-      int lo = 0, hi = 1023;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((int)(ssum[mid] >> 32) > v)
-          hi = mid;
-        else
-          lo = mid + 1;
-      }
-      const int b0 = (v - (lo ? (int)(ssum[lo - 1] >> 32) : 0)) * g;
-      qlist[3 * (qb + v)] = i0 + lo;
-      qlist[3 * (qb + v) + 1] = b0;
-      qlist[3 * (qb + v) + 2] = min(g, sG[lo] - b0);
-    }
-    __syncthreads();  // every thread has read sbase, qbase, ssum and sG
-    if (t == 1023) {
-      sbase = f + c;
-      qbase = qb + Q;
-    }
+    __syncthreads();  // every thread has read sbase
+    if (t == 1023) sbase = f + c;
     __syncthreads();
   }
-  if (t == 0) {
-    *total = sbase;
-    *qn = qbase;
-  }
+  if (t == 0) *total = sbase;
 }
 
 // The fixed-point cell sums of instance B's row chunk x cell slice
@@ -783,8 +719,6 @@ struct BatchWs {
   int32_t* b2i;             // block -> instance tables
   int64_t b2i_n;
   int32_t* chunks;          // allocation chunks (instance, first slot, slots)
-  int32_t* qlist;           // a round's allocation queue (b_list_kernel)
-  int32_t* qn;              // its chunk count
   int32_t* fin_list;        // the round's finish work list (b_list_kernel)
   int32_t* fin_first;       // n
   int32_t* list_total;      // its item count
@@ -855,16 +789,13 @@ void plan_batch(Carver& c, const lbg_instance* in, int n, BatchWs* w) {
     if (k != kPreItem) w->b2i_n += w->tot[k];
   w->b2i = c.take<int32_t>((size_t)w->b2i_n);
   w->chunks = c.take<int32_t>((size_t)(3 * w->tot[kPreItem]));
-  w->qlist = c.take<int32_t>((size_t)(3 * w->tot[kPreItem]));
-  w->qn = c.take<int32_t>(1);
   w->fin_list = c.take<int32_t>((size_t)w->tot[kPreFin]);
   w->fin_first = c.take<int32_t>((size_t)n);
   w->list_total = c.take<int32_t>(1);
 }
 
 // Allocation chunks of at most ``grab`` slots, never spanning two instances,
-// in instance order.  Returns their number.  (b_list_kernel forms the same
-// entries for the instances still running.)
+// in instance order.  Returns their number.
 int build_chunks(const std::vector<InstPlan>& plans, int grab, int32_t* out) {
   int nc = 0;
   for (size_t i = 0; i < plans.size(); ++i)
@@ -901,9 +832,7 @@ struct Launch {
   unsigned* ctr;
   size_t acc_lds, accd_lds;
   const int32_t* chunks;    // device chunk table for the current grab
-  int nchunks, grab;
-  int32_t* qlist;           // the round's allocation queue and its count
-  int32_t* qn;
+  int nchunks;
   const DevState* st;       // the instances' states (contiguous)
   const DevState* pend;
   int32_t* fin_list;        // finish work list (b_list_kernel)
@@ -921,11 +850,11 @@ int launch_round(const Launch& l, int grid, int split, hipStream_t s,
                  hipEvent_t* ev = nullptr) {
   if (ev) LBG_TRY_HIP(hipEventRecord(ev[0], s));
   hipLaunchKernelGGL(b_assign_kernel<false>, dim3((unsigned)grid), dim3(kT), kBatchLds, s, l.inst,
-                     l.qlist, l.nchunks, l.qn, l.ctr, split);
+                     l.chunks, l.nchunks, l.ctr, split);
   LBG_TRY_HIP(hipGetLastError());
   if (split) {
     hipLaunchKernelGGL(b_assign_kernel<true>, dim3((unsigned)grid), dim3(kT), kBatchLds, s,
-                       l.inst, l.qlist, l.nchunks, l.qn, l.ctr + 2, split);
+                       l.inst, l.chunks, l.nchunks, l.ctr + 2, split);
     LBG_TRY_HIP(hipGetLastError());
   }
   if (ev) LBG_TRY_HIP(hipEventRecord(ev[1], s));
@@ -940,7 +869,7 @@ int launch_round(const Launch& l, int grid, int split, hipStream_t s,
     LBG_TRY_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(b_list_kernel, dim3(1), dim3(1024), 0, s, l.st, l.pend, l.inst, l.n,
-                     l.fin_list, l.fin_first, l.list_total, l.grab, l.qlist, l.qn);
+                     l.fin_list, l.fin_first, l.list_total);
   LBG_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(b_fin_kernel, dim3((unsigned)std::min(l.blocks[kPreFin], kFinGrid)), dim3(kT),
                      0, s, l.inst, l.fin_list, l.fin_first, l.list_total, l.ctr, l.ctr + 1);
@@ -1014,12 +943,12 @@ int autotune(Launch l, const std::vector<InstPlan>& plans, int32_t* chunk_host,
         if (e == hipSuccess) e = hipEventRecord(e0, s);
         if (e == hipSuccess) {
           hipLaunchKernelGGL(b_assign_kernel<false>, dim3((unsigned)gr), dim3(kT), kBatchLds, s,
-                             l.inst, l.chunks, l.nchunks, nullptr, l.ctr, sp);
+                             l.inst, l.chunks, l.nchunks, l.ctr, sp);
           e = hipGetLastError();
         }
         if (e == hipSuccess && sp) {
           hipLaunchKernelGGL(b_assign_kernel<true>, dim3((unsigned)gr), dim3(kT), kBatchLds, s,
-                             l.inst, l.chunks, l.nchunks, nullptr, l.ctr + 2, sp);
+                             l.inst, l.chunks, l.nchunks, l.ctr + 2, sp);
           e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipEventRecord(e1, s);
@@ -1365,8 +1294,8 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
     }
   }
   int32_t* hchunk = reinterpret_cast<int32_t*>(host + b_inst + b_pre + b_st + 64 + b_tab);
-  Launch l{w.inst, n, w.pre, tb, {}, w.ctr, acc_lds, accd_lds, w.chunks, 0, 0, w.qlist,
-           w.qn, w.st, w.pend, w.fin_list, w.fin_first, w.list_total};
+  Launch l{w.inst, n, w.pre, tb, {}, w.ctr, acc_lds, accd_lds, w.chunks, 0,
+           w.st, w.pend, w.fin_list, w.fin_first, w.list_total};
   for (int k = 0; k < kNumPre; ++k) l.blocks[k] = tot[k];
 
   static const hipError_t lds_ok = hipFuncSetAttribute(
@@ -1406,17 +1335,9 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
   }
 
   // the allocation chunks for the chosen grab
-  // (the first round's queue is the whole table; b_list_kernel writes the
-  // later ones)
   l.nchunks = build_chunks(w.plans, grab, hchunk);
-  l.grab = grab;
-  int32_t* hqn = reinterpret_cast<int32_t*>(host + b_inst + b_pre + b_st + 16);
-  *hqn = l.nchunks;
   LBG_TRY_HIP(hipMemcpyAsync(w.chunks, hchunk, sizeof(int32_t) * 3 * l.nchunks,
                              hipMemcpyHostToDevice, s));
-  LBG_TRY_HIP(hipMemcpyAsync(w.qlist, hchunk, sizeof(int32_t) * 3 * l.nchunks,
-                             hipMemcpyHostToDevice, s));
-  LBG_TRY_HIP(hipMemcpyAsync(w.qn, hqn, sizeof(int32_t), hipMemcpyHostToDevice, s));
 
   // set-up: states, counters, centroids and first split, fixed-point shifts
   LBG_TRY_HIP(hipMemcpyAsync(w.st, hs, b_st, hipMemcpyHostToDevice, s));
@@ -1742,7 +1663,7 @@ extern "C" int lbg_assign_batched(const lbg_assign_item* items, int32_t n, void*
   // screen's build measured slower here too (5.3 vs 5.0 ms for the 512
   // instances of the batched workload with codebooks of their final sizes)
   hipLaunchKernelGGL(b_assign_kernel<false>, dim3(kGrid), dim3(kT), kBatchLds, s, w.inst,
-                     w.chunks, nchunks, nullptr, w.ctr, 0);
+                     w.chunks, nchunks, w.ctr, 0);
   LBG_TRY_HIP(hipGetLastError());
   bool anyD = false;
   for (int i = 0; i < n; ++i) anyD = anyD || items[i].D != nullptr;

@@ -135,10 +135,9 @@ def test_batched_many_instances(P):
 
 
 def test_batched_more_instances_than_one_list_workgroup(P):
-    # 1100 small instances: the round's finish list and next allocation queue
-    # are built 1024 instances at a time, and the instances stop at different
-    # rounds, so the queue of running instances shrinks unevenly across both
-    # batches
+    # 1100 small instances: the round's finish list is built 1024 instances at
+    # a time, and the instances stop at different rounds, so the running set
+    # shrinks unevenly across both passes
     rng = np.random.default_rng(77)
     inst = []
     for k in range(1100):
