@@ -489,24 +489,99 @@ __global__ __launch_bounds__(kT) void b_accd_kernel(const BInst* __restrict__ in
 #undef LBG_BACCD
 }
 
-// Cell k of instance B: centroid, or split, or nothing; cell 0 commits the
-// state.  (The work list holds only cells below the pending n_src of
-// instances still running.)
-__device__ __forceinline__ void fin_item(const BInst& B, int k, unsigned* __restrict__ ndone) {
-  const Ctl ctl{B.st, B.pend, B.dpart, (B.M + 31) / 32, B.Dtrace, B.Atrace};
-  const CbPair cbp{{B.Cb[0], B.Cb[1]}};
-  int N = B.N;
-  afp::fin_body<0>(
-      B.part, B.pcnt, B.nchunks, B.N, B.L, B.shift[0], nullptr, 0.0, k,
-      [&](const float** c_old, float** dst) {
-        return afp::fin_state(ctl, cbp, k, k == 0, B.L, &N, c_old, dst, ndone);
-      },
-      B.lo, B.shift[1]);
+// Cell k of instance B by one 64-lane wave: centroid, or split, or nothing;
+// cell 0 commits the state.  The same work and results, bit for bit, as
+// afp::fin_state with afp::fin_body<0> (one 256-thread workgroup per cell,
+// the single run's finish): the pending state's action, the state words
+// copied by the commit, the residual sums read and cleared whatever the
+// decision, integer sums of the chunk partials (their order immaterial) and
+// the same rounding.  A round's cells are many and small here (at most 64
+// dimensions, a few chunks each), so each workgroup keeps four cells in
+// flight; one cell per workgroup left the finish bound by the round trips
+// of 2,048 cells at a time.  (The work list holds only cells below the
+// pending n_src of instances still running.)
+__device__ __forceinline__ void fin_item_wave(const BInst& B, int k, unsigned* __restrict__ ndone) {
+  constexpr int NW = (int)(sizeof(DevState) / 4);
+  constexpr int NWL = (NW + 63) / 64;  // state words per lane
+  constexpr int U = 16;                // partial words in flight per lane
+  static_assert(sizeof(DevState) % 4 == 0, "state words");
+  const int lane = threadIdx.x & 63;
+  const int L = B.L, ns = B.N, nch = B.nchunks;
+  const int s = B.shift[0], tf = B.shift[1];
+  const bool fine = B.lo != nullptr && tf > 0;
+  const bool lead = k == 0;
+  const DevState* pd = B.pend;
+  const bool on = lane < L;  // lane d takes dimension d (L <= 64)
+  // loads issued together: the commit's words, the residual, the first
+  // partials and the counts, then the state
+  uint32_t word[NWL];
+#pragma unroll
+  for (int j = 0; j < NWL; ++j) {
+    const int w = lane + 64 * j;
+    word[j] = (lead && w < NW) ? reinterpret_cast<const uint32_t*>(pd)[w] : 0u;
+  }
+  long long slo = 0;
+  if (fine && on) {
+    unsigned long long* p = B.lo + (int64_t)k * L + lane;
+    slo = (long long)*p;
+    *p = 0ull;
+  }
+  unsigned long long a[U];
+  auto load_u = [&](int ch0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ch = ch0 + u;
+      a[u] = (on && ch < nch) ? B.part[((int64_t)ch * ns + k) * L + lane] : 0ull;
+    }
+  };
+  load_u(0);
+  long long c = 0;
+  for (int ch = lane; ch < nch; ch += 64) c += B.pcnt[(int64_t)ch * ns + k];
+  const int done = B.st->done;
+  const int action = pd->action, n_src = pd->n_src, src = pd->src, dst = pd->dst;
+  if (done) return;
+  if (lead) {
+#pragma unroll
+    for (int j = 0; j < NWL; ++j) {
+      const int w = lane + 64 * j;
+      if (w < NW) reinterpret_cast<uint32_t*>(B.st)[w] = word[j];
+    }
+    if (ndone && lane == 0 && pd->done) atomicAdd(ndone, 1u);
+  }
+  if (action == kActSplit) {
+    // Codebook Splitting of codevector k: children 2k ("+") and 2k+1 ("-")
+    if (k >= n_src || !on) return;
+    misc::split_pair(B.Cb[src][k * L + lane], pd->split_mode, pd->eps, pd->delta,
+                     &B.Cb[dst][(2 * k) * L + lane], &B.Cb[dst][(2 * k + 1) * L + lane]);
+    return;
+  }
+  if (action != kActUpdate || k >= n_src) return;
+  const float* C_old = B.Cb[src];
+  float* out = B.Cb[dst];
+  unsigned long long acc = 0ull;
+  for (int ch0 = U;; ch0 += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += a[u];
+    if (ch0 >= nch) break;
+    load_u(ch0);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+  if (!on) return;
+  const int64_t e = (int64_t)k * L + lane;
+  if (c == 0) {
+    if (out != C_old) out[e] = C_old[e];
+  } else {
+    const long long S = (long long)acc;
+    const double low = fine ? ldexp((double)slo, -(s + tf)) : 0.0;
+    out[e] = (float)((ldexp((double)S, -s) + low) / (double)c);
+  }
 }
 
-// Persistent over the round's finish list (b_list_kernel).  Block 0
-// also rearms the allocation queues (qctr[0] and qctr[2]) for the next round
-// (the round's allocation has completed before this launch starts).
+// Persistent over the round's finish list (b_list_kernel), a cell per
+// wave.  Block 0 also rearms the allocation queues (qctr[0] and qctr[2])
+// for the next round (the round's allocation has completed before this
+// launch starts).
 __global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ inst,
                                                    const int32_t* __restrict__ list,
                                                    const int32_t* __restrict__ first,
@@ -517,11 +592,12 @@ __global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ ins
     qctr[0] = 0u;
     qctr[2] = 0u;
   }
+  constexpr int W = kT / 64;
   const int T = *total;
-  for (int item = blockIdx.x; item < T; item += gridDim.x) {
-    __syncthreads();  // the previous item is done with the LDS
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int item = blockIdx.x * W + wave; item < T; item += gridDim.x * W) {
     const int i = list[item];
-    fin_item(inst[i], item - first[i], ndone);
+    fin_item_wave(inst[i], item - first[i], ndone);
   }
 }
 
