@@ -29,6 +29,64 @@ __device__ __forceinline__ uint32_t fine_bits(uint32_t b) {
   return (uint32_t)(256 - q);
 }
 
+// The set-up pass of a training run, block blk of nblk (256 threads): the
+// column sums of misc::colsum_body (the same blocks of rows_per_block rows,
+// the same order) into part[blk L ...] and, from the same loads, the block's
+// largest finite |x|, largest fine bits and the OR of the low 16 bits into
+// amax[blk], amax[nblk + blk] and amax[2 nblk + blk] (as absmax_body forms
+// them; none depends on the blocks); the blocks also clear lo (nlo words).
+__device__ __forceinline__ void setup_pass_body(const float* __restrict__ X, int64_t M, int L,
+                                                int64_t rows_per_block,
+                                                double* __restrict__ part,
+                                                uint32_t* __restrict__ amax, int64_t nblk,
+                                                int64_t blk, unsigned long long* __restrict__ lo,
+                                                int64_t nlo) {
+  __shared__ double s[kT];
+  __shared__ uint32_t sm[kT];
+  __shared__ uint32_t sf[kT];
+  __shared__ uint32_t sr[kT];
+  const int R = kT / L;
+  const int t = threadIdx.x;
+  const int q = t / L, d = t % L;
+  for (int64_t e = blk * kT + t; e < nlo; e += nblk * kT) lo[e] = 0ull;
+  const int64_t r0 = blk * rows_per_block;
+  const int64_t r1 = min(M, r0 + rows_per_block);
+  double acc = 0.0;
+  uint32_t m = 0, f = 0, rb = 0;
+  if (q < R)
+    for (int64_t r = r0 + q; r < r1; r += R) {
+      const float v = X[r * L + d];
+      acc += (double)v;
+      const uint32_t b = __float_as_uint(v) & 0x7fffffffu;
+      m = (b > m && b < 0x7f800000u) ? b : m;  // ignore Inf / NaN
+      f = max(f, fine_bits(b));
+      rb |= __float_as_uint(v) & 0xffffu;
+    }
+  s[t] = acc;
+  sm[t] = m;
+  sf[t] = f;
+  sr[t] = rb;
+  __syncthreads();
+  if (t < L) {
+    double v = 0.0;
+    for (int qi = 0; qi < R; ++qi) v += s[qi * L + t];
+    part[blk * L + t] = v;
+  }
+  for (int off = kT / 2; off > 0; off >>= 1) {
+    if (t < off) {
+      sm[t] = max(sm[t], sm[t + off]);
+      sf[t] = max(sf[t], sf[t + off]);
+      sr[t] |= sr[t + off];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    amax[blk] = sm[0];
+    amax[nblk + blk] = sf[0];
+    amax[2 * nblk + blk] = sr[0];
+  }
+}
+
 // Block maxima over X (n floats): part[block] = largest finite |x| (as
 // float bits), part[nblocks + block] = largest fine bits, part[2 nblocks +
 // block] = the OR of the coordinates' low 16 bits (zero: all exact in BF16).

@@ -602,13 +602,19 @@ __global__ __launch_bounds__(kT) void b_fin_kernel(const BInst* __restrict__ ins
 }
 
 // ------------------------------------------------------------- set-up, end --
-__global__ __launch_bounds__(kT) void b_colsum_kernel(const BInst* __restrict__ inst, int n_inst,
-                                                      const int64_t* __restrict__ pre, Tabs tb) {
+// The set-up pass of every instance (the single run's setup_pass_kernel,
+// the same blocks): its column-sum partials and, from the same loads, the
+// block maxima that fix its fixed-point shift (b_shift_kernel), the update's
+// second-word sums cleared.  One read of X; a column-sum pass and a
+// separate maxima pass over X took 775 + 522 us on the 512-instance set.
+__global__ __launch_bounds__(kT) void b_setup_kernel(const BInst* __restrict__ inst, int n_inst,
+                                                     const int64_t* __restrict__ pre, Tabs tb) {
   const int64_t* p = pre + (int64_t)kPreCol * (n_inst + 1);
   if ((int64_t)blockIdx.x >= p[n_inst]) return;
   const int i = tb.b2i[tb.off[kPreCol] + blockIdx.x];
   const BInst& B = inst[i];
-  misc::colsum_body(B.X, B.M, B.L, B.crpb, B.cpart, (int64_t)blockIdx.x - p[i]);
+  afp::setup_pass_body(B.X, B.M, B.L, B.crpb, B.cpart, B.amax, B.cnwg,
+                       (int64_t)blockIdx.x - p[i], B.lo, (int64_t)B.N * B.L);
 }
 
 // Column d of instance i's centroid into Cb[0]; with N > 1 also its split
@@ -639,9 +645,11 @@ __global__ __launch_bounds__(kT) void b_absmax_kernel(const BInst* __restrict__ 
                    (int64_t)B.N * B.L);
 }
 
-__global__ __launch_bounds__(kT) void b_shift_kernel(const BInst* __restrict__ inst) {
+// setup: the maxima come from b_setup_kernel (cnwg blocks), else from
+// b_absmax_kernel (absmax_blocks blocks).
+__global__ __launch_bounds__(kT) void b_shift_kernel(const BInst* __restrict__ inst, int setup) {
   const BInst& B = inst[blockIdx.x];
-  afp::shift_body(B.amax, B.absmax_blocks, B.M, B.shift);
+  afp::shift_body(B.amax, setup ? B.cnwg : B.absmax_blocks, B.M, B.shift);
 }
 
 // Row k of every instance's current codebook into its C_out.
@@ -853,6 +861,8 @@ void plan_batch(Carver& c, const lbg_instance* in, int n, BatchWs* w) {
     q.Dtrace = c.take<double>(kBatchTrace);
     q.Atrace = c.take<int32_t>(kBatchTrace);
     plan_afp(c, M, L, N, &q.afp, false, true, true);
+    // the set-up pass writes the maxima of its cnwg blocks there
+    if (q.cnwg > q.afp.absmax_blocks) q.afp.amax = c.take<uint32_t>((size_t)(3 * q.cnwg));
   }
   for (int k = 0; k < kNumPre; ++k) w->tot[k] = 0;
   for (int i = 0; i < n; ++i) {
@@ -1420,16 +1430,13 @@ extern "C" int lbg_train_batched(const lbg_instance* inst, int32_t n_inst, const
   LBG_TRY_HIP(hipMemcpyAsync(w.pend, hs, b_st, hipMemcpyHostToDevice, s));
   LBG_TRY_HIP(hipMemsetAsync(w.ctr, 0, 3 * sizeof(unsigned), s));
   LBG_TRY_HIP(hipMemsetAsync(w.nfb, 0, sizeof(unsigned long long) * (size_t)n, s));
-  hipLaunchKernelGGL(b_colsum_kernel, dim3((unsigned)tot[kPreCol]), dim3(kT), 0, s, w.inst, n,
+  hipLaunchKernelGGL(b_setup_kernel, dim3((unsigned)tot[kPreCol]), dim3(kT), 0, s, w.inst, n,
                      w.pre, tb);
   LBG_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(b_centroid_kernel, dim3((unsigned)tot[kPreColFin]), dim3(kT), 0, s, w.inst,
                      n, w.pre, tb, p->split_mode, p->eps_split, p->delta);
   LBG_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(b_absmax_kernel, dim3((unsigned)tot[kPreAmax]), dim3(kT), 0, s, w.inst, n,
-                     w.pre, tb);
-  LBG_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(b_shift_kernel, dim3((unsigned)n), dim3(kT), 0, s, w.inst);
+  hipLaunchKernelGGL(b_shift_kernel, dim3((unsigned)n), dim3(kT), 0, s, w.inst, 1);
   LBG_TRY_HIP(hipGetLastError());
 
   // rounds until every instance has finished
@@ -1833,7 +1840,7 @@ extern "C" int lbg_update_batched(const lbg_update_item* items, int32_t n, void*
   hipLaunchKernelGGL(b_absmax_kernel, dim3((unsigned)w.tot[kPreAmax]), dim3(kT), 0, s, w.inst, n,
                      w.pre, tb);
   LBG_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(b_shift_kernel, dim3((unsigned)n), dim3(kT), 0, s, w.inst);
+  hipLaunchKernelGGL(b_shift_kernel, dim3((unsigned)n), dim3(kT), 0, s, w.inst, 0);
   LBG_TRY_HIP(hipGetLastError());
   if (w.tot[kPreAccD] > 0) {
     hipLaunchKernelGGL(b_upd_accd_kernel, dim3((unsigned)w.tot[kPreAccD]), dim3(kT), accd_lds, s,

@@ -312,51 +312,7 @@ __global__ __launch_bounds__(kThreads) void setup_pass_kernel(const float* __res
                                                               uint32_t* __restrict__ amax,
                                                               unsigned long long* __restrict__ lo,
                                                               int64_t nlo) {
-  __shared__ double s[kThreads];
-  __shared__ uint32_t sm[kThreads];
-  __shared__ uint32_t sf[kThreads];
-  __shared__ uint32_t sr[kThreads];
-  const int R = kThreads / L;
-  const int t = threadIdx.x;
-  const int q = t / L, d = t % L;
-  const int64_t blk = blockIdx.x;
-  for (int64_t e = blk * kThreads + t; e < nlo; e += (int64_t)gridDim.x * kThreads) lo[e] = 0ull;
-  const int64_t r0 = blk * rows_per_block;
-  const int64_t r1 = min(M, r0 + rows_per_block);
-  double acc = 0.0;
-  uint32_t m = 0, f = 0, rb = 0;
-  if (q < R)
-    for (int64_t r = r0 + q; r < r1; r += R) {
-      const float v = X[r * L + d];
-      acc += (double)v;
-      const uint32_t b = __float_as_uint(v) & 0x7fffffffu;
-      m = (b > m && b < 0x7f800000u) ? b : m;  // ignore Inf / NaN
-      f = max(f, afp::fine_bits(b));
-      rb |= __float_as_uint(v) & 0xffffu;
-    }
-  s[t] = acc;
-  sm[t] = m;
-  sf[t] = f;
-  sr[t] = rb;
-  __syncthreads();
-  if (t < L) {
-    double v = 0.0;
-    for (int qi = 0; qi < R; ++qi) v += s[qi * L + t];
-    part[blk * L + t] = v;
-  }
-  for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if (t < off) {
-      sm[t] = max(sm[t], sm[t + off]);
-      sf[t] = max(sf[t], sf[t + off]);
-      sr[t] |= sr[t + off];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    amax[blk] = sm[0];
-    amax[gridDim.x + blk] = sf[0];
-    amax[2 * gridDim.x + blk] = sr[0];
-  }
+  afp::setup_pass_body(X, M, L, rows_per_block, part, amax, gridDim.x, blockIdx.x, lo, nlo);
 }
 
 // setup_final_kernel, one block per dimension d: c0[d] as colsum_final_kernel
