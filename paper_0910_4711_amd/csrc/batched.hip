@@ -762,23 +762,57 @@ __global__ __launch_bounds__(kT) void b_upd_accd_kernel(const BInst* __restrict_
 #undef LBG_BUACCD
 }
 
-// ... then every item's centroids (one workgroup per cell; an empty cell
-// keeps C_old, Cb[0]) into C_out, with the counts.
+// ... then every item's centroids (one cell per 64-lane wave; an empty cell
+// keeps C_old, Cb[0]) into C_out, with the counts: fin_body<0>'s results
+// bit for bit (integer sums of the chunk partials, the same rounding), as
+// fin_item_wave forms them in the training rounds.
 __global__ __launch_bounds__(kT) void b_upd_fin_kernel(const BInst* __restrict__ inst, int n_inst,
                                                        const int64_t* __restrict__ pre, Tabs tb) {
+  constexpr int U = 16;  // partial words in flight per lane
   const int64_t* fin_pre = pre + (int64_t)kPreFin * (n_inst + 1);
-  if ((int64_t)blockIdx.x >= fin_pre[n_inst]) return;
-  const int i = tb.b2i[tb.off[kPreFin] + blockIdx.x];
+  const int64_t g = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+  if (g >= fin_pre[n_inst]) return;
+  const int i = tb.b2i[tb.off[kPreFin] + g];
   const BInst& B = inst[i];
-  const int k = (int)((int64_t)blockIdx.x - fin_pre[i]);
-  afp::fin_body<0>(
-      B.part, B.pcnt, B.nchunks, B.N, B.L, B.shift[0], B.counts, 0.0, k,
-      [&](const float** c_old, float** dst) {
-        *c_old = B.Cb[0];
-        *dst = B.C_out;
-        return true;
-      },
-      B.lo, B.shift[1]);
+  const int k = (int)(g - fin_pre[i]);
+  const int lane = threadIdx.x & 63;
+  const int L = B.L, ns = B.N, nch = B.nchunks;
+  const int s = B.shift[0], tf = B.shift[1];
+  const bool fine = B.lo != nullptr && tf > 0;
+  const bool on = lane < L;  // lane d takes dimension d (L <= 64)
+  long long slo = 0;
+  if (fine && on) {
+    unsigned long long* p = B.lo + (int64_t)k * L + lane;
+    slo = (long long)*p;
+    *p = 0ull;
+  }
+  unsigned long long acc = 0ull;
+  for (int ch0 = 0; ch0 < nch; ch0 += U) {
+    unsigned long long a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ch = ch0 + u;
+      a[u] = (on && ch < nch) ? B.part[((int64_t)ch * ns + k) * L + lane] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += a[u];
+  }
+  long long c = 0;
+  for (int ch = lane; ch < nch; ch += 64) c += B.pcnt[(int64_t)ch * ns + k];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+  if (B.counts && lane == 0) B.counts[k] = (int32_t)c;
+  if (!on) return;
+  const float* C_old = B.Cb[0];
+  float* out = B.C_out;
+  const int64_t e = (int64_t)k * L + lane;
+  if (c == 0) {
+    if (out != C_old) out[e] = C_old[e];
+  } else {
+    const long long S = (long long)acc;
+    const double low = fine ? ldexp((double)slo, -(s + tf)) : 0.0;
+    out[e] = (float)((ldexp((double)S, -s) + low) / (double)c);
+  }
 }
 
 // ---------------------------------------------------------------- planning --
@@ -1852,8 +1886,8 @@ extern "C" int lbg_update_batched(const lbg_update_item* items, int32_t n, void*
                        w.inst, n, w.pre, tb);
     LBG_TRY_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(b_upd_fin_kernel, dim3((unsigned)w.tot[kPreFin]), dim3(kT), 0, s, w.inst,
-                     n, w.pre, tb);
+  hipLaunchKernelGGL(b_upd_fin_kernel, dim3((unsigned)((w.tot[kPreFin] + kT / 64 - 1) / (kT / 64))),
+                     dim3(kT), 0, s, w.inst, n, w.pre, tb);
   LBG_TRY_HIP(hipGetLastError());
   // the host images are released on return
   LBG_TRY_HIP(hipStreamSynchronize(s));
