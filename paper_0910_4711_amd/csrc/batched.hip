@@ -342,11 +342,23 @@ __global__ __launch_bounds__(1024) void b_list_kernel(const DevState* __restrict
       __syncthreads();
     }
     const int f = sbase + ssum[t] - c;
-    if (i < n_inst) {
-      first[i] = f;
-      for (int u = 0; u < c; ++u) list[f + u] = i;
+    if (i < n_inst) first[i] = f;
+    // the batch's items spread over the threads: item v belongs to the
+    // first instance whose inclusive count exceeds v (one instance's cells
+    // written by one thread had left the list bound by its longest run)
+    const int base = sbase, Q = ssum[1023];
+    for (int v = t; v < Q; v += 1024) {
+      int lo = 0, hi = 1023;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ssum[mid] > v)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      list[base + v] = i0 + lo;
     }
-    __syncthreads();  // every thread has read sbase
+    __syncthreads();  // every thread has read sbase and ssum
     if (t == 1023) sbase = f + c;
     __syncthreads();
   }
